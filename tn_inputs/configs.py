@@ -1,0 +1,55 @@
+"""The benchmark and test workloads, with their seeds (synthetic stand-ins).
+
+The paper's workloads are Sycamore circuits with experimental bitstrings,
+which are not available; seeded lattice circuits of the same gate family stand
+in for them.  Each workload fixes the lattice, depth, number of open qubits
+(correlated amplitudes of the last k qubits), the closed-bit seed, the memory
+cap (log2 elements of the largest intermediate) and the number of sliced bonds.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from functools import lru_cache
+
+from .circuits import open_and_closed, random_circuit
+from .network import circuit_network
+from .paths import find_path
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    rows: int
+    cols: int
+    cycles: int
+    k_open: int
+    circuit_seed: int
+    closed_seed: int
+    cap_log2: int
+    n_sliced: int = 0
+    removed: tuple = ()
+    trials: int = 8
+    description: str = ""
+
+
+WORKLOADS = {
+    "rqc12": Workload("rqc12", 3, 4, 8, 4, 101, 201, 60, 0,
+                      description="12-qubit 3x4 lattice, 8 cycles, 4 open qubits, unsliced"),
+    "rqc30": Workload("rqc30", 5, 6, 14, 6, 102, 202, 28, 8,
+                      description="30-qubit 5x6 lattice, 14 cycles, 6 open qubits, "
+                                  "8 sliced bonds (256 slices), cap 2^28"),
+    "rqc30d12": Workload("rqc30d12", 5, 6, 12, 9, 130, 230, 28, 0,
+                         description="30-qubit 5x6 lattice, 12 cycles, 9 open qubits, cap 2^28"),
+}
+
+
+@lru_cache(maxsize=None)
+def build(name: str):
+    """(circuit, network, path dict) of a named workload; deterministic."""
+    w = WORKLOADS[name]
+    circ = random_circuit(w.rows, w.cols, w.cycles, w.circuit_seed, removed=w.removed)
+    open_q, closed = open_and_closed(circ.n_qubits, w.k_open, w.closed_seed)
+    net = circuit_network(circ, open_q, closed)
+    best = find_path(net, cap_log2=w.cap_log2, n_sliced=w.n_sliced, trials=w.trials,
+                     seed=w.circuit_seed)
+    return circ, net, best
