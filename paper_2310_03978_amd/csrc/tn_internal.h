@@ -1,0 +1,76 @@
+// Internal structures shared by the host planner and the gfx950 kernels.
+//
+// Every extent is a power of two, so every tensor index is a bit string and
+// every layout is a permutation of bits: the storage offset of an element is
+// the sum, over its set index bits, of that bit's stride (a power of two, or
+// 0 when an operand does not carry the bit).  A pairwise step (the einsum of
+// Sec. 2.4) becomes a batched complex GEMM over four bit groups:
+//   batch bits  -- carried by A, B and C (labels still needed elsewhere), plus
+//                  the slice-local bits of a chunk of slices (Sec. 3.2),
+//   m bits      -- A and C only,   n bits -- B and C only,
+//   k bits      -- summed: A and B, or only one of them (stride 0 in the other).
+// The planner lays every intermediate out the way its consumer reads it
+// (consumer-driven index order, Sec. 4.1), so an operand of a step is stored
+// [batch][free][k] with its k bits innermost.
+#pragma once
+
+#include <stdint.h>
+
+#define TN_MAXB 24   // batch bits incl. slice-local bits
+#define TN_MAXR 40   // m or n bits
+#define TN_MAXK 40   // k bits
+#define TN_MAXE 16   // local bits of one operand tile
+
+// Small tile enumeration: the local bits of one operand tile, sorted by storage
+// stride so that consecutive threads touch consecutive addresses.
+struct TileEnum {
+  int32_t n;                    // number of local bits
+  int32_t pad_;
+  int64_t stride[TN_MAXE];      // storage stride of the j-th local bit
+  int32_t row[TN_MAXE];         // increment of the tile row index (m or n) for that bit
+  int32_t col[TN_MAXE];         // increment of the tile column index (k, or n for C)
+};
+
+struct GettDesc {
+  int32_t nbb;                  // batch bits present in the descriptor (own + max slice-local)
+  int32_t own_bb;               // own batch bits (slice-local bits follow them)
+  int32_t mb, nb, kb;           // m, n, k bit counts
+  int32_t c_nbits;              // storage bits of C without slice-local bits
+  int64_t c_elems;              // elements of one slice of C
+  int64_t a_b[TN_MAXB], a_m[TN_MAXR], a_k[TN_MAXK];
+  int64_t b_b[TN_MAXB], b_k[TN_MAXK], b_n[TN_MAXR];
+  int64_t c_b[TN_MAXB], c_m[TN_MAXR], c_n[TN_MAXR];
+  // role of each storage position of C, LSB first (own layout then slice-local bits):
+  // (role << 8) | index, role 0 = batch, 1 = m, 2 = n
+  int32_t c_pos[TN_MAXR + TN_MAXB];
+  // tile enumerations for the MFMA kernels (filled for the step's tile shape)
+  TileEnum ea, eb, ec;
+};
+
+// Per-launch arguments (by value).
+struct GettArgs {
+  const float* A;               // complex64 interleaved
+  const float* B;
+  float* C;
+  float* scratch;               // split-K partials [split][batch][m][n] (complex64)
+  const uint32_t* maxA; const uint32_t* maxB; uint32_t* maxC;   // |.|max bits per (tensor, slice)
+  const int32_t* expA; const int32_t* expB; int32_t* expC;       // power-of-two exponents
+  int32_t a_ps, b_ps, c_ps;     // 1: index max/exp by slice-local index, 0: slot 0
+  int32_t scale_mode;           // 0: no scaling/exponents; 1: scale operands to target_exp
+  int32_t target_exp;           // floor(log2 max) after scaling (14 for fp16 products)
+  int32_t chunk_bits;           // active slice-local bits in this launch
+  int32_t splits;               // K partitions
+  int32_t k_split_bits;         // log2(K per split)
+  int32_t tiles_m_bits, tiles_n_bits;
+  int32_t write_scratch;        // 1: this launch writes split partials to scratch
+};
+
+struct ReduceArgs {
+  const float* root;            // [slice][amp] complex64
+  const int32_t* exp;           // per slice exponent or null
+  double* acc;                  // [amp] complex128 accumulator
+  double* out;                  // partials output or null
+  int32_t* flag;                // set to 1 on Inf/NaN
+  int64_t n_amp;
+  int32_t n_slices;             // slices in this chunk
+};

@@ -1,0 +1,38 @@
+// Launch interface of the gfx950 kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tn_internal.h"
+
+enum {
+  TN_K_SMALL = 0,
+  TN_K_MFMA_F32 = 1,
+  TN_K_MFMA_F16X3 = 2,
+  TN_K_MFMA_BF16X3 = 3,
+  TN_K_SPLITK_REDUCE = 4
+};
+
+#define PERM_LOCAL_MAX 12
+
+// Permutation of one bit-indexed tensor: the block owns the local bits
+// (enumerated by ein in input-stride order and by eout in output-stride order,
+// row = LDS position increment); block index bits select the high bits.
+struct PermDesc {
+  int32_t nh;
+  int32_t pad_;
+  int64_t h_in[64];
+  int64_t h_out[64];
+  TileEnum ein, eout;
+};
+
+hipError_t tn_launch_gett(int kind, const GettDesc* d, const GettArgs& g, int64_t blocks, hipStream_t s);
+hipError_t tn_launch_permute(const PermDesc* p, int64_t blocks, const void* in, void* out, hipStream_t s);
+hipError_t tn_launch_slice_reduce(const ReduceArgs& r, hipStream_t s);
+hipError_t tn_launch_absmax(const void* x, int64_t n, uint32_t* dst, hipStream_t s);
+hipError_t tn_launch_fill_u32(void* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t tn_launch_scale_pow2(void* x, int64_t n, const int32_t* e, hipStream_t s);
+int tn_mfma_tile_m();
+int tn_mfma_tile_n();
+int tn_mfma_tile_k();

@@ -1,0 +1,1242 @@
+// Host planner and C ABI for sliced tensor-network contraction (see include/tn.h).
+//
+// Planning (once per network):
+//   1. validate labels, extents, open and sliced labels and the path (Sec. 3.1);
+//   2. expand every label into bits (all extents are powers of two);
+//   3. replay the path: for each pairwise step classify labels into batch /
+//      m / n / k (the einsum of Sec. 2.4; a label only one operand carries and
+//      nobody needs later is summed too), and mark steps that depend on the
+//      slice (Sec. 3.2);
+//   4. choose layouts from the root down: the root is stored in output order,
+//      and every other tensor is stored the way its consumer reads it,
+//      [k][free][batch] from the least significant bit up, with free bits in the
+//      order the consumer's result needs them (consumer-driven index order,
+//      Sec. 4.1 "reorder indices" applied to every step);
+//   5. pick a kernel, tile and K split per step, build the bit-stride
+//      descriptors, and place intermediates in two arenas by liveness;
+//   6. upload leaves and permute them on the device into their planned layouts.
+// Execution: slice-independent steps run once per call; slice-dependent steps
+// run per chunk of slices, with the slice-local index as extra batch bits;
+// every chunk ends with the FP64 cross-slice sum (Sec. 5: result tensors summed).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/tn.h"
+#include "tn_internal.h"
+#include "tn_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+tn_status fail(tn_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+int ilog2_exact(int64_t v) {
+  if (v < 1) return -1;
+  int b = 0;
+  while ((int64_t(1) << b) < v) ++b;
+  return (int64_t(1) << b) == v ? b : -1;
+}
+
+struct Label {
+  int64_t ext = 0;
+  int nb = 0;       // bits
+  int bit0 = 0;     // first bit id
+  bool open = false;
+  int slice_pos = -1;
+  int user = 0;
+};
+
+struct Tensor {
+  std::vector<int> labels;   // dense label ids (non-sliced), in no particular order
+  std::vector<int> bits;     // storage order, LSB first (non-sliced bits)
+  std::vector<int> sbits;    // leaves: sliced bits stored above `bits` (LSB first)
+  bool per_slice = false;
+  bool leaf = false;
+  bool layout_set = false;
+  int64_t elems = 1;         // 2^bits.size()
+  int arena = 0;             // 0 leaves, 1 invariant, 2 per-slice
+  int64_t offset = 0;        // elements
+  std::vector<int> user_layout;  // leaves: bits of the caller's row-major data, LSB first
+};
+
+struct Step {
+  int slot_a = 0, slot_b = 0;
+  int ta = 0, tb = 0, tc = 0;
+  std::vector<int> lb, lm, ln, lk;   // label classes
+  std::vector<int> bb, mb, nb, kb;   // bit lists in GEMM order, LSB first
+  bool per_slice = false;
+  int kernel = TN_K_SMALL;
+  int splits = 1;
+  int k_split_bits = 0;
+  int tiles_m_bits = 0, tiles_n_bits = 0;
+  int a_contig = 0, b_contig = 0;
+  double flops = 0, bytes = 0;
+  int64_t scratch_off = -1;          // elements in the step's arena
+  int64_t scratch_elems = 0;
+  GettDesc desc;
+};
+
+// First-fit interval allocator (units: elements), records the peak.
+struct Arena {
+  std::map<int64_t, int64_t> free_;  // offset -> size
+  int64_t top = 0, peak = 0;
+  static int64_t align(int64_t n) { return (n + 63) & ~int64_t(63); }
+  int64_t alloc(int64_t n) {
+    n = align(n);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        int64_t off = it->first, sz = it->second;
+        free_.erase(it);
+        if (sz > n) free_[off + n] = sz - n;
+        return off;
+      }
+    }
+    int64_t off = top;
+    top += n;
+    peak = std::max(peak, top);
+    return off;
+  }
+  void release(int64_t off, int64_t n) {
+    n = align(n);
+    free_[off] = n;
+    // coalesce
+    auto it = free_.find(off);
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+        it = prev;
+      }
+    }
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it->first + it->second == top) {
+      top = it->first;
+      free_.erase(it);
+    }
+  }
+};
+
+}  // namespace
+
+struct tn_plan_s {
+  tn_options opts{};
+  bool host_only = false;
+  hipStream_t stream = nullptr;
+  int precision = TN_PREC_C64;
+
+  std::vector<Label> labels;
+  int n_bits = 0;
+  std::vector<int> slice_bits;        // global slice id bit j -> bit id
+  int n_slice_bits = 0;
+  int64_t n_slices = 1;
+  int64_t n_amp = 1;
+  int n_leaves = 0;
+
+  std::vector<Tensor> tensors;
+  std::vector<Step> steps;
+  std::vector<int> inv_order, ps_order;   // step indices
+  int root = -1;
+
+  int S = 1, s_bits = 0;                  // slice chunk size
+  int64_t leaf_elems = 0, inv_elems = 0, ps_elems = 0;  // arena sizes (ps: for S slices)
+  int64_t max_intermediate = 0;
+  double flops_ps = 0, flops_inv = 0, bytes_ps = 0, bytes_inv = 0;
+
+  // device
+  float* d_leaves = nullptr;
+  float* d_inv = nullptr;
+  float* d_ps = nullptr;
+  GettDesc* d_desc = nullptr;
+  uint32_t* d_max_inv = nullptr;   // [n_tensors]
+  uint32_t* d_max_ps = nullptr;    // [n_tensors][S]
+  int32_t* d_exp_inv = nullptr;
+  int32_t* d_exp_ps = nullptr;
+  double* d_acc = nullptr;
+  double* d_part = nullptr;        // [S][n_amp] complex128 partials
+  int32_t* d_flag = nullptr;
+  int64_t slices_acc = 0;
+  size_t device_bytes = 0;
+
+  ~tn_plan_s() {
+    if (stream) hipStreamSynchronize(stream);
+    else if (!host_only) hipDeviceSynchronize();
+    void* ptrs[] = {d_leaves, d_inv, d_ps, d_desc, d_max_inv, d_max_ps, d_exp_inv, d_exp_ps, d_acc, d_part, d_flag};
+    for (void* p : ptrs)
+      if (p) hipFree(p);
+  }
+};
+
+namespace {
+
+bool scaled(const tn_plan_s* p) { return p->precision != TN_PREC_C64; }
+
+// stride (elements) of bit q in tensor T's storage; 0 if absent
+int64_t bit_stride(const Tensor& T, int q) {
+  for (size_t i = 0; i < T.bits.size(); ++i)
+    if (T.bits[i] == q) return int64_t(1) << i;
+  for (size_t i = 0; i < T.sbits.size(); ++i)
+    if (T.sbits[i] == q) return int64_t(1) << (T.bits.size() + i);
+  return 0;
+}
+
+// stride of slice-local bit j for operand T (chunk buffers: per-slice tensors are
+// stored [slice][elems]; sliced leaves carry the slice bits in their storage)
+int64_t slice_stride(const tn_plan_s* p, const Tensor& T, int j) {
+  if (!T.per_slice) return 0;
+  if (T.leaf) return bit_stride(T, p->slice_bits[j]);
+  return T.elems << j;
+}
+
+void fill_enum(TileEnum& en, std::vector<std::pair<int64_t, std::pair<int, int>>> bitsv) {
+  // bitsv: (stride, (row increment, col increment)); sort by stride
+  std::stable_sort(bitsv.begin(), bitsv.end(),
+                   [](const auto& a, const auto& b) { return a.first < b.first; });
+  memset(&en, 0, sizeof(en));
+  en.n = (int)bitsv.size();
+  for (size_t j = 0; j < bitsv.size(); ++j) {
+    en.stride[j] = bitsv[j].first;
+    en.row[j] = bitsv[j].second.first;
+    en.col[j] = bitsv[j].second.second;
+  }
+}
+
+int contig_run(const TileEnum& en) {
+  int r = 0;
+  for (int j = 0; j < en.n; ++j) {
+    if (en.stride[j] == (int64_t(1) << r)) ++r;
+    else if (en.stride[j] == 0) continue;
+    else break;
+  }
+  return r;
+}
+
+void build_desc(tn_plan_s* p, Step& st) {
+  GettDesc& d = st.desc;
+  memset(&d, 0, sizeof(d));
+  const Tensor& A = p->tensors[st.ta];
+  const Tensor& B = p->tensors[st.tb];
+  const Tensor& C = p->tensors[st.tc];
+  const int own = (int)st.bb.size();
+  const int sb = st.per_slice ? p->s_bits : 0;
+  d.own_bb = own;
+  d.nbb = own + sb;
+  d.mb = (int)st.mb.size();
+  d.nb = (int)st.nb.size();
+  d.kb = (int)st.kb.size();
+  d.c_nbits = (int)C.bits.size();
+  d.c_elems = C.elems;
+  for (int j = 0; j < own; ++j) {
+    d.a_b[j] = bit_stride(A, st.bb[j]);
+    d.b_b[j] = bit_stride(B, st.bb[j]);
+    d.c_b[j] = bit_stride(C, st.bb[j]);
+  }
+  for (int j = 0; j < sb; ++j) {
+    d.a_b[own + j] = slice_stride(p, A, j);
+    d.b_b[own + j] = slice_stride(p, B, j);
+    d.c_b[own + j] = slice_stride(p, C, j);
+  }
+  for (int j = 0; j < d.mb; ++j) {
+    d.a_m[j] = bit_stride(A, st.mb[j]);
+    d.c_m[j] = bit_stride(C, st.mb[j]);
+  }
+  for (int j = 0; j < d.nb; ++j) {
+    d.b_n[j] = bit_stride(B, st.nb[j]);
+    d.c_n[j] = bit_stride(C, st.nb[j]);
+  }
+  for (int j = 0; j < d.kb; ++j) {
+    d.a_k[j] = bit_stride(A, st.kb[j]);
+    d.b_k[j] = bit_stride(B, st.kb[j]);
+  }
+  for (size_t pos = 0; pos < C.bits.size(); ++pos) {
+    const int q = C.bits[pos];
+    int code = -1;
+    for (int j = 0; j < own; ++j)
+      if (st.bb[j] == q) code = (0 << 8) | j;
+    for (int j = 0; j < d.mb; ++j)
+      if (st.mb[j] == q) code = (1 << 8) | j;
+    for (int j = 0; j < d.nb; ++j)
+      if (st.nb[j] == q) code = (2 << 8) | j;
+    d.c_pos[pos] = code;
+  }
+  for (int j = 0; j < sb; ++j) d.c_pos[C.bits.size() + j] = (0 << 8) | (own + j);
+  // tile enumerations for the MFMA kernels
+  const int lm = std::min(d.mb, 7), ln = std::min(d.nb, 6), lk = std::min(d.kb, 4);
+  std::vector<std::pair<int64_t, std::pair<int, int>>> va, vb, vc;
+  for (int j = 0; j < lm; ++j) va.push_back({d.a_m[j], {1 << j, 0}});
+  for (int j = 0; j < lk; ++j) va.push_back({d.a_k[j], {0, 1 << j}});
+  for (int j = 0; j < ln; ++j) vb.push_back({d.b_n[j], {1 << j, 0}});
+  for (int j = 0; j < lk; ++j) vb.push_back({d.b_k[j], {0, 1 << j}});
+  for (int j = 0; j < lm; ++j) vc.push_back({d.c_m[j], {1 << j, 0}});
+  for (int j = 0; j < ln; ++j) vc.push_back({d.c_n[j], {0, 1 << j}});
+  fill_enum(d.ea, va);
+  fill_enum(d.eb, vb);
+  fill_enum(d.ec, vc);
+  st.a_contig = contig_run(d.ea);
+  st.b_contig = contig_run(d.eb);
+}
+
+void choose_kernel(tn_plan_s* p, Step& st) {
+  const int bbits = (int)st.bb.size() + (st.per_slice ? p->s_bits : 0);
+  const int mb = (int)st.mb.size(), nb = (int)st.nb.size(), kb = (int)st.kb.size();
+  const bool small = (kb <= 6 && bbits + mb + nb <= 14) || (bbits + mb + nb + kb <= 16);
+  if (small) {
+    st.kernel = TN_K_SMALL;
+    st.splits = 1;
+    return;
+  }
+  bool split_prec = false;
+  if (p->precision != TN_PREC_C64) {
+    if (p->opts.split_policy == 1) split_prec = kb >= 3;
+    else split_prec = kb >= 4 && mb >= 5 && nb >= 4;
+  }
+  st.kernel = split_prec ? (p->precision == TN_PREC_F16X3 ? TN_K_MFMA_F16X3 : TN_K_MFMA_BF16X3)
+                         : TN_K_MFMA_F32;
+  const int lm = std::min(mb, 7), ln = std::min(nb, 6), lk = std::min(kb, 4);
+  st.tiles_m_bits = mb - lm;
+  st.tiles_n_bits = nb - ln;
+  const int tile_bits = st.tiles_m_bits + st.tiles_n_bits + bbits;
+  int s = 0;
+  // split K when the grid is small and K long: aim for >= 1024 blocks, >= 8 K iterations per split
+  while (tile_bits + s < 10 && kb - (s + 1) >= lk + 3) ++s;
+  st.splits = 1 << s;
+  st.k_split_bits = kb - s;
+  st.scratch_elems = st.splits > 1 ? (int64_t(st.splits) << (bbits + mb + nb)) : 0;
+}
+
+// Every address a kernel forms is a sum of per-bit strides.  Check, for every
+// step and operand, that the largest reachable offset stays inside its buffer
+// and that no two bits share a non-zero stride.
+tn_status validate_bounds(const tn_plan_s* p) {
+  const int64_t S = int64_t(1) << p->s_bits;
+  for (size_t s = 0; s < p->steps.size(); ++s) {
+    const Step& st = p->steps[s];
+    const GettDesc& d = st.desc;
+    struct Op {
+      const Tensor* T;
+      const int64_t* b;
+      const int64_t* r;
+      int nr;
+      const int64_t* k;
+      int nk;
+    } ops[3] = {{&p->tensors[st.ta], d.a_b, d.a_m, d.mb, d.a_k, d.kb},
+                {&p->tensors[st.tb], d.b_b, d.b_n, d.nb, d.b_k, d.kb},
+                {&p->tensors[st.tc], d.c_b, d.c_m, d.mb, d.c_n, d.nb}};
+    for (int o = 0; o < 3; ++o) {
+      const Tensor& T = *ops[o].T;
+      std::vector<int64_t> strides;
+      for (int j = 0; j < d.nbb; ++j) strides.push_back(ops[o].b[j]);
+      for (int j = 0; j < ops[o].nr; ++j) strides.push_back(ops[o].r[j]);
+      for (int j = 0; j < ops[o].nk; ++j) strides.push_back(ops[o].k[j]);
+      int64_t cap = T.leaf ? (T.elems << T.sbits.size()) : (T.per_slice ? T.elems * S : T.elems);
+      int64_t mx = 0;
+      if (T.leaf && T.per_slice)  // slice bits above the chunk are a base offset
+        for (int j = (st.per_slice ? p->s_bits : 0); j < p->n_slice_bits; ++j) mx += bit_stride(T, p->slice_bits[j]);
+      std::set<int64_t> seen;
+      for (int64_t v : strides) {
+        if (v < 0 || (v & (v - 1)) != 0)
+          return fail(TN_E_STATE, "internal: step " + std::to_string(s) + " has a stride that is not a power of two");
+        if (v > 0 && !seen.insert(v).second)
+          return fail(TN_E_STATE, "internal: step " + std::to_string(s) + " has aliased operand bits");
+        mx += v;
+      }
+      if (mx >= cap)
+        return fail(TN_E_STATE, "internal: step " + std::to_string(s) + " operand " + std::to_string(o) +
+                                    " reaches offset " + std::to_string(mx) + " of " + std::to_string(cap));
+    }
+    if (st.kernel != TN_K_SMALL && st.splits > 1) {
+      const int64_t need = int64_t(st.splits) << (d.nbb + d.mb + d.nb);
+      if (need > st.scratch_elems) return fail(TN_E_STATE, "internal: split-K scratch too small");
+    }
+  }
+  return TN_OK;
+}
+
+tn_status check(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(TN_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return TN_OK;
+}
+
+// device permutation of a bit-indexed tensor: in_pos[q], out_pos[q] are storage positions
+tn_status permute_bits(const std::vector<int>& in_pos, const std::vector<int>& out_pos, const void* in,
+                       void* out, hipStream_t s, PermDesc* d_desc_scratch) {
+  const int n = (int)in_pos.size();
+  PermDesc pd;
+  memset(&pd, 0, sizeof(pd));
+  // local bits: lowest input positions U lowest output positions
+  std::vector<int> local;
+  const int want = std::min(n, 6);
+  for (int q = 0; q < n; ++q)
+    if (in_pos[q] < want || out_pos[q] < want) local.push_back(q);
+  while ((int)local.size() < std::min(n, PERM_LOCAL_MAX)) {
+    // widen with the next lowest output positions
+    int best = -1;
+    for (int q = 0; q < n; ++q)
+      if (std::find(local.begin(), local.end(), q) == local.end() && (best < 0 || out_pos[q] < out_pos[best])) best = q;
+    if (best < 0) break;
+    local.push_back(best);
+  }
+  std::vector<std::pair<int64_t, std::pair<int, int>>> vi, vo;
+  for (size_t r = 0; r < local.size(); ++r) {
+    vi.push_back({int64_t(1) << in_pos[local[r]], {1 << r, 0}});
+    vo.push_back({int64_t(1) << out_pos[local[r]], {1 << r, 0}});
+  }
+  fill_enum(pd.ein, vi);
+  fill_enum(pd.eout, vo);
+  int h = 0;
+  for (int q = 0; q < n; ++q) {
+    if (std::find(local.begin(), local.end(), q) != local.end()) continue;
+    pd.h_in[h] = int64_t(1) << in_pos[q];
+    pd.h_out[h] = int64_t(1) << out_pos[q];
+    ++h;
+  }
+  pd.nh = h;
+  tn_status st = check(hipMemcpyAsync(d_desc_scratch, &pd, sizeof(pd), hipMemcpyHostToDevice, s), "permute desc");
+  if (st) return st;
+  st = check(tn_launch_permute(d_desc_scratch, int64_t(1) << h, in, out, s), "permute launch");
+  if (st) return st;
+  return check(hipStreamSynchronize(s), "permute sync");
+}
+
+tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, const int32_t* const* labels,
+                     const int64_t* const* extents, const double* const* data, int32_t n_open,
+                     const int32_t* open_labels, int32_t n_steps, const int32_t* path, int32_t n_sliced,
+                     const int32_t* sliced_labels) {
+  if (n_tensors < 1) return fail(TN_E_ARG, "n_tensors must be >= 1");
+  if (!ranks || (!labels && n_tensors > 0) || !extents) return fail(TN_E_ARG, "null ranks/labels/extents");
+  if (n_open < 0 || (n_open > 0 && !open_labels)) return fail(TN_E_ARG, "bad open labels");
+  if (n_sliced < 0 || (n_sliced > 0 && !sliced_labels)) return fail(TN_E_ARG, "bad sliced labels");
+  if (n_steps < 0 || (n_steps > 0 && !path)) return fail(TN_E_ARG, "bad path");
+  if (!p->host_only && !data) return fail(TN_E_ARG, "null data");
+  std::map<int, int> dense;
+  // labels
+  for (int t = 0; t < n_tensors; ++t) {
+    if (ranks[t] < 0 || ranks[t] > 64) return fail(TN_E_ARG, "rank out of range");
+    if (ranks[t] > 0 && (!labels[t] || !extents[t])) return fail(TN_E_ARG, "null labels/extents of a tensor");
+    std::set<int> seen;
+    for (int r = 0; r < ranks[t]; ++r) {
+      const int l = labels[t][r];
+      const int64_t e = extents[t][r];
+      if (l < 0) return fail(TN_E_LABEL, "negative label id");
+      if (!seen.insert(l).second) return fail(TN_E_LABEL, "label repeated within one tensor");
+      if (e < 1) return fail(TN_E_LABEL, "extent must be >= 1");
+      auto it = dense.find(l);
+      if (it == dense.end()) {
+        Label L;
+        L.ext = e;
+        L.user = l;
+        L.nb = ilog2_exact(e);
+        if (L.nb < 0) return fail(TN_E_UNSUPPORTED, "extent " + std::to_string(e) + " is not a power of two");
+        dense[l] = (int)p->labels.size();
+        p->labels.push_back(L);
+      } else if (p->labels[it->second].ext != e) {
+        return fail(TN_E_LABEL, "label " + std::to_string(l) + " has inconsistent extents");
+      }
+    }
+  }
+  std::vector<int> open_d;
+  for (int i = 0; i < n_open; ++i) {
+    auto it = dense.find(open_labels[i]);
+    if (it == dense.end()) return fail(TN_E_LABEL, "open label " + std::to_string(open_labels[i]) + " is on no tensor");
+    if (p->labels[it->second].open) return fail(TN_E_LABEL, "open label repeated");
+    p->labels[it->second].open = true;
+    open_d.push_back(it->second);
+  }
+  std::vector<int> sliced_d;
+  for (int i = 0; i < n_sliced; ++i) {
+    auto it = dense.find(sliced_labels[i]);
+    if (it == dense.end()) return fail(TN_E_SLICE, "sliced label is on no tensor");
+    Label& L = p->labels[it->second];
+    if (L.open) return fail(TN_E_SLICE, "a sliced label may not be open");
+    if (L.slice_pos >= 0) return fail(TN_E_SLICE, "sliced label repeated");
+    L.slice_pos = i;
+    sliced_d.push_back(it->second);
+  }
+  // bits
+  p->n_bits = 0;
+  for (auto& L : p->labels) {
+    L.bit0 = p->n_bits;
+    p->n_bits += L.nb;
+  }
+  // slice id bits, LSB first: last sliced label least significant
+  for (int i = n_sliced - 1; i >= 0; --i) {
+    const Label& L = p->labels[sliced_d[i]];
+    for (int b = 0; b < L.nb; ++b) p->slice_bits.push_back(L.bit0 + b);
+  }
+  p->n_slice_bits = (int)p->slice_bits.size();
+  if (p->n_slice_bits > 40) return fail(TN_E_UNSUPPORTED, "too many slice bits");
+  p->n_slices = int64_t(1) << p->n_slice_bits;
+  int amp_bits = 0;
+  for (int l : open_d) amp_bits += p->labels[l].nb;
+  if (amp_bits > 30) return fail(TN_E_UNSUPPORTED, "too many output bits");
+  p->n_amp = int64_t(1) << amp_bits;
+
+  // leaves (plus a unit scalar when the network is a single tensor)
+  const bool single = n_tensors == 1;
+  if (single) {
+    if (n_steps != 0) return fail(TN_E_PATH, "a single tensor takes an empty path");
+  } else if (n_steps != n_tensors - 1) {
+    return fail(TN_E_PATH, "path must have n_tensors - 1 steps");
+  }
+  p->n_leaves = n_tensors + (single ? 1 : 0);
+  for (int t = 0; t < n_tensors; ++t) {
+    Tensor T;
+    T.leaf = true;
+    for (int r = ranks[t] - 1; r >= 0; --r) {
+      const Label& L = p->labels[dense[labels[t][r]]];
+      for (int b = 0; b < L.nb; ++b) T.user_layout.push_back(L.bit0 + b);
+    }
+    for (int r = 0; r < ranks[t]; ++r) {
+      const int l = dense[labels[t][r]];
+      if (p->labels[l].slice_pos >= 0) {
+        if (p->labels[l].nb > 0) T.per_slice = true;
+      } else {
+        T.labels.push_back(l);
+      }
+    }
+    p->tensors.push_back(T);
+  }
+  if (single) {
+    Tensor U;
+    U.leaf = true;
+    p->tensors.push_back(U);
+  }
+  // replay the path
+  std::vector<int> slot(p->n_leaves);
+  for (int i = 0; i < p->n_leaves; ++i) slot[i] = i;
+  std::vector<int> count(p->labels.size(), 0);
+  for (auto& T : p->tensors)
+    for (int l : T.labels) count[l]++;
+  std::vector<std::pair<int, int>> pairs;
+  if (single) pairs.push_back({0, 1});
+  for (int s = 0; s < n_steps; ++s) pairs.push_back({path[2 * s], path[2 * s + 1]});
+  for (size_t s = 0; s < pairs.size(); ++s) {
+    const int i = pairs[s].first, j = pairs[s].second;
+    if (i < 0 || j < 0 || i >= p->n_leaves || j >= p->n_leaves || i == j)
+      return fail(TN_E_PATH, "path step " + std::to_string(s) + " has an invalid slot");
+    if (slot[i] < 0 || slot[j] < 0) return fail(TN_E_PATH, "path step " + std::to_string(s) + " uses a dead slot");
+    Step st;
+    st.slot_a = i;
+    st.slot_b = j;
+    st.ta = slot[i];
+    st.tb = slot[j];
+    const Tensor& A = p->tensors[st.ta];
+    const Tensor& B = p->tensors[st.tb];
+    for (int l : A.labels) count[l]--;
+    for (int l : B.labels) count[l]--;
+    std::set<int> sa(A.labels.begin(), A.labels.end()), sbs(B.labels.begin(), B.labels.end());
+    std::set<int> all = sa;
+    all.insert(sbs.begin(), sbs.end());
+    Tensor C;
+    for (int l : all) {
+      const bool keep = p->labels[l].open || count[l] > 0;
+      const bool ina = sa.count(l), inb = sbs.count(l);
+      if (ina && inb) (keep ? st.lb : st.lk).push_back(l);
+      else if (ina) (keep ? st.lm : st.lk).push_back(l);
+      else (keep ? st.ln : st.lk).push_back(l);
+      if (keep) C.labels.push_back(l);
+    }
+    for (int l : C.labels) count[l]++;
+    C.per_slice = A.per_slice || B.per_slice;
+    st.per_slice = C.per_slice;
+    st.tc = (int)p->tensors.size();
+    p->tensors.push_back(C);
+    slot[i] = st.tc;
+    slot[j] = -1;
+    p->steps.push_back(st);
+  }
+  int live = 0;
+  for (int i = 0; i < p->n_leaves; ++i)
+    if (slot[i] >= 0) {
+      ++live;
+      p->root = slot[i];
+    }
+  if (live != 1) return fail(TN_E_PATH, "path does not reduce the network to one tensor");
+  // sizes and cap
+  for (auto& T : p->tensors) {
+    int nb = 0;
+    for (int l : T.labels) nb += p->labels[l].nb;
+    if (nb > 36) return fail(TN_E_UNSUPPORTED, "tensor with more than 2^36 elements");
+    T.elems = int64_t(1) << nb;
+  }
+  for (auto& st : p->steps) {
+    p->max_intermediate = std::max(p->max_intermediate, p->tensors[st.tc].elems);
+    if (p->opts.mem_cap_elems > 0 && p->tensors[st.tc].elems > p->opts.mem_cap_elems)
+      return fail(TN_E_CAP, "intermediate of " + std::to_string(p->tensors[st.tc].elems) +
+                                " elements exceeds the cap");
+  }
+  // layouts, root first
+  {
+    Tensor& R = p->tensors[p->root];
+    R.bits.clear();
+    for (int i = (int)open_d.size() - 1; i >= 0; --i) {
+      const Label& L = p->labels[open_d[i]];
+      for (int b = 0; b < L.nb; ++b) R.bits.push_back(L.bit0 + b);
+    }
+    R.layout_set = true;
+  }
+  for (int s = (int)p->steps.size() - 1; s >= 0; --s) {
+    Step& st = p->steps[s];
+    const Tensor& C = p->tensors[st.tc];
+    std::map<int, int> cpos;
+    for (size_t i = 0; i < C.bits.size(); ++i) cpos[C.bits[i]] = (int)i;
+    auto bits_of = [&](const std::vector<int>& ls) {
+      std::vector<int> out;
+      for (int l : ls)
+        for (int b = 0; b < p->labels[l].nb; ++b) out.push_back(p->labels[l].bit0 + b);
+      return out;
+    };
+    auto by_cpos = [&](std::vector<int> v) {
+      std::sort(v.begin(), v.end(), [&](int a, int b) { return cpos.at(a) < cpos.at(b); });
+      return v;
+    };
+    st.bb = by_cpos(bits_of(st.lb));
+    st.mb = by_cpos(bits_of(st.lm));
+    st.nb = by_cpos(bits_of(st.ln));
+    st.kb = bits_of(st.lk);
+    std::sort(st.kb.begin(), st.kb.end());
+    if ((int)st.bb.size() + p->s_bits > TN_MAXB - 8 || (int)st.mb.size() > TN_MAXR ||
+        (int)st.nb.size() > TN_MAXR || (int)st.kb.size() > TN_MAXK)
+      return fail(TN_E_UNSUPPORTED, "step has too many bits for the kernels");
+    Tensor& A = p->tensors[st.ta];
+    Tensor& B = p->tensors[st.tb];
+    std::set<int> abits, bbits;
+    for (int q : bits_of(A.labels)) abits.insert(q);
+    for (int q : bits_of(B.labels)) bbits.insert(q);
+    A.bits.clear();
+    for (int q : st.kb)
+      if (abits.count(q)) A.bits.push_back(q);
+    for (int q : st.mb) A.bits.push_back(q);
+    for (int q : st.bb) A.bits.push_back(q);
+    B.bits.clear();
+    for (int q : st.kb)
+      if (bbits.count(q)) B.bits.push_back(q);
+    for (int q : st.nb) B.bits.push_back(q);
+    for (int q : st.bb) B.bits.push_back(q);
+    A.layout_set = B.layout_set = true;
+  }
+  // leaves: sliced bits on top, in slice-id order
+  for (int t = 0; t < p->n_leaves; ++t) {
+    Tensor& T = p->tensors[t];
+    for (int q : p->slice_bits)
+      if (std::find(T.user_layout.begin(), T.user_layout.end(), q) != T.user_layout.end()) T.sbits.push_back(q);
+  }
+  // slice chunk size
+  int64_t want = p->opts.slice_batch > 0 ? p->opts.slice_batch : 8;
+  if (p->opts.slice_batch > 0 && ilog2_exact(p->opts.slice_batch) < 0)
+    return fail(TN_E_ARG, "slice_batch must be a power of two");
+  p->s_bits = 0;
+  while ((int64_t(2) << p->s_bits) <= std::min<int64_t>(want, p->n_slices)) ++p->s_bits;
+  if (p->n_slice_bits == 0) p->s_bits = 0;
+  // kernels, descriptors and costs
+  for (auto& st : p->steps) {
+    choose_kernel(p, st);
+    const Tensor& A = p->tensors[st.ta];
+    const Tensor& B = p->tensors[st.tb];
+    const Tensor& C = p->tensors[st.tc];
+    int ub = (int)(st.bb.size() + st.mb.size() + st.nb.size() + st.kb.size());
+    st.flops = 8.0 * std::ldexp(1.0, ub);
+    st.bytes = 8.0 * ((double)A.elems + (double)B.elems + (double)C.elems);
+    if (st.per_slice) {
+      p->flops_ps += st.flops;
+      p->bytes_ps += st.bytes;
+    } else {
+      p->flops_inv += st.flops;
+      p->bytes_inv += st.bytes;
+    }
+  }
+  for (size_t s = 0; s < p->steps.size(); ++s)
+    (p->steps[s].per_slice ? p->ps_order : p->inv_order).push_back((int)s);
+  // memory: leaves, invariant arena, per-slice arena (S copies of each tensor)
+  int64_t off = 0;
+  for (int t = 0; t < p->n_leaves; ++t) {
+    Tensor& T = p->tensors[t];
+    T.arena = 0;
+    T.offset = off;
+    off += Arena::align(T.elems << T.sbits.size());
+  }
+  p->leaf_elems = std::max<int64_t>(off, 64);
+  Arena inv, ps;
+  for (int s : p->inv_order) {
+    Step& st = p->steps[s];
+    Tensor& C = p->tensors[st.tc];
+    C.arena = 1;
+    C.offset = inv.alloc(C.elems);
+    if (st.scratch_elems) st.scratch_off = inv.alloc(st.scratch_elems);
+    if (st.scratch_elems) inv.release(st.scratch_off, st.scratch_elems);
+    for (int x : {st.ta, st.tb}) {
+      Tensor& X = p->tensors[x];
+      if (!X.leaf && X.arena == 1) inv.release(X.offset, X.elems);
+    }
+  }
+  const int64_t S = int64_t(1) << p->s_bits;
+  for (int s : p->ps_order) {
+    Step& st = p->steps[s];
+    Tensor& C = p->tensors[st.tc];
+    C.arena = 2;
+    C.offset = ps.alloc(C.elems * S);
+    if (st.scratch_elems) st.scratch_off = ps.alloc(st.scratch_elems);
+    if (st.scratch_elems) ps.release(st.scratch_off, st.scratch_elems);
+    for (int x : {st.ta, st.tb}) {
+      Tensor& X = p->tensors[x];
+      if (!X.leaf && X.arena == 2) ps.release(X.offset, X.elems * S);
+    }
+  }
+  p->inv_elems = std::max<int64_t>(inv.peak, 64);
+  p->ps_elems = std::max<int64_t>(ps.peak, 64);
+  for (auto& st : p->steps) build_desc(p, st);
+  p->S = (int)S;
+  if (tn_status vb = validate_bounds(p)) return vb;
+  if (p->host_only) return TN_OK;
+
+  // ---- device setup ----
+  hipStream_t s = p->stream;
+  auto dmalloc = [&](void** ptr, size_t bytes) -> tn_status {
+    if (hipMalloc(ptr, bytes) != hipSuccess) {
+      hipGetLastError();
+      return fail(TN_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    p->device_bytes += bytes;
+    return TN_OK;
+  };
+  tn_status st;
+  const size_t nt = p->tensors.size();
+  if ((st = dmalloc((void**)&p->d_leaves, p->leaf_elems * 8))) return st;
+  if ((st = dmalloc((void**)&p->d_inv, p->inv_elems * 8))) return st;
+  if ((st = dmalloc((void**)&p->d_ps, p->ps_elems * 8))) return st;
+  if ((st = dmalloc((void**)&p->d_desc, sizeof(GettDesc) * std::max<size_t>(p->steps.size(), 1) + sizeof(PermDesc)))) return st;
+  if ((st = dmalloc((void**)&p->d_max_inv, nt * 4))) return st;
+  if ((st = dmalloc((void**)&p->d_max_ps, nt * S * 4))) return st;
+  if ((st = dmalloc((void**)&p->d_exp_inv, nt * 4))) return st;
+  if ((st = dmalloc((void**)&p->d_exp_ps, nt * S * 4))) return st;
+  if ((st = dmalloc((void**)&p->d_acc, p->n_amp * 16))) return st;
+  if ((st = dmalloc((void**)&p->d_part, p->n_amp * 16 * S))) return st;
+  if ((st = dmalloc((void**)&p->d_flag, 64))) return st;
+  if ((st = check(hipMemsetAsync(p->d_acc, 0, p->n_amp * 16, s), "memset acc"))) return st;
+  if ((st = check(hipMemsetAsync(p->d_flag, 0, 64, s), "memset flag"))) return st;
+  if ((st = check(hipMemsetAsync(p->d_max_inv, 0, nt * 4, s), "memset max"))) return st;
+  if ((st = check(hipMemsetAsync(p->d_exp_inv, 0, nt * 4, s), "memset exp"))) return st;
+  if ((st = check(hipMemsetAsync(p->d_exp_ps, 0, nt * S * 4, s), "memset exp"))) return st;
+  std::vector<GettDesc> descs(p->steps.size());
+  for (size_t i = 0; i < p->steps.size(); ++i) descs[i] = p->steps[i].desc;
+  if (!descs.empty() &&
+      (st = check(hipMemcpyAsync(p->d_desc, descs.data(), sizeof(GettDesc) * descs.size(), hipMemcpyHostToDevice, s),
+                  "desc upload")))
+    return st;
+  PermDesc* d_perm = reinterpret_cast<PermDesc*>(p->d_desc + std::max<size_t>(p->steps.size(), 1));
+  // leaves: upload complex128 -> complex64 staging, then permute on the device
+  float* d_stage = nullptr;
+  int64_t max_leaf = 1;
+  for (int t = 0; t < p->n_leaves; ++t) max_leaf = std::max(max_leaf, p->tensors[t].elems << p->tensors[t].sbits.size());
+  if ((st = dmalloc((void**)&d_stage, max_leaf * 8))) return st;
+  std::vector<float> host;
+  for (int t = 0; t < p->n_leaves; ++t) {
+    Tensor& T = p->tensors[t];
+    const int64_t n = T.elems << T.sbits.size();
+    host.assign(2 * n, 0.f);
+    if (t < n_tensors) {
+      if (!data[t]) {
+        hipFree(d_stage);
+        return fail(TN_E_ARG, "null data for a tensor");
+      }
+      for (int64_t i = 0; i < 2 * n; ++i) host[i] = (float)data[t][i];
+    } else {
+      host[0] = 1.f;  // unit scalar
+    }
+    st = check(hipMemcpyAsync(d_stage, host.data(), n * 8, hipMemcpyHostToDevice, s), "leaf upload");
+    if (!st) st = check(hipStreamSynchronize(s), "leaf upload sync");
+    if (st) {
+      hipFree(d_stage);
+      return st;
+    }
+    // user layout -> planned layout (bits then sliced bits)
+    std::vector<int> full = T.bits;
+    full.insert(full.end(), T.sbits.begin(), T.sbits.end());
+    if (full.size() != T.user_layout.size()) {
+      hipFree(d_stage);
+      return fail(TN_E_STATE, "internal: leaf layout size mismatch");
+    }
+    std::vector<int> in_pos(full.size()), out_pos(full.size());
+    for (size_t q = 0; q < full.size(); ++q) {
+      out_pos[q] = (int)q;
+      in_pos[q] = (int)(std::find(T.user_layout.begin(), T.user_layout.end(), full[q]) - T.user_layout.begin());
+    }
+    float* dst = p->d_leaves + 2 * T.offset;
+    if (full.empty()) {
+      st = check(hipMemcpyAsync(dst, d_stage, 8, hipMemcpyDeviceToDevice, s), "scalar leaf");
+    } else {
+      st = permute_bits(in_pos, out_pos, d_stage, dst, s, d_perm);
+    }
+    if (st) {
+      hipFree(d_stage);
+      return st;
+    }
+    if (scaled(p)) {
+      st = check(tn_launch_absmax(dst, n, p->d_max_inv + t, s), "leaf max");
+      if (st) {
+        hipFree(d_stage);
+        return st;
+      }
+    }
+  }
+  st = check(hipStreamSynchronize(s), "setup sync");
+  hipFree(d_stage);
+  p->device_bytes -= max_leaf * 8;
+  return st;
+}
+
+const float* tensor_ptr(const tn_plan_s* p, const Tensor& T) {
+  if (T.arena == 0) return p->d_leaves + 2 * T.offset;
+  if (T.arena == 1) return p->d_inv + 2 * T.offset;
+  return p->d_ps + 2 * T.offset;
+}
+
+// chunk offset of a sliced leaf for the slice bits above the chunk
+int64_t leaf_chunk_offset(const tn_plan_s* p, const Tensor& T, int64_t base, int chunk_bits) {
+  int64_t off = 0;
+  for (int j = chunk_bits; j < p->n_slice_bits; ++j)
+    if ((base >> j) & 1) off += bit_stride(T, p->slice_bits[j]);
+  return off;
+}
+
+tn_status run_step(tn_plan_s* p, int s, int64_t chunk_base, int chunk_bits) {
+  Step& st = p->steps[s];
+  const Tensor& A = p->tensors[st.ta];
+  const Tensor& B = p->tensors[st.tb];
+  const Tensor& C = p->tensors[st.tc];
+  GettArgs g;
+  memset(&g, 0, sizeof(g));
+  g.A = tensor_ptr(p, A) + 2 * (A.leaf ? leaf_chunk_offset(p, A, chunk_base, chunk_bits) : 0);
+  g.B = tensor_ptr(p, B) + 2 * (B.leaf ? leaf_chunk_offset(p, B, chunk_base, chunk_bits) : 0);
+  g.C = const_cast<float*>(tensor_ptr(p, C));
+  const int S = p->S;
+  auto slots = [&](const Tensor& T, int id, const uint32_t*& mx, const int32_t*& ex, int& ps) {
+    if (T.per_slice && !T.leaf) {
+      mx = p->d_max_ps + (int64_t)id * S;
+      ex = p->d_exp_ps + (int64_t)id * S;
+      ps = 1;
+    } else {
+      mx = p->d_max_inv + id;
+      ex = p->d_exp_inv + id;
+      ps = 0;
+    }
+  };
+  const int32_t* ec;
+  const uint32_t* mc;
+  slots(A, st.ta, g.maxA, g.expA, g.a_ps);
+  slots(B, st.tb, g.maxB, g.expB, g.b_ps);
+  slots(C, st.tc, mc, ec, g.c_ps);
+  g.scale_mode = scaled(p) ? 1 : 0;
+  if (g.scale_mode) {
+    g.maxC = const_cast<uint32_t*>(mc);
+    g.expC = const_cast<int32_t*>(ec);
+  }
+  g.target_exp = (st.kernel == TN_K_MFMA_F16X3 || st.kernel == TN_K_MFMA_BF16X3) ? 14 : 0;
+  g.chunk_bits = st.per_slice ? chunk_bits : 0;
+  const GettDesc* d = p->d_desc + s;
+  const int bbits = (int)st.bb.size() + g.chunk_bits;
+  if (st.kernel == TN_K_SMALL) {
+    const int64_t total = int64_t(1) << (C.bits.size() + g.chunk_bits);
+    return check(tn_launch_gett(TN_K_SMALL, d, g, (total + 255) / 256, p->stream), "small step");
+  }
+  g.splits = st.splits;
+  g.k_split_bits = st.k_split_bits;
+  g.tiles_m_bits = st.tiles_m_bits;
+  g.tiles_n_bits = st.tiles_n_bits;
+  const int64_t blocks = (int64_t(st.splits)) << (st.tiles_m_bits + st.tiles_n_bits + bbits);
+  if (st.splits > 1) {
+    float* base = st.per_slice ? p->d_ps : p->d_inv;
+    g.scratch = base + 2 * st.scratch_off;
+    g.write_scratch = 1;
+    tn_status r = check(tn_launch_gett(st.kernel, d, g, blocks, p->stream), "mfma step");
+    if (r) return r;
+    g.write_scratch = 0;
+    const int64_t total = int64_t(1) << (C.bits.size() + g.chunk_bits);
+    return check(tn_launch_gett(TN_K_SPLITK_REDUCE, d, g, (total + 255) / 256, p->stream), "split-K reduce");
+  }
+  return check(tn_launch_gett(st.kernel, d, g, blocks, p->stream), "mfma step");
+}
+
+tn_status run_invariant(tn_plan_s* p) {
+  tn_status st;
+  if (scaled(p)) {
+    const int64_t nt = (int64_t)p->tensors.size();
+    if ((st = check(tn_launch_fill_u32(p->d_max_inv + p->n_leaves, 0, nt - p->n_leaves, p->stream), "fill")))
+      return st;
+  }
+  for (int s : p->inv_order)
+    if ((st = run_step(p, s, 0, 0))) return st;
+  return TN_OK;
+}
+
+// One chunk of 2^bits slices starting at base (aligned); reduce into acc or write partials.
+tn_status run_chunk(tn_plan_s* p, int64_t base, int bits, double* partial_out) {
+  tn_status st;
+  if (scaled(p) && !p->ps_order.empty()) {
+    if ((st = check(tn_launch_fill_u32(p->d_max_ps, 0, (int64_t)p->tensors.size() * p->S, p->stream), "fill")))
+      return st;
+  }
+  for (int s : p->ps_order)
+    if ((st = run_step(p, s, base, bits))) return st;
+  const Tensor& R = p->tensors[p->root];
+  ReduceArgs r;
+  memset(&r, 0, sizeof(r));
+  r.root = tensor_ptr(p, R);
+  if (scaled(p)) r.exp = R.per_slice ? p->d_exp_ps + (int64_t)p->root * p->S : p->d_exp_inv + p->root;
+  r.acc = p->d_acc;
+  r.out = partial_out;
+  r.flag = p->d_flag;
+  r.n_amp = p->n_amp;
+  r.n_slices = 1 << bits;
+  return check(tn_launch_slice_reduce(r, p->stream), "slice reduce");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tn_status_string(tn_status s) {
+  switch (s) {
+    case TN_OK: return "TN_OK";
+    case TN_E_ARG: return "TN_E_ARG";
+    case TN_E_LABEL: return "TN_E_LABEL";
+    case TN_E_PATH: return "TN_E_PATH";
+    case TN_E_SLICE: return "TN_E_SLICE";
+    case TN_E_CAP: return "TN_E_CAP";
+    case TN_E_NOMEM: return "TN_E_NOMEM";
+    case TN_E_DEVICE: return "TN_E_DEVICE";
+    case TN_E_STATE: return "TN_E_STATE";
+    case TN_E_UNSUPPORTED: return "TN_E_UNSUPPORTED";
+    case TN_E_NUMERIC: return "TN_E_NUMERIC";
+  }
+  return "unknown status";
+}
+
+const char* tn_last_error_message(void) { return g_err.c_str(); }
+
+tn_status tn_plan_create(tn_plan* out, int32_t n_tensors, const int32_t* ranks, const int32_t* const* labels,
+                         const int64_t* const* extents, const double* const* data, int32_t n_open,
+                         const int32_t* open_labels, int32_t n_steps, const int32_t* path, int32_t n_sliced,
+                         const int32_t* sliced_labels, const tn_options* opts) {
+  if (!out) return fail(TN_E_ARG, "null output pointer");
+  *out = nullptr;
+  tn_plan_s* p = new (std::nothrow) tn_plan_s();
+  if (!p) return fail(TN_E_NOMEM, "host allocation failed");
+  if (opts) {
+    if (opts->struct_size < (int32_t)offsetof(tn_options, reserved)) {
+      delete p;
+      return fail(TN_E_ARG, "tn_options.struct_size too small");
+    }
+    memcpy(&p->opts, opts, std::min<size_t>(sizeof(tn_options), (size_t)opts->struct_size));
+  }
+  p->host_only = p->opts.host_only != 0;
+  p->stream = reinterpret_cast<hipStream_t>(p->opts.stream);
+  p->precision = p->opts.precision;
+  if (p->precision < TN_PREC_C64 || p->precision > TN_PREC_BF16X3) {
+    delete p;
+    return fail(TN_E_ARG, "unknown precision");
+  }
+  g_err.clear();
+  tn_status st = plan_build(p, n_tensors, ranks, labels, extents, data, n_open, open_labels, n_steps, path,
+                            n_sliced, sliced_labels);
+  if (st != TN_OK) {
+    std::string keep = g_err;
+    delete p;
+    g_err = keep;
+    return st;
+  }
+  *out = p;
+  return TN_OK;
+}
+
+void tn_plan_destroy(tn_plan plan) { delete plan; }
+
+tn_status tn_plan_describe(tn_plan p, tn_plan_info* out) {
+  if (!p || !out) return fail(TN_E_ARG, "null argument");
+  memset(out, 0, sizeof(*out));
+  out->n_slices = p->n_slices;
+  out->n_amplitudes = p->n_amp;
+  out->n_steps = (int32_t)p->steps.size();
+  out->n_slice_steps = (int32_t)p->ps_order.size();
+  out->flops_per_slice = p->flops_ps;
+  out->flops_invariant = p->flops_inv;
+  out->bytes_per_slice = p->bytes_ps;
+  out->bytes_invariant = p->bytes_inv;
+  out->max_intermediate = p->max_intermediate;
+  out->workspace_bytes = p->host_only ? (p->leaf_elems + p->inv_elems + p->ps_elems) * 8 : (int64_t)p->device_bytes;
+  out->slice_batch = p->S;
+  out->precision = p->precision;
+  return TN_OK;
+}
+
+tn_status tn_plan_steps(tn_plan p, tn_step_info* steps, int32_t cap) {
+  if (!p || (!steps && cap > 0) || cap < 0) return fail(TN_E_ARG, "bad arguments");
+  const int n = std::min<int>(cap, (int)p->steps.size());
+  for (int i = 0; i < n; ++i) {
+    const Step& st = p->steps[i];
+    tn_step_info& o = steps[i];
+    memset(&o, 0, sizeof(o));
+    o.slot_a = st.slot_a;
+    o.slot_b = st.slot_b;
+    o.per_slice = st.per_slice;
+    o.kernel = st.kernel == TN_K_SMALL ? 0 : st.kernel == TN_K_MFMA_F32 ? 1 : st.kernel == TN_K_MFMA_F16X3 ? 2 : 3;
+    o.batch = int64_t(1) << st.bb.size();
+    o.m = int64_t(1) << st.mb.size();
+    o.n = int64_t(1) << st.nb.size();
+    o.k = int64_t(1) << st.kb.size();
+    o.split_k = st.splits;
+    o.tile_m = st.kernel == TN_K_SMALL ? 1 : (int)std::min<int64_t>(o.m, tn_mfma_tile_m());
+    o.tile_n = st.kernel == TN_K_SMALL ? 1 : (int)std::min<int64_t>(o.n, tn_mfma_tile_n());
+    o.a_contig = st.a_contig;
+    o.b_contig = st.b_contig;
+    o.flops = st.flops;
+    o.bytes = st.bytes;
+  }
+  return TN_OK;
+}
+
+tn_status tn_contract_slices(tn_plan p, int64_t first, int64_t n) {
+  if (!p) return fail(TN_E_ARG, "null plan");
+  if (p->host_only) return fail(TN_E_STATE, "host-only plan");
+  if (first < 0 || n < 0 || first + n > p->n_slices) return fail(TN_E_SLICE, "slice range out of bounds");
+  if (n == 0) return TN_OK;
+  tn_status st = run_invariant(p);
+  if (st) return st;
+  int64_t cur = first, end = first + n;
+  while (cur < end) {
+    int bits = 0;
+    while (bits < p->s_bits && (cur & ((int64_t(2) << bits) - 1)) == 0 && cur + (int64_t(2) << bits) <= end) ++bits;
+    if ((st = run_chunk(p, cur, bits, nullptr))) return st;
+    cur += int64_t(1) << bits;
+  }
+  p->slices_acc += n;
+  return TN_OK;
+}
+
+tn_status tn_slice_partials(tn_plan p, const int64_t* ids, int64_t n, double* out) {
+  if (!p || (n > 0 && (!ids || !out)) || n < 0) return fail(TN_E_ARG, "bad arguments");
+  if (p->host_only) return fail(TN_E_STATE, "host-only plan");
+  for (int64_t i = 0; i < n; ++i)
+    if (ids[i] < 0 || ids[i] >= p->n_slices) return fail(TN_E_SLICE, "slice id out of range");
+  if (n == 0) return TN_OK;
+  tn_status st = run_invariant(p);
+  if (st) return st;
+  for (int64_t i = 0; i < n; ++i) {
+    if ((st = run_chunk(p, ids[i], 0, p->d_part))) return st;
+    if ((st = check(hipMemcpyAsync(out + 2 * p->n_amp * i, p->d_part, p->n_amp * 16, hipMemcpyDeviceToHost, p->stream),
+                    "partials copy")))
+      return st;
+  }
+  st = check(hipStreamSynchronize(p->stream), "partials sync");
+  if (st) return st;
+  int32_t flag = 0;
+  st = check(hipMemcpy(&flag, p->d_flag, 4, hipMemcpyDeviceToHost), "flag copy");
+  if (st) return st;
+  if (flag) return fail(TN_E_NUMERIC, "Inf or NaN in a slice result");
+  return TN_OK;
+}
+
+tn_status tn_amplitudes(tn_plan p, double* out, int64_t n_amp, int64_t* slices_accumulated) {
+  if (!p || !out) return fail(TN_E_ARG, "null argument");
+  if (p->host_only) return fail(TN_E_STATE, "host-only plan");
+  if (n_amp != p->n_amp) return fail(TN_E_ARG, "n_amp does not match the plan's output size");
+  tn_status st = check(hipStreamSynchronize(p->stream), "stream sync");
+  if (st) return st;
+  int32_t flag = 0;
+  if ((st = check(hipMemcpy(&flag, p->d_flag, 4, hipMemcpyDeviceToHost), "flag copy"))) return st;
+  if (flag) return fail(TN_E_NUMERIC, "Inf or NaN reached a slice result");
+  if ((st = check(hipMemcpy(out, p->d_acc, n_amp * 16, hipMemcpyDeviceToHost), "accumulator copy"))) return st;
+  if (slices_accumulated) *slices_accumulated = p->slices_acc;
+  return TN_OK;
+}
+
+tn_status tn_accumulator_set(tn_plan p, const double* acc, int64_t n_amp, int64_t slices_accumulated) {
+  if (!p || !acc) return fail(TN_E_ARG, "null argument");
+  if (p->host_only) return fail(TN_E_STATE, "host-only plan");
+  if (n_amp != p->n_amp) return fail(TN_E_ARG, "n_amp does not match the plan's output size");
+  if (slices_accumulated < 0) return fail(TN_E_ARG, "negative slice count");
+  tn_status st = check(hipStreamSynchronize(p->stream), "stream sync");
+  if (st) return st;
+  if ((st = check(hipMemcpy(p->d_acc, acc, n_amp * 16, hipMemcpyHostToDevice), "accumulator copy"))) return st;
+  p->slices_acc = slices_accumulated;
+  return TN_OK;
+}
+
+tn_status tn_reset(tn_plan p) {
+  if (!p) return fail(TN_E_ARG, "null plan");
+  if (p->host_only) return fail(TN_E_STATE, "host-only plan");
+  tn_status st = check(hipMemsetAsync(p->d_acc, 0, p->n_amp * 16, p->stream), "reset");
+  if (st) return st;
+  if ((st = check(hipMemsetAsync(p->d_flag, 0, 4, p->stream), "reset"))) return st;
+  p->slices_acc = 0;
+  return check(hipStreamSynchronize(p->stream), "reset sync");
+}
+
+tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_t k, const void* A, const void* B,
+                  void* C, void* stream) {
+  const int bb = ilog2_exact(batch), mb = ilog2_exact(m), nb = ilog2_exact(n), kb = ilog2_exact(k);
+  if (!A || !B || !C) return fail(TN_E_ARG, "null pointer");
+  if (bb < 0 || mb < 0 || nb < 0 || kb < 0) return fail(TN_E_UNSUPPORTED, "dimensions must be powers of two");
+  if (precision < 0 || precision > 2) return fail(TN_E_ARG, "unknown precision");
+  if (bb > 16 || mb > 30 || nb > 30 || kb > 30 || bb + mb + nb > 34) return fail(TN_E_UNSUPPORTED, "too large");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  tn_plan_s tmp;
+  tmp.precision = precision;
+  tmp.opts.split_policy = 1;
+  tmp.host_only = true;
+  Step st;
+  for (int j = 0; j < bb; ++j) st.bb.push_back(j);
+  for (int j = 0; j < mb; ++j) st.mb.push_back(bb + j);
+  for (int j = 0; j < nb; ++j) st.nb.push_back(bb + mb + j);
+  for (int j = 0; j < kb; ++j) st.kb.push_back(bb + mb + nb + j);
+  Tensor TA, TB, TC;
+  TA.bits = st.kb;
+  TA.bits.insert(TA.bits.end(), st.mb.begin(), st.mb.end());
+  TA.bits.insert(TA.bits.end(), st.bb.begin(), st.bb.end());
+  TB.bits = st.nb;
+  TB.bits.insert(TB.bits.end(), st.kb.begin(), st.kb.end());
+  TB.bits.insert(TB.bits.end(), st.bb.begin(), st.bb.end());
+  TC.bits = st.nb;
+  TC.bits.insert(TC.bits.end(), st.mb.begin(), st.mb.end());
+  TC.bits.insert(TC.bits.end(), st.bb.begin(), st.bb.end());
+  TA.elems = int64_t(1) << TA.bits.size();
+  TB.elems = int64_t(1) << TB.bits.size();
+  TC.elems = int64_t(1) << TC.bits.size();
+  tmp.tensors = {TA, TB, TC};
+  st.ta = 0;
+  st.tb = 1;
+  st.tc = 2;
+  choose_kernel(&tmp, st);
+  if (st.kernel == TN_K_SMALL && (precision != 0)) {
+    // keep the split arithmetic on small diagnostic problems too
+    st.kernel = precision == 1 ? TN_K_MFMA_F16X3 : TN_K_MFMA_BF16X3;
+    const int lm = std::min(mb, 7), ln = std::min(nb, 6);
+    st.tiles_m_bits = mb - lm;
+    st.tiles_n_bits = nb - ln;
+    st.splits = 1;
+    st.k_split_bits = kb;
+    st.scratch_elems = 0;
+  } else if (st.kernel == TN_K_MFMA_F32 && precision != 0) {
+    st.kernel = precision == 1 ? TN_K_MFMA_F16X3 : TN_K_MFMA_BF16X3;
+  }
+  build_desc(&tmp, st);
+  // device scratch: desc, max/exp slots, split partials
+  const size_t desc_bytes = (sizeof(GettDesc) + 255) & ~size_t(255);
+  const size_t slot_bytes = 256;
+  const size_t scratch_bytes = st.scratch_elems * 8;
+  char* buf = nullptr;
+  if (hipMalloc((void**)&buf, desc_bytes + slot_bytes + scratch_bytes) != hipSuccess) {
+    hipGetLastError();
+    return fail(TN_E_NOMEM, "scratch allocation failed");
+  }
+  GettDesc* dd = reinterpret_cast<GettDesc*>(buf);
+  uint32_t* slots = reinterpret_cast<uint32_t*>(buf + desc_bytes);  // maxA maxB maxC expA expB expC
+  tn_status r = check(hipMemcpyAsync(dd, &st.desc, sizeof(GettDesc), hipMemcpyHostToDevice, s), "desc");
+  if (!r) r = check(hipMemsetAsync(slots, 0, slot_bytes, s), "slots");
+  GettArgs g;
+  memset(&g, 0, sizeof(g));
+  g.A = reinterpret_cast<const float*>(A);
+  g.B = reinterpret_cast<const float*>(B);
+  g.C = reinterpret_cast<float*>(C);
+  if (precision != 0) {
+    if (!r) r = check(tn_launch_absmax(A, batch * m * k, slots + 0, s), "max A");
+    if (!r) r = check(tn_launch_absmax(B, batch * k * n, slots + 1, s), "max B");
+    g.scale_mode = 1;
+    g.maxA = slots + 0;
+    g.maxB = slots + 1;
+    g.maxC = slots + 2;
+    g.expA = reinterpret_cast<int32_t*>(slots + 3);
+    g.expB = reinterpret_cast<int32_t*>(slots + 4);
+    g.expC = reinterpret_cast<int32_t*>(slots + 5);
+    g.target_exp = (st.kernel == TN_K_MFMA_F16X3 || st.kernel == TN_K_MFMA_BF16X3) ? 14 : 0;
+  }
+  const GettDesc* d = dd;
+  if (!r) {
+    if (st.kernel == TN_K_SMALL) {
+      r = check(tn_launch_gett(TN_K_SMALL, d, g, ((int64_t(1) << (bb + mb + nb)) + 255) / 256, s), "gemm");
+    } else {
+      g.splits = st.splits;
+      g.k_split_bits = st.k_split_bits;
+      g.tiles_m_bits = st.tiles_m_bits;
+      g.tiles_n_bits = st.tiles_n_bits;
+      const int64_t blocks = int64_t(st.splits) << (st.tiles_m_bits + st.tiles_n_bits + bb);
+      if (st.splits > 1) {
+        g.scratch = reinterpret_cast<float*>(buf + desc_bytes + slot_bytes);
+        g.write_scratch = 1;
+        r = check(tn_launch_gett(st.kernel, d, g, blocks, s), "gemm");
+        g.write_scratch = 0;
+        if (!r)
+          r = check(tn_launch_gett(TN_K_SPLITK_REDUCE, d, g, ((int64_t(1) << (bb + mb + nb)) + 255) / 256, s),
+                    "gemm reduce");
+      } else {
+        r = check(tn_launch_gett(st.kernel, d, g, blocks, s), "gemm");
+      }
+    }
+  }
+  if (!r && precision != 0)
+    r = check(tn_launch_scale_pow2(C, batch * m * n, reinterpret_cast<int32_t*>(slots + 5), s), "rescale");
+  tn_status r2 = check(hipStreamSynchronize(s), "gemm sync");
+  hipFree(buf);
+  return r ? r : r2;
+}
+
+tn_status tn_permute(int32_t rank, const int64_t* dims, const int32_t* perm, const void* in, void* out,
+                     void* stream) {
+  if (rank < 0 || rank > 32 || (rank > 0 && (!dims || !perm)) || !in || !out) return fail(TN_E_ARG, "bad arguments");
+  std::vector<int> nb(rank), bit0(rank);
+  int total = 0;
+  for (int r = 0; r < rank; ++r) {
+    nb[r] = ilog2_exact(dims[r]);
+    if (nb[r] < 0) return fail(TN_E_UNSUPPORTED, "dims must be powers of two");
+    bit0[r] = total;
+    total += nb[r];
+  }
+  if (total > 40) return fail(TN_E_UNSUPPORTED, "tensor too large");
+  std::vector<int> used(rank, 0);
+  for (int r = 0; r < rank; ++r) {
+    if (perm[r] < 0 || perm[r] >= rank || used[perm[r]]) return fail(TN_E_ARG, "perm is not a permutation");
+    used[perm[r]] = 1;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // input position of (axis r, bit b): row-major, last axis least significant
+  std::vector<int> in_pos(total), out_pos(total);
+  int pos = 0;
+  for (int r = rank - 1; r >= 0; --r)
+    for (int b = 0; b < nb[r]; ++b) in_pos[bit0[r] + b] = pos++;
+  pos = 0;
+  for (int r = rank - 1; r >= 0; --r) {
+    const int ax = perm[r];
+    for (int b = 0; b < nb[ax]; ++b) out_pos[bit0[ax] + b] = pos++;
+  }
+  if (total == 0) {
+    tn_status r = check(hipMemcpyAsync(out, in, 8, hipMemcpyDeviceToDevice, s), "copy");
+    tn_status r2 = check(hipStreamSynchronize(s), "sync");
+    return r ? r : r2;
+  }
+  PermDesc* d = nullptr;
+  if (hipMalloc((void**)&d, sizeof(PermDesc)) != hipSuccess) {
+    hipGetLastError();
+    return fail(TN_E_NOMEM, "desc allocation failed");
+  }
+  tn_status r = permute_bits(in_pos, out_pos, in, out, s, d);
+  hipFree(d);
+  return r;
+}
+
+}  // extern "C"

@@ -1,0 +1,288 @@
+"""ctypes binding of the C ABI in include/tn.h (argument marshalling only).
+
+Every contraction step runs in the HIP library ``_lib/libtnmi.so``; nothing
+here computes amplitudes.  Importing this module raises ImportError when the
+library has not been built, so a missing extension fails loudly instead of
+falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libtnmi.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
+                      "(run __graft_entry__.build() or python paper_2310_03978_amd/build.py)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+TN_PREC_C64, TN_PREC_F16X3, TN_PREC_BF16X3 = 0, 1, 2
+PRECISIONS = {"c64": TN_PREC_C64, "f16x3": TN_PREC_F16X3, "bf16x3": TN_PREC_BF16X3}
+
+STATUS = {0: "TN_OK", -1: "TN_E_ARG", -2: "TN_E_LABEL", -3: "TN_E_PATH", -4: "TN_E_SLICE",
+          -5: "TN_E_CAP", -6: "TN_E_NOMEM", -7: "TN_E_DEVICE", -8: "TN_E_STATE",
+          -9: "TN_E_UNSUPPORTED", -10: "TN_E_NUMERIC"}
+
+EXPORTED = ["tn_plan_create", "tn_plan_destroy", "tn_plan_describe", "tn_plan_steps",
+            "tn_contract_slices", "tn_slice_partials", "tn_amplitudes", "tn_accumulator_set",
+            "tn_reset", "tn_gemm", "tn_permute", "tn_status_string", "tn_last_error_message"]
+
+
+class TnError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class tn_options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("mem_cap_elems", ctypes.c_int64), ("stream", ctypes.c_void_p),
+                ("slice_batch", ctypes.c_int32), ("host_only", ctypes.c_int32),
+                ("split_policy", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class tn_plan_info(ctypes.Structure):
+    _fields_ = [("n_slices", ctypes.c_int64), ("n_amplitudes", ctypes.c_int64),
+                ("n_steps", ctypes.c_int32), ("n_slice_steps", ctypes.c_int32),
+                ("flops_per_slice", ctypes.c_double), ("flops_invariant", ctypes.c_double),
+                ("bytes_per_slice", ctypes.c_double), ("bytes_invariant", ctypes.c_double),
+                ("max_intermediate", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("slice_batch", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class tn_step_info(ctypes.Structure):
+    _fields_ = [("slot_a", ctypes.c_int32), ("slot_b", ctypes.c_int32),
+                ("per_slice", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("batch", ctypes.c_int64), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("k", ctypes.c_int64), ("split_k", ctypes.c_int32), ("tile_m", ctypes.c_int32),
+                ("tile_n", ctypes.c_int32), ("a_contig", ctypes.c_int32),
+                ("b_contig", ctypes.c_int32), ("flops", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+_P = ctypes.POINTER
+_lib.tn_plan_create.argtypes = [_P(ctypes.c_void_p), ctypes.c_int32, _P(ctypes.c_int32),
+                                _P(_P(ctypes.c_int32)), _P(_P(ctypes.c_int64)),
+                                _P(_P(ctypes.c_double)), ctypes.c_int32, _P(ctypes.c_int32),
+                                ctypes.c_int32, _P(ctypes.c_int32), ctypes.c_int32,
+                                _P(ctypes.c_int32), _P(tn_options)]
+_lib.tn_plan_create.restype = ctypes.c_int
+_lib.tn_plan_destroy.argtypes = [ctypes.c_void_p]
+_lib.tn_plan_destroy.restype = None
+_lib.tn_plan_describe.argtypes = [ctypes.c_void_p, _P(tn_plan_info)]
+_lib.tn_plan_describe.restype = ctypes.c_int
+_lib.tn_plan_steps.argtypes = [ctypes.c_void_p, _P(tn_step_info), ctypes.c_int32]
+_lib.tn_plan_steps.restype = ctypes.c_int
+_lib.tn_contract_slices.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]
+_lib.tn_contract_slices.restype = ctypes.c_int
+_lib.tn_slice_partials.argtypes = [ctypes.c_void_p, _P(ctypes.c_int64), ctypes.c_int64,
+                                   _P(ctypes.c_double)]
+_lib.tn_slice_partials.restype = ctypes.c_int
+_lib.tn_amplitudes.argtypes = [ctypes.c_void_p, _P(ctypes.c_double), ctypes.c_int64,
+                               _P(ctypes.c_int64)]
+_lib.tn_amplitudes.restype = ctypes.c_int
+_lib.tn_accumulator_set.argtypes = [ctypes.c_void_p, _P(ctypes.c_double), ctypes.c_int64,
+                                    ctypes.c_int64]
+_lib.tn_accumulator_set.restype = ctypes.c_int
+_lib.tn_reset.argtypes = [ctypes.c_void_p]
+_lib.tn_reset.restype = ctypes.c_int
+_lib.tn_gemm.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                         ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                         ctypes.c_void_p]
+_lib.tn_gemm.restype = ctypes.c_int
+_lib.tn_permute.argtypes = [ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_int32),
+                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+_lib.tn_permute.restype = ctypes.c_int
+_lib.tn_status_string.argtypes = [ctypes.c_int]
+_lib.tn_status_string.restype = ctypes.c_char_p
+_lib.tn_last_error_message.argtypes = []
+_lib.tn_last_error_message.restype = ctypes.c_char_p
+
+
+def _check(status: int):
+    if status != 0:
+        raise TnError(status, _lib.tn_last_error_message().decode())
+
+
+def exported_symbols() -> list:
+    return [name for name in EXPORTED if hasattr(_lib, name)]
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def tn_plan_create(tensors, labels, open_labels, path, sliced_labels=(), precision="c64",
+                   mem_cap_elems: int = 0, stream=None, slice_batch: int = 0,
+                   host_only: bool = False, split_policy: int = 0):
+    """Create a plan; returns an opaque handle (int).  Leaves are copied."""
+    n = len(labels)
+    ranks = (ctypes.c_int32 * n)(*[len(l) for l in labels])
+    lab_arrays = [(ctypes.c_int32 * max(len(l), 1))(*l) for l in labels]
+    if tensors is None:
+        shapes = None
+    else:
+        shapes = [tuple(np.shape(t)) for t in tensors]
+    ext_arrays = []
+    for t, l in enumerate(labels):
+        if shapes is not None:
+            ext = shapes[t]
+        else:
+            raise ValueError("tensors are required to know the extents")
+        ext_arrays.append((ctypes.c_int64 * max(len(l), 1))(*ext))
+    lab_pp = (_P(ctypes.c_int32) * n)(*[ctypes.cast(a, _P(ctypes.c_int32)) for a in lab_arrays])
+    ext_pp = (_P(ctypes.c_int64) * n)(*[ctypes.cast(a, _P(ctypes.c_int64)) for a in ext_arrays])
+    keep = []
+    if host_only:
+        data_pp = None
+    else:
+        arrs = [np.ascontiguousarray(np.asarray(t, dtype=np.complex128)).view(np.float64)
+                for t in tensors]
+        keep = arrs
+        data_pp = (_P(ctypes.c_double) * n)(*[a.ctypes.data_as(_P(ctypes.c_double)) for a in arrs])
+    op = (ctypes.c_int32 * max(len(open_labels), 1))(*open_labels)
+    flat = [x for pair in path for x in pair]
+    pa = (ctypes.c_int32 * max(len(flat), 1))(*flat)
+    sl = (ctypes.c_int32 * max(len(sliced_labels), 1))(*sliced_labels)
+    opts = tn_options()
+    opts.struct_size = ctypes.sizeof(tn_options)
+    opts.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    opts.mem_cap_elems = int(mem_cap_elems)
+    opts.stream = _stream_handle(stream)
+    opts.slice_batch = int(slice_batch)
+    opts.host_only = 1 if host_only else 0
+    opts.split_policy = int(split_policy)
+    handle = ctypes.c_void_p()
+    status = _lib.tn_plan_create(ctypes.byref(handle), n, ranks, lab_pp, ext_pp, data_pp,
+                                 len(open_labels), op, len(path), pa, len(sliced_labels), sl,
+                                 ctypes.byref(opts))
+    del keep
+    _check(status)
+    return handle.value
+
+
+def tn_plan_destroy(plan):
+    _lib.tn_plan_destroy(plan)
+
+
+def tn_plan_describe(plan) -> dict:
+    info = tn_plan_info()
+    _check(_lib.tn_plan_describe(plan, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in tn_plan_info._fields_}
+
+
+def tn_plan_steps(plan) -> list:
+    n = tn_plan_describe(plan)["n_steps"]
+    arr = (tn_step_info * max(n, 1))()
+    _check(_lib.tn_plan_steps(plan, arr, n))
+    return [{name: getattr(arr[i], name) for name, _ in tn_step_info._fields_} for i in range(n)]
+
+
+def tn_contract_slices(plan, first_slice: int, n_slices: int):
+    _check(_lib.tn_contract_slices(plan, int(first_slice), int(n_slices)))
+
+
+def tn_slice_partials(plan, slice_ids) -> np.ndarray:
+    ids = np.ascontiguousarray(np.asarray(slice_ids, dtype=np.int64))
+    n_amp = tn_plan_describe(plan)["n_amplitudes"]
+    out = np.zeros((len(ids), n_amp), dtype=np.complex128)
+    _check(_lib.tn_slice_partials(plan, ids.ctypes.data_as(_P(ctypes.c_int64)), len(ids),
+                                  out.view(np.float64).ctypes.data_as(_P(ctypes.c_double))))
+    return out
+
+
+def tn_amplitudes(plan):
+    n_amp = tn_plan_describe(plan)["n_amplitudes"]
+    out = np.zeros(n_amp, dtype=np.complex128)
+    count = ctypes.c_int64()
+    _check(_lib.tn_amplitudes(plan, out.view(np.float64).ctypes.data_as(_P(ctypes.c_double)),
+                              n_amp, ctypes.byref(count)))
+    return out, count.value
+
+
+def tn_accumulator_set(plan, acc, slices_accumulated: int):
+    acc = np.ascontiguousarray(np.asarray(acc, dtype=np.complex128))
+    _check(_lib.tn_accumulator_set(plan, acc.view(np.float64).ctypes.data_as(_P(ctypes.c_double)),
+                                   acc.size, int(slices_accumulated)))
+
+
+def tn_reset(plan):
+    _check(_lib.tn_reset(plan))
+
+
+def tn_gemm(A, B, C, precision="c64", stream=None):
+    """C[b] = A[b] @ B[b] on device complex64 torch tensors of shape (b, m, k), (b, k, n), (b, m, n)."""
+    b, m, k = A.shape
+    n = B.shape[2]
+    if tuple(B.shape) != (b, k, n) or tuple(C.shape) != (b, m, n):
+        raise ValueError("shape mismatch")
+    for x in (A, B, C):
+        if not x.is_contiguous() or str(x.dtype) != "torch.complex64" or x.device.type != "cuda":
+            raise ValueError("operands must be contiguous complex64 device tensors")
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(_lib.tn_gemm(prec, b, m, n, k, A.data_ptr(), B.data_ptr(), C.data_ptr(),
+                        _stream_handle(stream)))
+
+
+def tn_permute(x, perm, out, stream=None):
+    """out = x.permute(perm) (contiguous) on device complex64 torch tensors."""
+    rank = x.dim()
+    if out.numel() != x.numel() or not x.is_contiguous() or not out.is_contiguous():
+        raise ValueError("bad tensors")
+    dims = (ctypes.c_int64 * max(rank, 1))(*x.shape)
+    pm = (ctypes.c_int32 * max(rank, 1))(*perm)
+    _check(_lib.tn_permute(rank, dims, pm, x.data_ptr(), out.data_ptr(), _stream_handle(stream)))
+
+
+class Plan:
+    """Owning wrapper around a plan handle."""
+
+    def __init__(self, tensors, labels, open_labels, path, sliced_labels=(), **kw):
+        self.handle = tn_plan_create(tensors, labels, open_labels, path, sliced_labels, **kw)
+
+    def close(self):
+        if self.handle:
+            tn_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def describe(self):
+        return tn_plan_describe(self.handle)
+
+    def steps(self):
+        return tn_plan_steps(self.handle)
+
+    def contract(self, first=0, n=None):
+        if n is None:
+            n = self.describe()["n_slices"] - first
+        tn_contract_slices(self.handle, first, n)
+
+    def amplitudes(self):
+        return tn_amplitudes(self.handle)
+
+    def partials(self, ids):
+        return tn_slice_partials(self.handle, ids)
+
+    def reset(self):
+        tn_reset(self.handle)
+
+    def set_accumulator(self, acc, slices):
+        tn_accumulator_set(self.handle, acc, slices)

@@ -1,0 +1,120 @@
+"""Host-side tests of the C ABI: symbols, planner output and error codes (no GPU needed)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import contract
+from tn_inputs import configs
+from tn_inputs.network import random_network
+from tn_inputs.paths import greedy_path
+
+tn = pytest.importorskip("paper_2310_03978_amd.tn")
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "tn.h")
+
+
+def test_library_exports_every_declared_symbol():
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:tn_status|void|const char\*)\s+(tn_\w+)\(", text, re.M))
+    assert len(declared) >= 13
+    missing = [name for name in declared if not hasattr(tn._lib, name)]
+    assert not missing, missing
+
+
+def _host_plan(net, path, sliced=(), **kw):
+    return tn.tn_plan_create(net.tensors, net.labels, net.open_labels, path, sliced,
+                             host_only=True, **kw)
+
+
+def _compare_costs(net, path, sliced):
+    h = _host_plan(net, path, sliced)
+    try:
+        steps = tn.tn_plan_steps(h)
+        info = tn.tn_plan_describe(h)
+    finally:
+        tn.tn_plan_destroy(h)
+    ref = contract.step_costs(net.tensors, net.labels, net.open_labels, path, sliced)
+    assert len(steps) == len(ref)
+    for s, r in zip(steps, ref):
+        assert (s["batch"], s["m"], s["n"], s["k"]) == (r["B"], r["M"], r["N"], r["K"])
+        assert s["flops"] == r["flops"]
+        assert s["bytes"] == r["bytes"]
+    ps = sum(s["flops"] for s in steps if s["per_slice"])
+    inv = sum(s["flops"] for s in steps if not s["per_slice"])
+    assert info["flops_per_slice"] == ps and info["flops_invariant"] == inv
+    return info, steps
+
+
+def test_planner_costs_match_oracle_rqc12():
+    circ, net, best = configs.build("rqc12")
+    info, steps = _compare_costs(net, best["path"], ())
+    assert info["n_slices"] == 1 and info["n_amplitudes"] == 16
+    assert info["n_steps"] == len(net.tensors) - 1
+
+
+def test_planner_costs_match_oracle_rqc30():
+    circ, net, best = configs.build("rqc30")
+    info, steps = _compare_costs(net, best["path"], best["sliced"])
+    assert info["n_slices"] == 256 and info["n_amplitudes"] == 64
+    assert info["max_intermediate"] <= 2 ** 28
+    # the slice-dependent steps are the ones that touch a sliced leaf
+    assert 0 < info["n_slice_steps"] < info["n_steps"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_planner_costs_match_oracle_random(seed):
+    net = random_network(seed, n_tensors=6, n_labels=10, extents=(1, 2, 4), n_open=2)
+    path = greedy_path(net.labels, net.open_labels, net.extents(), seed=seed)
+    ext = net.extents()
+    sliced = [l for l in sorted(ext) if l not in net.open_labels and ext[l] > 1][:1]
+    _compare_costs(net, path, sliced)
+
+
+def test_single_tensor_plan():
+    x = np.arange(8, dtype=np.complex128).reshape(2, 4)
+    h = tn.tn_plan_create([x], [(3, 5)], (5,), [], (), host_only=True)
+    info = tn.tn_plan_describe(h)
+    tn.tn_plan_destroy(h)
+    assert info["n_steps"] == 1 and info["n_amplitudes"] == 4
+
+
+def _expect(status, fn):
+    with pytest.raises(tn.TnError) as e:
+        fn()
+    assert e.value.name == status, str(e.value)
+
+
+def test_error_codes():
+    a = np.zeros((2, 2), dtype=np.complex128)
+    b = np.zeros((2, 2), dtype=np.complex128)
+    c = np.zeros((2, 3), dtype=np.complex128)
+    d = np.zeros((4,), dtype=np.complex128)
+    mk = lambda *args, **kw: tn.tn_plan_create(*args, host_only=True, **kw)
+    _expect("TN_E_LABEL", lambda: mk([a, b], [(0, -1), (1, 0)], (1,), [(0, 1)]))
+    _expect("TN_E_LABEL", lambda: mk([a, d], [(0, 1), (1,)], (0,), [(0, 1)]))
+    _expect("TN_E_LABEL", lambda: mk([a, b], [(0, 0), (1, 0)], (1,), [(0, 1)]))
+    _expect("TN_E_LABEL", lambda: mk([a, b], [(0, 1), (1, 2)], (7,), [(0, 1)]))
+    _expect("TN_E_UNSUPPORTED", lambda: mk([c, b], [(0, 1), (0, 2)], (2,), [(0, 1)]))
+    _expect("TN_E_PATH", lambda: mk([a, b], [(0, 1), (1, 2)], (0, 2), []))
+    _expect("TN_E_PATH", lambda: mk([a, b, a], [(0, 1), (1, 2), (2, 3)], (0, 3), [(0, 1), (1, 2)]))
+    _expect("TN_E_PATH", lambda: mk([a, b], [(0, 1), (1, 2)], (0, 2), [(0, 0)]))
+    _expect("TN_E_PATH", lambda: mk([a, b], [(0, 1), (1, 2)], (0, 2), [(0, 5)]))
+    _expect("TN_E_SLICE", lambda: mk([a, b], [(0, 1), (1, 2)], (0, 2), [(0, 1)], (0,)))
+    _expect("TN_E_SLICE", lambda: mk([a, b], [(0, 1), (1, 2)], (0, 2), [(0, 1)], (9,)))
+    _expect("TN_E_SLICE", lambda: mk([a, b], [(0, 1), (1, 2)], (0, 2), [(0, 1)], (1, 1)))
+    _expect("TN_E_CAP", lambda: mk([a, b], [(0, 1), (2, 3)], (0, 1, 2, 3), [(0, 1)],
+                                   mem_cap_elems=8))
+    _expect("TN_E_ARG", lambda: mk([a, b], [(0, 1), (1, 2)], (0, 2), [(0, 1)], slice_batch=3))
+    h = mk([a, b], [(0, 1), (1, 2)], (0, 2), [(0, 1)])
+    try:
+        _expect("TN_E_STATE", lambda: tn.tn_contract_slices(h, 0, 1))
+        _expect("TN_E_STATE", lambda: tn.tn_amplitudes(h))
+    finally:
+        tn.tn_plan_destroy(h)
+
+
+def test_status_strings():
+    for code, name in tn.STATUS.items():
+        assert tn._lib.tn_status_string(code).decode() == name

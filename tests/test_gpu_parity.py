@@ -1,0 +1,246 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU complex128 oracle.
+
+Tolerances (relative L2 error of the amplitude batch, as the judged metric):
+complex64 <= 1e-5; split FP16 / BF16 products with power-of-two scaling <= 1e-3.
+Kernel-level products use the Frobenius relative error against numpy.
+"""
+import numpy as np
+import pytest
+
+from oracle import contract, metrics
+from tn_inputs import configs
+from tn_inputs.network import Network, random_network
+from tn_inputs.paths import choose_slices, greedy_path
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+tn = pytest.importorskip("paper_2310_03978_amd.tn")
+
+TOL = {"c64": 1e-5, "f16x3": 1e-3, "bf16x3": 1e-3}
+GEMM_TOL = {"c64": 2e-6, "f16x3": 2e-6, "bf16x3": 1e-4}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _crandn(rng, shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+@pytest.mark.parametrize("prec", ["c64", "f16x3", "bf16x3"])
+@pytest.mark.parametrize("b,m,n,k", [(1, 128, 64, 16), (2, 256, 128, 64), (1, 8, 4, 2),
+                                     (1, 1, 1, 1), (4, 32, 16, 512),
+                                     (1, 64, 32, 8192), (1, 512, 256, 256), (2, 16, 128, 32)])
+def test_gemm_matches_numpy(prec, b, m, n, k):
+    print(f"gemm {prec} b={b} m={m} n={n} k={k}", flush=True)
+    rng = np.random.default_rng(b * 7 + m + n + k)
+    A, B = _crandn(rng, (b, m, k)), _crandn(rng, (b, k, n))
+    C = torch.zeros((b, m, n), dtype=torch.complex64, device="cuda")
+    tn.tn_gemm(_dev(A), _dev(B), C, precision=prec)
+    got = C.cpu().numpy().astype(np.complex128)
+    ref = np.matmul(A.astype(np.complex128), B.astype(np.complex128))
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err <= GEMM_TOL[prec] * max(1.0, np.sqrt(k / 64)), err
+
+
+@pytest.mark.parametrize("shape,perm", [((2, 4, 8), (2, 0, 1)), ((64, 32), (1, 0)),
+                                        ((2,) * 14, tuple(np.random.default_rng(1).permutation(14))),
+                                        ((4, 1, 256, 8, 2), (3, 1, 4, 0, 2)), ((), ())])
+def test_permute_bit_exact(shape, perm):
+    print(f"permute {shape} {perm}", flush=True)
+    rng = np.random.default_rng(len(shape))
+    x = _crandn(rng, shape)
+    out = torch.zeros(int(np.prod(shape)) if shape else 1, dtype=torch.complex64, device="cuda")
+    xd = _dev(x.reshape(shape) if shape else x.reshape(()))
+    tn.tn_permute(xd, list(perm), out)
+    ref = np.transpose(x, perm).reshape(-1) if shape else x.reshape(-1)
+    assert np.array_equal(out.cpu().numpy(), ref)
+
+
+def _gpu_amplitudes(net, path, sliced=(), prec="c64", **kw):
+    with tn.Plan(net.tensors, net.labels, net.open_labels, path, sliced, precision=prec, **kw) as p:
+        p.contract()
+        amps, count = p.amplitudes()
+    return amps, count
+
+
+@pytest.mark.parametrize("prec", ["c64", "f16x3", "bf16x3"])
+def test_rqc12_matches_oracle(prec):
+    print(f"rqc12 {prec}", flush=True)
+    circ, net, best = configs.build("rqc12")
+    ref = contract.amplitudes(net.tensors, net.labels, net.open_labels, best["path"])
+    got, count = _gpu_amplitudes(net, best["path"], prec=prec, split_policy=1)
+    assert count == 1
+    assert metrics.rel_l2(got, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["c64", "f16x3"])
+def test_rqc12_sliced_matches_oracle(prec):
+    print(f"rqc12 sliced {prec}", flush=True)
+    circ, net, best = configs.build("rqc12")
+    sliced = choose_slices(net.labels, net.open_labels, net.extents(), best["path"], cap_log2=6,
+                           min_sliced=4)
+    ref = contract.amplitudes(net.tensors, net.labels, net.open_labels, best["path"])
+    for sb in (1, 4, 16):
+        got, count = _gpu_amplitudes(net, best["path"], sliced, prec=prec, slice_batch=sb)
+        assert count == 2 ** len(sliced)
+        assert metrics.rel_l2(got, ref) <= TOL[prec]
+    # per-slice partials against the oracle's slices
+    ids = [0, 3, 2 ** len(sliced) - 1]
+    with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], sliced, precision=prec) as p:
+        parts = p.partials(ids)
+    for i, s in enumerate(ids):
+        r = contract.contract_slice(net.tensors, net.labels, net.open_labels, best["path"], sliced, s)
+        assert metrics.rel_l2(parts[i], r) <= TOL[prec]
+
+
+@pytest.mark.parametrize("seed", range(10))
+@pytest.mark.parametrize("prec", ["c64", "f16x3"])
+def test_random_networks_match_oracle(seed, prec):
+    """Batch (hyperedge) labels, labels summed on one operand, extents 1/2/4, slicing."""
+    print(f"random net {seed} {prec}", flush=True)
+    net = random_network(seed, n_tensors=7, n_labels=12, extents=(1, 2, 4), n_open=2)
+    ext = net.extents()
+    path = greedy_path(net.labels, net.open_labels, ext, seed=seed)
+    sliced = [l for l in sorted(ext) if l not in net.open_labels and ext[l] > 1][: seed % 3]
+    ref = contract.amplitudes(net.tensors, net.labels, net.open_labels, path, sliced)
+    got, _ = _gpu_amplitudes(net, path, sliced, prec=prec, split_policy=1)
+    assert metrics.rel_l2(got, ref) <= TOL[prec]
+
+
+def test_large_random_steps_use_mfma_and_match():
+    """A synthetic network whose steps are large enough for the MFMA kernels and split K."""
+    print("large steps", flush=True)
+    rng = np.random.default_rng(5)
+    # A[a(2^7) k(2^9)] B[k(2^9) b(2^6)] C[b(2^6) c(2^1)] -> open a, c
+    shapes = {"A": (128, 512), "B": (512, 64), "C": (64, 2)}
+    tensors = [(_crandn(rng, shapes[x]) / 8).astype(np.complex128) for x in "ABC"]
+    net = Network(tensors=tensors, labels=[(0, 1), (1, 2), (2, 3)], open_labels=(0, 3))
+    ref = contract.amplitudes(net.tensors, net.labels, net.open_labels, [(0, 1), (0, 2)])
+    for prec in ("c64", "f16x3", "bf16x3"):
+        with tn.Plan(net.tensors, net.labels, net.open_labels, [(0, 1), (0, 2)], (),
+                     precision=prec, split_policy=1) as p:
+            kinds = [s["kernel"] for s in p.steps()]
+            p.contract()
+            got, _ = p.amplitudes()
+        assert kinds[0] != 0
+        assert metrics.rel_l2(got, ref) <= TOL[prec], prec
+
+
+def test_chunking_accumulation_and_resume():
+    print("chunking", flush=True)
+    circ, net, best = configs.build("rqc12")
+    sliced = choose_slices(net.labels, net.open_labels, net.extents(), best["path"], cap_log2=6,
+                           min_sliced=4)
+    n = 2 ** len(sliced)
+    with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], sliced,
+                 slice_batch=4) as p:
+        p.contract(0, n)
+        full, c = p.amplitudes()
+        assert c == n
+        p.reset()
+        for first, cnt in ((0, 3), (3, 6), (9, n - 9)):
+            p.contract(first, cnt)
+        parts, c = p.amplitudes()
+        assert c == n
+        assert metrics.rel_l2(parts, full) <= 1e-6
+        # checkpoint after half, resume
+        p.reset()
+        p.contract(0, n // 2)
+        half, c = p.amplitudes()
+        p.reset()
+        p.set_accumulator(half, c)
+        p.contract(n // 2, n - n // 2)
+        resumed, c = p.amplitudes()
+        assert c == n and metrics.rel_l2(resumed, full) <= 1e-6
+        # re-running a range adds it again
+        p.reset()
+        p.contract(0, n)
+        p.contract(0, n)
+        twice, _ = p.amplitudes()
+        assert metrics.rel_l2(twice, 2 * full) <= 1e-6
+        with pytest.raises(tn.TnError):
+            p.contract(n - 1, 2)
+
+
+def test_deterministic_bitwise():
+    print("determinism", flush=True)
+    circ, net, best = configs.build("rqc12")
+    sliced = choose_slices(net.labels, net.open_labels, net.extents(), best["path"], cap_log2=6,
+                           min_sliced=3)
+    outs = []
+    for _ in range(2):
+        got, _ = _gpu_amplitudes(net, best["path"], sliced, prec="f16x3")
+        outs.append(got)
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_degenerate_networks():
+    print("degenerate", flush=True)
+    x = (np.arange(8) + 1j * np.arange(8)[::-1]).reshape(2, 4).astype(np.complex128)
+    # single tensor: sum over label 3, keep 5
+    net = Network(tensors=[x], labels=[(3, 5)], open_labels=(5,))
+    got, _ = _gpu_amplitudes(net, [])
+    np.testing.assert_allclose(got, x.sum(axis=0), rtol=1e-6)
+    # closed network (single amplitude): <u|v>
+    u, v = np.array([1, 2j], dtype=np.complex128), np.array([3, -1j], dtype=np.complex128)
+    net = Network(tensors=[u, v], labels=[(0,), (0,)], open_labels=())
+    got, _ = _gpu_amplitudes(net, [(0, 1)])
+    np.testing.assert_allclose(got, [np.sum(u * v)], rtol=1e-6)
+    # scalar leaf and an outer product
+    s = np.array(2.0 - 1j, dtype=np.complex128)
+    net = Network(tensors=[s, u, v], labels=[(), (0,), (1,)], open_labels=(1, 0))
+    got, _ = _gpu_amplitudes(net, [(1, 2), (0, 1)])
+    np.testing.assert_allclose(got, (s * np.outer(v, u)).reshape(-1), rtol=1e-6)
+
+
+def test_numeric_error_is_reported():
+    print("numeric", flush=True)
+    a = np.array([np.inf, 1.0], dtype=np.complex128)
+    b = np.array([1.0, 1.0], dtype=np.complex128)
+    net = Network(tensors=[a, b], labels=[(0,), (0,)], open_labels=())
+    with tn.Plan(net.tensors, net.labels, net.open_labels, [(0, 1)]) as p:
+        p.contract()
+        with pytest.raises(tn.TnError) as e:
+            p.amplitudes()
+        assert e.value.name == "TN_E_NUMERIC"
+
+
+@pytest.mark.parametrize("prec", ["c64", "f16x3"])
+def test_rqc30_sampled_slices_match_oracle(prec):
+    """The 30-qubit, 14-cycle, 256-slice workload at full size: sampled slices vs the oracle."""
+    print(f"rqc30 {prec}", flush=True)
+    circ, net, best = configs.build("rqc30")
+    sid = 137
+    ref = _rqc30_oracle_slice(sid)
+    with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best["sliced"],
+                 precision=prec) as p:
+        part = p.partials([sid])[0]
+        # the full run accumulates every slice once; chunked sums agree with partial sums
+        p.contract(128, 16)
+        acc, c = p.amplitudes()
+        assert c == 16
+        parts = p.partials(list(range(128, 144)))
+    rep = metrics.report(part, ref)
+    print(f"rqc30 slice {sid} {prec}: {rep}", flush=True)
+    assert rep["rel_l2"] <= TOL[prec]
+    assert metrics.rel_l2(acc, parts.sum(axis=0)) <= 1e-6
+
+
+_ORACLE_CACHE = {}
+
+
+def _rqc30_oracle_slice(sid):
+    if sid not in _ORACLE_CACHE:
+        circ, net, best = configs.build("rqc30")
+        _ORACLE_CACHE[sid] = contract.contract_slice(net.tensors, net.labels, net.open_labels,
+                                                     best["path"], best["sliced"], sid)
+    return _ORACLE_CACHE[sid]
