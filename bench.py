@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Sliced-contraction benchmark on one MI355X.
+
+Workload (default ``rqc30``): the 30-qubit 5x6-lattice random circuit with 14
+cycles, 6 open qubits (64 correlated amplitudes) and 8 sliced bonds (256
+slices, largest intermediate <= 2^28), on synthetic seeded inputs.  One
+benchmark step is one tn_contract_slices call over all 256 slices: the
+slice-independent steps, every slice-dependent step of every slice and the
+FP64 cross-slice sum.  Inputs are resident on the GPU before timing starts.
+
+Prints ONE JSON line with the split-FP16 throughput as ``value`` (TFLOPS,
+algorithmic: 8 real flops per complex multiply-add) and the complex64 run
+beside it, the roofline of the dominant kernel (its launches timed with HIP
+events on the plan's stream inside the timed region) and the CPU oracle timed
+on one slice of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"f16x3": ("mfma", 2500.0, "fp16 MFMA"), "bf16x3": ("mfma", 2500.0, "bf16 MFMA"),
+        "c64": ("mfma", 157.3, "fp32 MFMA")}
+KERNEL_NAME = {0: "k_gett_small", 1: "k_gett_mfma<0>", 2: "k_gett_mfma<1>", 3: "k_gett_mfma<2>"}
+PRODUCTS = {0: 1, 1: 1, 2: 3, 3: 3}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_precision(tn, torch, net, best, prec, steps, warmup, sample_slice):
+    stream = torch.cuda.current_stream()
+    plan = tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best["sliced"],
+                   precision=prec, stream=stream, record_steps=True)
+    info = plan.describe()
+    st = plan.steps()
+    n_slices = info["n_slices"]
+    for _ in range(warmup):
+        plan.contract(0, n_slices)
+    torch.cuda.synchronize()
+    plan.step_times()          # clear warm-up records
+    plan.reset()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        plan.contract(0, n_slices)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = start.elapsed_time(end) / steps
+    step_ms, launches = plan.step_times()
+    amps, count = plan.amplitudes()
+    assert count == steps * n_slices
+    amps = amps / steps
+    part = plan.partials([sample_slice])[0]
+    plan.close()
+    flops_step = info["flops_invariant"] + n_slices * info["flops_per_slice"]
+    # per kernel kind: total algorithmic flops and measured time in the timed region
+    by_kind = {}
+    for s, ms, nl in zip(st, step_ms, launches):
+        reps = steps * (n_slices if s["per_slice"] else 1)
+        d = by_kind.setdefault(s["kernel"], {"ms": 0.0, "flops": 0.0, "launches": 0})
+        d["ms"] += float(ms)
+        d["flops"] += s["flops"] * reps
+        d["launches"] += int(nl)
+    return {"info": info, "ms_per_step": ms_per_step, "flops_step": flops_step,
+            "tflops": flops_step / (ms_per_step * 1e-3) / 1e12,
+            "slices_per_s": n_slices / (ms_per_step * 1e-3),
+            "by_kind": by_kind, "amps": amps, "partial": part}
+
+
+def cpu_baseline(net, best, sample_slice, flops_slice):
+    from oracle import contract
+    threads = os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [x.get("num_threads", 0) for x in threadpool_info() if x.get("user_api") == "blas"]
+        if blas:
+            threads = max(blas)
+    except Exception:
+        pass
+    t0 = time.perf_counter()
+    ref = contract.contract_slice(net.tensors, net.labels, net.open_labels, best["path"],
+                                  best["sliced"], sample_slice)
+    dt = time.perf_counter() - t0
+    return ref, {"value": flops_slice / dt / 1e12, "unit": "TFLOPS", "cores": threads,
+                 "kind": "oracle", "slices_per_s": 1.0 / dt, "seconds": dt,
+                 "sample": f"1 slice (id {sample_slice}) of the same workload, complex128 numpy "
+                           f"tensordot along the same path; flops counted as for the GPU"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rqc30")
+    ap.add_argument("--precisions", default="f16x3,c64")
+    ap.add_argument("--sample-slice", type=int, default=137)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: slices are independent sub-tasks and the "
+              "multi-GPU sum of partial amplitudes is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    from oracle import metrics
+    from paper_2310_03978_amd import tn
+    from tn_inputs import configs
+
+    t0 = time.perf_counter()
+    circ, net, best = configs.build(args.workload)
+    w = configs.WORKLOADS[args.workload]
+    log(f"workload {args.workload}: {w.description}; path found in {time.perf_counter() - t0:.1f}s")
+    precs = [p for p in args.precisions.split(",") if p]
+    runs = {}
+    for prec in precs:
+        log(f"running {prec}: warmup {args.warmup}, steps {args.steps}")
+        runs[prec] = run_precision(tn, torch, net, best, prec, args.steps, args.warmup,
+                                   args.sample_slice)
+        r = runs[prec]
+        log(f"  {prec}: {r['ms_per_step']:.1f} ms/step, {r['tflops']:.1f} TFLOPS, "
+            f"{r['slices_per_s']:.1f} slices/s")
+    head = precs[0]
+    main_run = runs[head]
+    info = main_run["info"]
+
+    # roofline of the dominant kernel (most measured time) of the headline run
+    kinds = main_run["by_kind"]
+    dom = max(kinds, key=lambda k: kinds[k]["ms"])
+    dk = kinds[dom]
+    achieved = dk["flops"] / (dk["ms"] * 1e-3) / 1e12
+    bound, peak, peak_name = PEAK[head] if dom != 0 else ("alu", 78.6, "fp32 vector")
+    roof = {"bound": bound, "kernel": KERNEL_NAME[dom], "achieved": round(achieved, 2),
+            "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "launches": dk["launches"], "avg_launch_ms": round(dk["ms"] / max(dk["launches"], 1), 4),
+            "flops_per_launch": dk["flops"] / max(dk["launches"], 1),
+            "time_share": round(dk["ms"] / sum(v["ms"] for v in kinds.values()), 4),
+            "peak_dtype": peak_name}
+    if PRODUCTS[dom] > 1:
+        roof["executed_mfma_tflops"] = round(achieved * PRODUCTS[dom], 2)
+        roof["executed_frac"] = round(achieved * PRODUCTS[dom] / peak, 4)
+
+    out = {"metric": "sliced-contraction TFLOPS & slices/s, FP16-scaled vs complex64, <=1e-3 amp err",
+           "value": round(main_run["tflops"], 3), "unit": "TFLOPS", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(main_run["ms_per_step"], 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": head, "data": "synthetic",
+           "config": {"workload": f"{args.workload}: {w.description}",
+                      "n_slices": info["n_slices"], "n_amplitudes": info["n_amplitudes"],
+                      "flops_per_step": main_run["flops_step"],
+                      "max_intermediate": info["max_intermediate"],
+                      "slice_batch": info["slice_batch"], "precision": head},
+           "slices_per_s": round(main_run["slices_per_s"], 2)}
+    for prec, r in runs.items():
+        out[prec] = {"tflops": round(r["tflops"], 3), "slices_per_s": round(r["slices_per_s"], 2),
+                     "ms_per_step": round(r["ms_per_step"], 3)}
+    if "c64" in runs and head != "c64":
+        out["speedup_vs_c64"] = round(runs["c64"]["ms_per_step"] / main_run["ms_per_step"], 3)
+        out["rel_l2_vs_c64_full"] = metrics.rel_l2(main_run["amps"], runs["c64"]["amps"])
+    out["roofline"] = roof
+    if not args.no_cpu_baseline:
+        ref, cb = cpu_baseline(net, best, args.sample_slice,
+                               info["flops_per_slice"] + info["flops_invariant"])
+        out["cpu_baseline"] = cb
+        for prec, r in runs.items():
+            out[prec]["rel_l2_vs_oracle_slice"] = metrics.rel_l2(r["partial"], ref)
+            out[prec]["fidelity_vs_oracle_slice"] = metrics.fidelity(r["partial"], ref)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

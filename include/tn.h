@@ -73,7 +73,9 @@ typedef struct {
                               calls return TN_E_STATE and no device memory is touched */
   int32_t split_policy;    /* 0 = split products on steps that are MFMA-bound, FP32 elsewhere;
                               1 = split products on every MFMA step */
-  int32_t reserved[7];
+  int32_t record_steps;    /* 1 = time every step's main kernel launch with HIP events on the
+                              plan's stream (read with tn_plan_step_times) */
+  int32_t reserved[6];
 } tn_options;
 
 /* Plan summary.  Operation counts follow Sec. 2.4: flops = 8*B*M*N*K per step
@@ -139,6 +141,13 @@ tn_status tn_plan_describe(tn_plan plan, tn_plan_info* out);
 
 /* Copy min(cap, n_steps) step records into steps[] (host memory). */
 tn_status tn_plan_steps(tn_plan plan, tn_step_info* steps, int32_t cap);
+
+/* Per-step kernel times recorded since the last call (options.record_steps = 1):
+ * synchronises the stream, then writes for step i < cap the summed duration in
+ * milliseconds of its main kernel launches (ms_total[i], may be NULL) and their
+ * number (launches[i], may be NULL), and clears the record.  Split-K reduction
+ * launches are not included.  TN_E_STATE if recording is off. */
+tn_status tn_plan_step_times(tn_plan plan, double* ms_total, int64_t* launches, int32_t cap);
 
 /* Contract slices [first_slice, first_slice + n_slices) and ADD their amplitudes into the
  * plan's FP64 accumulator, summing in increasing slice id (Sec. 3.2, Sec. 5: sub-task

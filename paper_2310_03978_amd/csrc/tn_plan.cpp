@@ -174,12 +174,27 @@ struct tn_plan_s {
   int64_t slices_acc = 0;
   size_t device_bytes = 0;
 
+  // step timing (options.record_steps)
+  struct Timing {
+    int step;
+    hipEvent_t start, stop;
+  };
+  std::vector<Timing> pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
+  std::vector<double> step_ms;
+  std::vector<int64_t> step_launches;
+
   ~tn_plan_s() {
     if (stream) hipStreamSynchronize(stream);
     else if (!host_only) hipDeviceSynchronize();
     void* ptrs[] = {d_leaves, d_inv, d_ps, d_desc, d_max_inv, d_max_ps, d_exp_inv, d_exp_ps, d_acc, d_part, d_flag};
     for (void* p : ptrs)
       if (p) hipFree(p);
+    for (auto& t : pending) event_pool.push_back({t.start, t.stop});
+    for (auto& e : event_pool) {
+      hipEventDestroy(e.first);
+      hipEventDestroy(e.second);
+    }
   }
 };
 
@@ -815,6 +830,25 @@ int64_t leaf_chunk_offset(const tn_plan_s* p, const Tensor& T, int64_t base, int
   return off;
 }
 
+tn_status timed_launch(tn_plan_s* p, int s, int kind, const GettDesc* d, const GettArgs& g, int64_t blocks,
+                       const char* what) {
+  if (!p->opts.record_steps) return check(tn_launch_gett(kind, d, g, blocks, p->stream), what);
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  if (!p->event_pool.empty()) {
+    ev = p->event_pool.back();
+    p->event_pool.pop_back();
+  } else {
+    tn_status st = check(hipEventCreate(&ev.first), "event create");
+    if (!st) st = check(hipEventCreate(&ev.second), "event create");
+    if (st) return st;
+  }
+  tn_status st = check(hipEventRecord(ev.first, p->stream), "event record");
+  if (!st) st = check(tn_launch_gett(kind, d, g, blocks, p->stream), what);
+  if (!st) st = check(hipEventRecord(ev.second, p->stream), "event record");
+  p->pending.push_back({s, ev.first, ev.second});
+  return st;
+}
+
 tn_status run_step(tn_plan_s* p, int s, int64_t chunk_base, int chunk_bits) {
   Step& st = p->steps[s];
   const Tensor& A = p->tensors[st.ta];
@@ -853,7 +887,7 @@ tn_status run_step(tn_plan_s* p, int s, int64_t chunk_base, int chunk_bits) {
   const int bbits = (int)st.bb.size() + g.chunk_bits;
   if (st.kernel == TN_K_SMALL) {
     const int64_t total = int64_t(1) << (C.bits.size() + g.chunk_bits);
-    return check(tn_launch_gett(TN_K_SMALL, d, g, (total + 255) / 256, p->stream), "small step");
+    return timed_launch(p, s, TN_K_SMALL, d, g, (total + 255) / 256, "small step");
   }
   g.splits = st.splits;
   g.k_split_bits = st.k_split_bits;
@@ -864,13 +898,13 @@ tn_status run_step(tn_plan_s* p, int s, int64_t chunk_base, int chunk_bits) {
     float* base = st.per_slice ? p->d_ps : p->d_inv;
     g.scratch = base + 2 * st.scratch_off;
     g.write_scratch = 1;
-    tn_status r = check(tn_launch_gett(st.kernel, d, g, blocks, p->stream), "mfma step");
+    tn_status r = timed_launch(p, s, st.kernel, d, g, blocks, "mfma step");
     if (r) return r;
     g.write_scratch = 0;
     const int64_t total = int64_t(1) << (C.bits.size() + g.chunk_bits);
     return check(tn_launch_gett(TN_K_SPLITK_REDUCE, d, g, (total + 255) / 256, p->stream), "split-K reduce");
   }
-  return check(tn_launch_gett(st.kernel, d, g, blocks, p->stream), "mfma step");
+  return timed_launch(p, s, st.kernel, d, g, blocks, "mfma step");
 }
 
 tn_status run_invariant(tn_plan_s* p) {
@@ -1008,6 +1042,32 @@ tn_status tn_plan_steps(tn_plan p, tn_step_info* steps, int32_t cap) {
     o.flops = st.flops;
     o.bytes = st.bytes;
   }
+  return TN_OK;
+}
+
+tn_status tn_plan_step_times(tn_plan p, double* ms_total, int64_t* launches, int32_t cap) {
+  if (!p || cap < 0) return fail(TN_E_ARG, "bad arguments");
+  if (p->host_only || !p->opts.record_steps) return fail(TN_E_STATE, "step recording is off");
+  tn_status st = check(hipStreamSynchronize(p->stream), "stream sync");
+  if (st) return st;
+  p->step_ms.resize(p->steps.size(), 0.0);
+  p->step_launches.resize(p->steps.size(), 0);
+  for (auto& t : p->pending) {
+    float ms = 0.f;
+    if (!st) st = check(hipEventElapsedTime(&ms, t.start, t.stop), "event elapsed");
+    p->step_ms[t.step] += ms;
+    p->step_launches[t.step] += 1;
+    p->event_pool.push_back({t.start, t.stop});
+  }
+  p->pending.clear();
+  if (st) return st;
+  const int n = std::min<int>(cap, (int)p->steps.size());
+  for (int i = 0; i < n; ++i) {
+    if (ms_total) ms_total[i] = p->step_ms[i];
+    if (launches) launches[i] = p->step_launches[i];
+  }
+  std::fill(p->step_ms.begin(), p->step_ms.end(), 0.0);
+  std::fill(p->step_launches.begin(), p->step_launches.end(), 0);
   return TN_OK;
 }
 

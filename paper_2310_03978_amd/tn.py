@@ -29,7 +29,7 @@ STATUS = {0: "TN_OK", -1: "TN_E_ARG", -2: "TN_E_LABEL", -3: "TN_E_PATH", -4: "TN
           -9: "TN_E_UNSUPPORTED", -10: "TN_E_NUMERIC"}
 
 EXPORTED = ["tn_plan_create", "tn_plan_destroy", "tn_plan_describe", "tn_plan_steps",
-            "tn_contract_slices", "tn_slice_partials", "tn_amplitudes", "tn_accumulator_set",
+            "tn_plan_step_times", "tn_contract_slices", "tn_slice_partials", "tn_amplitudes", "tn_accumulator_set",
             "tn_reset", "tn_gemm", "tn_permute", "tn_status_string", "tn_last_error_message"]
 
 
@@ -44,7 +44,8 @@ class tn_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("mem_cap_elems", ctypes.c_int64), ("stream", ctypes.c_void_p),
                 ("slice_batch", ctypes.c_int32), ("host_only", ctypes.c_int32),
-                ("split_policy", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("split_policy", ctypes.c_int32), ("record_steps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class tn_plan_info(ctypes.Structure):
@@ -79,6 +80,9 @@ _lib.tn_plan_describe.argtypes = [ctypes.c_void_p, _P(tn_plan_info)]
 _lib.tn_plan_describe.restype = ctypes.c_int
 _lib.tn_plan_steps.argtypes = [ctypes.c_void_p, _P(tn_step_info), ctypes.c_int32]
 _lib.tn_plan_steps.restype = ctypes.c_int
+_lib.tn_plan_step_times.argtypes = [ctypes.c_void_p, _P(ctypes.c_double), _P(ctypes.c_int64),
+                                    ctypes.c_int32]
+_lib.tn_plan_step_times.restype = ctypes.c_int
 _lib.tn_contract_slices.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]
 _lib.tn_contract_slices.restype = ctypes.c_int
 _lib.tn_slice_partials.argtypes = [ctypes.c_void_p, _P(ctypes.c_int64), ctypes.c_int64,
@@ -124,7 +128,7 @@ def _stream_handle(stream):
 
 def tn_plan_create(tensors, labels, open_labels, path, sliced_labels=(), precision="c64",
                    mem_cap_elems: int = 0, stream=None, slice_batch: int = 0,
-                   host_only: bool = False, split_policy: int = 0):
+                   host_only: bool = False, split_policy: int = 0, record_steps: bool = False):
     """Create a plan; returns an opaque handle (int).  Leaves are copied."""
     n = len(labels)
     ranks = (ctypes.c_int32 * n)(*[len(l) for l in labels])
@@ -162,6 +166,7 @@ def tn_plan_create(tensors, labels, open_labels, path, sliced_labels=(), precisi
     opts.slice_batch = int(slice_batch)
     opts.host_only = 1 if host_only else 0
     opts.split_policy = int(split_policy)
+    opts.record_steps = 1 if record_steps else 0
     handle = ctypes.c_void_p()
     status = _lib.tn_plan_create(ctypes.byref(handle), n, ranks, lab_pp, ext_pp, data_pp,
                                  len(open_labels), op, len(path), pa, len(sliced_labels), sl,
@@ -186,6 +191,16 @@ def tn_plan_steps(plan) -> list:
     arr = (tn_step_info * max(n, 1))()
     _check(_lib.tn_plan_steps(plan, arr, n))
     return [{name: getattr(arr[i], name) for name, _ in tn_step_info._fields_} for i in range(n)]
+
+
+def tn_plan_step_times(plan):
+    """(ms_total, launches) numpy arrays per step, recorded since the last call."""
+    n = tn_plan_describe(plan)["n_steps"]
+    ms = np.zeros(max(n, 1), dtype=np.float64)
+    cnt = np.zeros(max(n, 1), dtype=np.int64)
+    _check(_lib.tn_plan_step_times(plan, ms.ctypes.data_as(_P(ctypes.c_double)),
+                                   cnt.ctypes.data_as(_P(ctypes.c_int64)), n))
+    return ms[:n], cnt[:n]
 
 
 def tn_contract_slices(plan, first_slice: int, n_slices: int):
@@ -277,6 +292,9 @@ class Plan:
 
     def amplitudes(self):
         return tn_amplitudes(self.handle)
+
+    def step_times(self):
+        return tn_plan_step_times(self.handle)
 
     def partials(self, ids):
         return tn_slice_partials(self.handle, ids)
