@@ -63,7 +63,15 @@ struct GettArgs {
   int32_t k_split_bits;         // log2(K per split)
   int32_t tiles_m_bits, tiles_n_bits;
   int32_t write_scratch;        // 1: this launch writes split partials to scratch
+  int32_t fa, fb, fc;           // storage format of A, B, C: TN_FMT_C64 or TN_FMT_SPLIT
+  int32_t split_bf16;           // split storage uses bf16 halves (else fp16)
 };
+
+// Storage formats of an intermediate.  TN_FMT_SPLIT keeps, per complex element,
+// the word (hi_re, hi_im) and the word (lo_re, lo_im) of 16-bit halves with
+// hi = rn(x), lo = rn(x - hi) of the scaled value: 8 bytes, like complex64.
+#define TN_FMT_C64 0
+#define TN_FMT_SPLIT 1
 
 struct ReduceArgs {
   const float* root;            // [slice][amp] complex64

@@ -14,6 +14,15 @@ enum {
   TN_K_SPLITK_REDUCE = 4
 };
 
+// MFMA tile shapes (complex outputs per block, waves)
+enum {
+  TN_TILE_256x128 = 0,   // 4 x 2 waves
+  TN_TILE_128x128 = 1,   // 2 x 2 waves
+  TN_TILE_128x64 = 2,    // 2 x 1 waves
+  TN_TILE_64x64 = 3,     // 1 wave
+  TN_N_TILES = 4
+};
+
 #define PERM_LOCAL_MAX 12
 
 // Permutation of one bit-indexed tensor: the block owns the local bits
@@ -27,12 +36,10 @@ struct PermDesc {
   TileEnum ein, eout;
 };
 
-hipError_t tn_launch_gett(int kind, const GettDesc* d, const GettArgs& g, int64_t blocks, hipStream_t s);
+hipError_t tn_launch_gett(int kind, int tile, const GettDesc* d, const GettArgs& g, int64_t blocks, hipStream_t s);
 hipError_t tn_launch_permute(const PermDesc* p, int64_t blocks, const void* in, void* out, hipStream_t s);
 hipError_t tn_launch_slice_reduce(const ReduceArgs& r, hipStream_t s);
 hipError_t tn_launch_absmax(const void* x, int64_t n, uint32_t* dst, hipStream_t s);
 hipError_t tn_launch_fill_u32(void* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t tn_launch_scale_pow2(void* x, int64_t n, const int32_t* e, hipStream_t s);
-int tn_mfma_tile_m();
-int tn_mfma_tile_n();
-int tn_mfma_tile_k();
+void tn_tile_shape(int tile, int* bm, int* bn, int* threads);

@@ -1,22 +1,32 @@
 // gfx950 kernels for sliced tensor-network contraction.
 //
-//  k_gett_small      one thread per output element, FP32 VALU; tiny steps.
-//  k_gett_mfma<P>    tiled complex GEMM over bit-strided operands (GETT form of
-//                    the einsum of Sec. 2.4).  P = 0: complex64 on FP32 MFMA
-//                    (v_mfma_f32_32x32x2_f32).  P = 1 / 2: the extended-precision
-//                    split of Sec. 4.2 with fp16 / bf16 operands on
-//                    v_mfma_f32_32x32x16_{f16,bf16}: each operand is scaled by a
-//                    power of two, split into hi = rn(x), lo = rn(x - hi), and
-//                    C += hi*hi + hi*lo + lo*hi in FP32 (lo*lo dropped).
-//  k_splitk_reduce   sums K partitions in fixed order, writes C in its layout.
-//  k_permute         LDS-staged index permutation, coalesced on both sides.
-//  k_slice_reduce    FP64 cross-slice sum in increasing slice order.
+//  k_gett_small       one thread per output element, FP32 VALU; tiny steps.
+//  k_gett_mfma<P,WM,WN>  tiled complex GEMM over bit-strided operands (the GETT
+//                     form of the einsum of Sec. 2.4).  P = 0: complex64 on FP32
+//                     MFMA (v_mfma_f32_32x32x2_f32).  P = 1 / 2: the extended-
+//                     precision split of Sec. 4.2 with fp16 / bf16 operands on
+//                     v_mfma_f32_32x32x16_{f16,bf16}: operands are split into
+//                     hi = rn(x), lo = rn(x - hi) and C += hi*hi + hi*lo + lo*hi in
+//                     FP32 (lo*lo dropped).  WM x WN waves, 64 x 64 complex outputs
+//                     per wave, K step 16 complex, double-buffered LDS with the next
+//                     stage prefetched into registers during the MFMA phase.
+//  k_splitk_reduce    sums K partitions in fixed order, writes C in its layout.
+//  k_permute          LDS-staged index permutation, coalesced on both sides.
+//  k_slice_reduce     FP64 cross-slice sum in increasing slice order.
 //
 // The complex product is a real GEMM on stacked blocks: A is read as the real
 // matrix [Ar Ai] (M x 2K, the interleaved complex storage itself), B is expanded
-// per element into the 2x2 block [[Br, Bi], [-Bi, Br]] (2K x 2N), and the real
-// product is C = [Cr Ci] interleaved (M x 2N): 8 real flops per complex
-// multiply-add, the same count as the complex product.
+// per element into the 2x2 block [[Br, Bi], [-Bi, Br]] (2K x 2N, built in
+// registers from the stored (re, im) word), and the real product is C = [Cr Ci]
+// interleaved (M x 2N): 8 real flops per complex multiply-add, the same count as
+// the complex product.
+//
+// Scaling (Sec. 4.2 dynamic scaling): an operand stored as complex64 is scaled by
+// 2^s so that its largest |re|, |im| lands in [2^target, 2^(target+1)); an operand
+// stored split is already in range and is used as stored.  A result written split
+// is scaled by 2^t with t chosen from the bound |C| <= 2 K max|A| max|B|, so it
+// fits fp16 without a second pass.  Every (tensor, slice) carries an exponent:
+// true value = stored value * 2^e, e_C = e_A + e_B - s_A - s_B - t.
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
@@ -31,32 +41,37 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-__device__ __forceinline__ int64_t bits_offset(uint64_t v, const int64_t* __restrict__ stride,
-                                               int nbits) {
+__device__ __forceinline__ int64_t bits_offset(uint64_t v, const int64_t* __restrict__ stride, int nbits) {
   int64_t off = 0;
   for (int i = 0; i < nbits; ++i)
     if ((v >> i) & 1) off += stride[i];
   return off;
 }
 
+// frexp exponent of a positive finite float given by its bits: x in [2^(e-1), 2^e)
+__device__ __forceinline__ int fexp_bits(uint32_t bits) {
+  int e;
+  frexpf(__uint_as_float(bits), &e);
+  return e;
+}
+
+__device__ __forceinline__ bool usable_max(uint32_t bits) { return bits != 0u && bits < 0x7f800000u; }
+
 // Power-of-two shift that brings the tensor maximum to [2^target, 2^(target+1)).
 __device__ __forceinline__ int scale_shift(uint32_t maxbits, int target) {
-  float mx = __uint_as_float(maxbits);
-  if (!(mx > 0.f) || maxbits >= 0x7f800000u) return 0;
-  int e;
-  frexpf(mx, &e);
-  return target - (e - 1);
+  if (!usable_max(maxbits)) return 0;
+  return target - (fexp_bits(maxbits) - 1);
 }
 
 __device__ __forceinline__ uint32_t abs_bits(float2 v) {
-  uint32_t a = __float_as_uint(v.x) & 0x7fffffffu;
-  uint32_t b = __float_as_uint(v.y) & 0x7fffffffu;
+  const uint32_t a = __float_as_uint(v.x) & 0x7fffffffu;
+  const uint32_t b = __float_as_uint(v.y) & 0x7fffffffu;
   return a > b ? a : b;
 }
 
 __device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
   for (int off = 32; off > 0; off >>= 1) {
-    uint32_t o = __shfl_xor(v, off, 64);
+    const uint32_t o = __shfl_xor(v, off, 64);
     v = o > v ? o : v;
   }
   return v;
@@ -77,48 +92,114 @@ __device__ void block_umax_atomic(uint32_t v, uint32_t* dst, uint32_t* red) {
   }
 }
 
-__device__ __forceinline__ uint32_t pack_h2(_Float16 lo, _Float16 hi) {
-  return (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
-}
-__device__ __forceinline__ uint32_t pack_b2(__bf16 lo, __bf16 hi) {
-  return (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+__device__ __forceinline__ uint32_t pack16(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+
+// Split a scaled complex value into the hi word and the lo word of 16-bit pairs.
+__device__ __forceinline__ uint2 split_pair(float re, float im, bool bf) {
+  if (!bf) {
+    const _Float16 hr = (_Float16)re, hm = (_Float16)im;
+    const _Float16 lr = (_Float16)(re - (float)hr), lm = (_Float16)(im - (float)hm);
+    return make_uint2(pack16(__builtin_bit_cast(uint16_t, hr), __builtin_bit_cast(uint16_t, hm)),
+                      pack16(__builtin_bit_cast(uint16_t, lr), __builtin_bit_cast(uint16_t, lm)));
+  }
+  const __bf16 hr = (__bf16)re, hm = (__bf16)im;
+  const __bf16 lr = (__bf16)(re - (float)hr), lm = (__bf16)(im - (float)hm);
+  return make_uint2(pack16(__builtin_bit_cast(uint16_t, hr), __builtin_bit_cast(uint16_t, hm)),
+                    pack16(__builtin_bit_cast(uint16_t, lr), __builtin_bit_cast(uint16_t, lm)));
 }
 
-// Split a (scaled) complex value into hi and lo words of packed (re, im) pairs.
-template <int P>
-__device__ __forceinline__ void split2(float re, float im, uint32_t& hi, uint32_t& lo,
-                                       uint32_t& hi_neg_im, uint32_t& hi_swap,
-                                       uint32_t& lo_neg_im, uint32_t& lo_swap) {
-  if constexpr (P == 1) {
-    _Float16 hr = (_Float16)re, hm = (_Float16)im;
-    _Float16 lr = (_Float16)(re - (float)hr), lm = (_Float16)(im - (float)hm);
-    hi = pack_h2(hr, hm);
-    lo = pack_h2(lr, lm);
-    hi_neg_im = pack_h2(hr, -hm);
-    hi_swap = pack_h2(hm, hr);
-    lo_neg_im = pack_h2(lr, -lm);
-    lo_swap = pack_h2(lm, lr);
-  } else {
-    __bf16 hr = (__bf16)re, hm = (__bf16)im;
-    __bf16 lr = (__bf16)(re - (float)hr), lm = (__bf16)(im - (float)hm);
-    hi = pack_b2(hr, hm);
-    lo = pack_b2(lr, lm);
-    hi_neg_im = pack_b2(hr, -hm);
-    hi_swap = pack_b2(hm, hr);
-    lo_neg_im = pack_b2(lr, -lm);
-    lo_swap = pack_b2(lm, lr);
-  }
+__device__ __forceinline__ float half_bits_to_float(uint32_t h16, bool bf) {
+  if (bf) return __uint_as_float(h16 << 16);
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)h16);
+}
+
+// hi + lo of a split element as float2 (for maxima of split-written tensors)
+__device__ __forceinline__ float2 split_value(uint2 w, bool bf) {
+  return make_float2(half_bits_to_float(w.x & 0xffffu, bf) + half_bits_to_float(w.y & 0xffffu, bf),
+                     half_bits_to_float(w.x >> 16, bf) + half_bits_to_float(w.y >> 16, bf));
 }
 
 template <int P>
 __device__ __forceinline__ floatx16 mfma16(const u32x4& a, const u32x4& b, const floatx16& c) {
   if constexpr (P == 1) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(halfx8, a),
-                                                  __builtin_bit_cast(halfx8, b), c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(halfx8, a), __builtin_bit_cast(halfx8, b), c,
+                                                  0, 0, 0);
   } else {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
-                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
   }
+}
+
+// Per-step scale shifts (uniform within a block).
+struct Scales {
+  int sa, sb, t;
+  float fa, fb, ft;
+};
+
+__device__ __forceinline__ Scales step_scales(const GettDesc* __restrict__ d, const GettArgs& g, int sl) {
+  Scales r{0, 0, 0, 1.f, 1.f, 1.f};
+  if (!g.scale_mode) return r;
+  const uint32_t ma = g.maxA[g.a_ps ? sl : 0];
+  const uint32_t mb = g.maxB[g.b_ps ? sl : 0];
+  r.sa = g.fa == TN_FMT_SPLIT ? 0 : scale_shift(ma, g.target_exp);
+  r.sb = g.fb == TN_FMT_SPLIT ? 0 : scale_shift(mb, g.target_exp);
+  if (g.fc == TN_FMT_SPLIT && usable_max(ma) && usable_max(mb)) {
+    // |C| < 2 K 2^(ea + sa) 2^(eb + sb); write it below 2^15
+    r.t = 15 - (1 + d->kb + fexp_bits(ma) + r.sa + fexp_bits(mb) + r.sb);
+  }
+  r.fa = ldexpf(1.f, r.sa);
+  r.fb = ldexpf(1.f, r.sb);
+  r.ft = ldexpf(1.f, r.t);
+  return r;
+}
+
+__device__ __forceinline__ void write_exp(const GettArgs& g, int sl, const Scales& sc) {
+  g.expC[g.c_ps ? sl : 0] = g.expA[g.a_ps ? sl : 0] + g.expB[g.b_ps ? sl : 0] - sc.sa - sc.sb - sc.t;
+}
+
+// Store one result element in C's format; returns the bits of its max(|re|, |im|).
+__device__ __forceinline__ uint32_t store_c(float* C, int64_t off, float2 v, const GettArgs& g, float ft) {
+  v.x *= ft;
+  v.y *= ft;
+  if (g.fc == TN_FMT_SPLIT) {
+    const uint2 w = split_pair(v.x, v.y, g.split_bf16 != 0);
+    reinterpret_cast<uint2*>(C)[off] = w;
+    return abs_bits(split_value(w, g.split_bf16 != 0));
+  }
+  reinterpret_cast<float2*>(C)[off] = v;
+  return abs_bits(v);
+}
+
+struct ThreadEnum {
+  int64_t off;
+  int row, col;
+};
+
+template <int TB>
+__device__ __forceinline__ ThreadEnum thread_part(const TileEnum& en, int t) {
+  ThreadEnum r{0, 0, 0};
+  const int lo = en.n < TB ? en.n : TB;
+  for (int j = 0; j < lo; ++j) {
+    if ((t >> j) & 1) {
+      r.off += en.stride[j];
+      r.row += en.row[j];
+      r.col += en.col[j];
+    }
+  }
+  return r;
+}
+
+template <int TB>
+__device__ __forceinline__ ThreadEnum iter_part(const TileEnum& en, int it) {
+  ThreadEnum r{0, 0, 0};
+  for (int j = TB; j < en.n; ++j) {
+    if ((it >> (j - TB)) & 1) {
+      r.off += en.stride[j];
+      r.row += en.row[j];
+      r.col += en.col[j];
+    }
+  }
+  return r;
 }
 
 }  // namespace
@@ -146,14 +227,7 @@ __global__ __launch_bounds__(256) void k_gett_small(const GettDesc* __restrict__
       }
     }
     sl = (int)(bidx >> d->own_bb);
-    float sa = 1.f, sb = 1.f;
-    int sha = 0, shb = 0;
-    if (g.scale_mode) {
-      sha = scale_shift(g.maxA[g.a_ps ? sl : 0], g.target_exp);
-      shb = scale_shift(g.maxB[g.b_ps ? sl : 0], g.target_exp);
-      sa = ldexpf(1.f, sha);
-      sb = ldexpf(1.f, shb);
-    }
+    const Scales sc = step_scales(d, g, sl);
     const int64_t oa = bits_offset(bidx, d->a_b, nbb) + bits_offset(m, d->a_m, d->mb);
     const int64_t ob = bits_offset(bidx, d->b_b, nbb) + bits_offset(n, d->b_n, d->nb);
     const float2* A = reinterpret_cast<const float2*>(g.A);
@@ -163,18 +237,15 @@ __global__ __launch_bounds__(256) void k_gett_small(const GettDesc* __restrict__
     for (int64_t k = 0; k < K; ++k) {
       const float2 a = A[oa + bits_offset(k, d->a_k, d->kb)];
       const float2 b = B[ob + bits_offset(k, d->b_k, d->kb)];
-      const float ar = a.x * sa, ai = a.y * sa, br = b.x * sb, bi = b.y * sb;
+      const float ar = a.x * sc.fa, ai = a.y * sc.fa, br = b.x * sc.fb, bi = b.y * sc.fb;
       cr = fmaf(ar, br, cr);
       cr = fmaf(-ai, bi, cr);
       ci = fmaf(ar, bi, ci);
       ci = fmaf(ai, br, ci);
     }
-    reinterpret_cast<float2*>(g.C)[e] = make_float2(cr, ci);
-    mx = abs_bits(make_float2(cr, ci));
+    mx = store_c(g.C, e, make_float2(cr, ci), g, sc.ft);
     const uint64_t own_mask = (1ull << d->own_bb) - 1;
-    if (g.scale_mode && m == 0 && n == 0 && (bidx & own_mask) == 0) {
-      g.expC[g.c_ps ? sl : 0] = g.expA[g.a_ps ? sl : 0] + g.expB[g.b_ps ? sl : 0] - sha - shb;
-    }
+    if (g.scale_mode && m == 0 && n == 0 && (bidx & own_mask) == 0) write_exp(g, sl, sc);
   }
   if (g.maxC) {
     if (d->c_nbits >= 8) {
@@ -187,60 +258,34 @@ __global__ __launch_bounds__(256) void k_gett_small(const GettDesc* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Tiled MFMA kernel.  Tile: 128 x 64 complex outputs, K step 16 complex.
-// 256 threads = 4 waves in a 2 x 2 grid, each wave 64 x 32 complex
-// (64 x 64 real: 2 x 2 blocks of 32 x 32 MFMA outputs).
+// Tiled MFMA kernel.
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int BM = 128, BN = 64, BK = 16;
-constexpr int LDA_F = 2 * BM + 2;      // c64: A tile [BK][BM] float2, row stride in floats
-constexpr int LDB_F = 2 * BN + 2;      // c64: B tile [BK][BN] float2
-constexpr int LDW = BK + 4;            // split: words per row of the [row][k] tiles
-constexpr int LDC_F = 2 * BN + 8;      // epilogue C tile [BM][BN] float2
-constexpr int SMEM_C64 = (BK * LDA_F + BK * LDB_F) * 4;
-constexpr int SMEM_X3 = (2 * BM * LDW + 2 * (2 * BN) * LDW) * 4;
-constexpr int SMEM_C = 64 * LDC_F * 4;
-constexpr int SMEM_BYTES = (SMEM_C > SMEM_C64 ? (SMEM_C > SMEM_X3 ? SMEM_C : SMEM_X3)
-                                              : (SMEM_C64 > SMEM_X3 ? SMEM_C64 : SMEM_X3));
+constexpr int KB = 16;        // complex k per LDS stage
+constexpr int LDK = KB + 4;   // split: words per LDS row ([row][k] tiles)
 
-struct ThreadEnum {
-  int64_t off;
-  int row, col;
+template <int P, int WM, int WN>
+struct Tile {
+  static constexpr int NT = 64 * WM * WN;
+  static constexpr int TB = NT == 512 ? 9 : NT == 256 ? 8 : NT == 128 ? 7 : 6;
+  static constexpr int BM = 64 * WM, BN = 64 * WN;
+  static constexpr int IA = BM * KB / NT, IB = BN * KB / NT;
+  static constexpr int LDA0 = 2 * BM + 2, LDB0 = 2 * BN + 2;   // c64: floats per k row
+  static constexpr int BUF = P == 0 ? KB * LDA0 + KB * LDB0 : 2 * BM * LDK + 2 * BN * LDK;  // words
+  static constexpr int LDC = 2 * BN + 8;                        // epilogue floats per row (64 rows)
+  static constexpr int SMEM = 4 * (2 * BUF > 64 * LDC ? 2 * BUF : 64 * LDC);
 };
-
-__device__ __forceinline__ ThreadEnum thread_part(const TileEnum& en, int t) {
-  ThreadEnum r{0, 0, 0};
-  const int lo = en.n < 8 ? en.n : 8;
-  for (int j = 0; j < lo; ++j) {
-    if ((t >> j) & 1) {
-      r.off += en.stride[j];
-      r.row += en.row[j];
-      r.col += en.col[j];
-    }
-  }
-  return r;
-}
-
-__device__ __forceinline__ ThreadEnum iter_part(const TileEnum& en, int it) {
-  ThreadEnum r{0, 0, 0};
-  for (int j = 8; j < en.n; ++j) {
-    if ((it >> (j - 8)) & 1) {
-      r.off += en.stride[j];
-      r.row += en.row[j];
-      r.col += en.col[j];
-    }
-  }
-  return r;
-}
 }  // namespace
 
-template <int P>
-__global__ __launch_bounds__(256, 2) void k_gett_mfma(const GettDesc* __restrict__ d, GettArgs g) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t red[8];
+template <int P, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN, 2) void k_gett_mfma(const GettDesc* __restrict__ d, GettArgs g) {
+  using T = Tile<P, WM, WN>;
+  constexpr int NT = T::NT, TB = T::TB, BM = T::BM, BN = T::BN, IA = T::IA, IB = T::IB;
+  extern __shared__ __align__(16) uint32_t smem[];
+  __shared__ uint32_t red[16];
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
-  const int wm = w >> 1, wn = w & 1;
+  const int wm = w / WN, wn = w % WN;
   const int nbb = d->own_bb + g.chunk_bits;
 
   // block -> (tile_m, tile_n, batch, split)
@@ -252,192 +297,247 @@ __global__ __launch_bounds__(256, 2) void k_gett_mfma(const GettDesc* __restrict
   const uint64_t bidx = bid & ((1ull << nbb) - 1);
   const int split = (int)(bid >> nbb);
 
-  const int lm = d->mb < 7 ? d->mb : 7;
-  const int ln = d->nb < 6 ? d->nb : 6;
+  constexpr int LMAX = WM == 4 ? 8 : WM == 2 ? 7 : 6;
+  constexpr int NMAX = WN == 4 ? 8 : WN == 2 ? 7 : 6;
+  const int lm = d->mb < LMAX ? d->mb : LMAX;
+  const int ln = d->nb < NMAX ? d->nb : NMAX;
   const int lk = d->kb < 4 ? d->kb : 4;
   const int sl = (int)(bidx >> d->own_bb);
-
-  int sha = 0, shb = 0;
-  float sa = 1.f, sb = 1.f;
-  if (g.scale_mode) {
-    sha = scale_shift(g.maxA[g.a_ps ? sl : 0], g.target_exp);
-    shb = scale_shift(g.maxB[g.b_ps ? sl : 0], g.target_exp);
-    sa = ldexpf(1.f, sha);
-    sb = ldexpf(1.f, shb);
-  }
+  const Scales sc = step_scales(d, g, sl);
+  const bool bf = g.split_bf16 != 0;
 
   const int64_t a_base = bits_offset(bidx, d->a_b, nbb) + bits_offset(tile_m << lm, d->a_m, d->mb);
   const int64_t b_base = bits_offset(bidx, d->b_b, nbb) + bits_offset(tile_n << ln, d->b_n, d->nb);
-  const float2* A = reinterpret_cast<const float2*>(g.A);
-  const float2* B = reinterpret_cast<const float2*>(g.B);
+  const uint2* A = reinterpret_cast<const uint2*>(g.A);
+  const uint2* B = reinterpret_cast<const uint2*>(g.B);
 
-  const int na = d->ea.n, nbn = d->eb.n;
-  const int ea_elems = 1 << na, eb_elems = 1 << nbn;
-  const ThreadEnum ta = thread_part(d->ea, t);
-  const ThreadEnum tb = thread_part(d->eb, t);
-  const int it_a = ea_elems > 256 ? ea_elems >> 8 : 1;
-  const int it_b = eb_elems > 256 ? eb_elems >> 8 : 1;
+  const int ea_elems = 1 << d->ea.n, eb_elems = 1 << d->eb.n;
+  const ThreadEnum ta = thread_part<TB>(d->ea, t);
+  const ThreadEnum tb = thread_part<TB>(d->eb, t);
+  int64_t ia_off[IA], ib_off[IB];
+  int ia_pos[IA], ib_pos[IB];
+#pragma unroll
+  for (int i = 0; i < IA; ++i) {
+    const ThreadEnum ip = iter_part<TB>(d->ea, i);
+    ia_off[i] = ta.off + ip.off;
+    const int r = ta.row + ip.row, c = ta.col + ip.col;   // r = m_loc, c = k_loc
+    ia_pos[i] = P == 0 ? c * T::LDA0 + 2 * r : r * LDK + c;
+  }
+#pragma unroll
+  for (int i = 0; i < IB; ++i) {
+    const ThreadEnum ip = iter_part<TB>(d->eb, i);
+    ib_off[i] = tb.off + ip.off;
+    const int r = tb.row + ip.row, c = tb.col + ip.col;   // r = n_loc, c = k_loc
+    ib_pos[i] = P == 0 ? c * T::LDB0 + 2 * r : r * LDK + c;
+  }
 
-  floatx16 acc[2][2];
+  floatx16 acc[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
-  const int64_t k_iters = (int64_t)1 << (g.k_split_bits - lk);
+  const int64_t n_iters = (int64_t)1 << (g.k_split_bits - lk);
   const int64_t k_first = (int64_t)split << g.k_split_bits;
 
-  float* As = reinterpret_cast<float*>(smem);
-  float* Bs = As + BK * LDA_F;
-  uint32_t* Ahi = reinterpret_cast<uint32_t*>(smem);
-  uint32_t* Alo = Ahi + BM * LDW;
-  uint32_t* Bhi = Alo + BM * LDW;
-  uint32_t* Blo = Bhi + 2 * BN * LDW;
-
-  if constexpr (P != 0) {
-    // zero k columns beyond K (only when K < BK)
-    if (lk < 4) {
-      for (int i = t; i < 2 * BM * LDW + 4 * BN * LDW; i += 256) Ahi[i] = 0u;
-      __syncthreads();
-    }
+  if (lk < 4) {  // short K: columns beyond K stay zero in both buffers
+    for (int i = t; i < 2 * T::BUF; i += NT) smem[i] = 0u;
+    __syncthreads();
   }
 
-  for (int64_t kit = 0; kit < k_iters; ++kit) {
+  uint2 ra[IA], rb[IB];
+  auto load_stage = [&](int64_t kit) {
     const int64_t k0 = k_first + (kit << lk);
-    const int64_t ak = bits_offset(k0, d->a_k, d->kb);
-    const int64_t bk = bits_offset(k0, d->b_k, d->kb);
-    // ---- global -> LDS ----
-    for (int it = 0; it < it_a; ++it) {
-      if (t < ea_elems) {
-        const ThreadEnum ip = iter_part(d->ea, it);
-        const float2 v = A[a_base + ak + ta.off + ip.off];
-        const int r = ta.row + ip.row, c = ta.col + ip.col;   // r = m_loc, c = k_loc
-        if constexpr (P == 0) {
-          *reinterpret_cast<float2*>(As + c * LDA_F + 2 * r) = make_float2(v.x * sa, v.y * sa);
-        } else {
-          uint32_t hi, lo, h1, h2, l1, l2;
-          split2<P>(v.x * sa, v.y * sa, hi, lo, h1, h2, l1, l2);
-          Ahi[r * LDW + c] = hi;
-          Alo[r * LDW + c] = lo;
-        }
-      }
-    }
-    for (int it = 0; it < it_b; ++it) {
-      if (t < eb_elems) {
-        const ThreadEnum ip = iter_part(d->eb, it);
-        const float2 v = B[b_base + bk + tb.off + ip.off];
-        const int r = tb.row + ip.row, c = tb.col + ip.col;   // r = n_loc, c = k_loc
-        if constexpr (P == 0) {
-          *reinterpret_cast<float2*>(Bs + c * LDB_F + 2 * r) = make_float2(v.x * sb, v.y * sb);
-        } else {
-          uint32_t hi, lo, h1, h2, l1, l2;
-          split2<P>(v.x * sb, v.y * sb, hi, lo, h1, h2, l1, l2);
-          Bhi[(2 * r) * LDW + c] = h1;       // real column 2n:   (Br, -Bi)
-          Bhi[(2 * r + 1) * LDW + c] = h2;   // real column 2n+1: (Bi,  Br)
-          Blo[(2 * r) * LDW + c] = l1;
-          Blo[(2 * r + 1) * LDW + c] = l2;
-        }
-      }
-    }
-    __syncthreads();
-    // ---- MFMA ----
+    const int64_t ak = a_base + bits_offset(k0, d->a_k, d->kb);
+    const int64_t bk = b_base + bits_offset(k0, d->b_k, d->kb);
+#pragma unroll
+    for (int i = 0; i < IA; ++i)
+      if (t + NT * i < ea_elems) ra[i] = A[ak + ia_off[i]];
+#pragma unroll
+    for (int i = 0; i < IB; ++i)
+      if (t + NT * i < eb_elems) rb[i] = B[bk + ib_off[i]];
+  };
+  auto store_stage = [&](uint32_t* buf) {
     if constexpr (P == 0) {
+      float* As = reinterpret_cast<float*>(buf);
+      float* Bs = As + KB * T::LDA0;
+#pragma unroll
+      for (int i = 0; i < IA; ++i)
+        if (t + NT * i < ea_elems) {
+          const float2 v = __builtin_bit_cast(float2, ra[i]);
+          *reinterpret_cast<float2*>(As + ia_pos[i]) = make_float2(v.x * sc.fa, v.y * sc.fa);
+        }
+#pragma unroll
+      for (int i = 0; i < IB; ++i)
+        if (t + NT * i < eb_elems) {
+          const float2 v = __builtin_bit_cast(float2, rb[i]);
+          *reinterpret_cast<float2*>(Bs + ib_pos[i]) = make_float2(v.x * sc.fb, v.y * sc.fb);
+        }
+    } else {
+      uint32_t* Ah = buf;
+      uint32_t* Al = Ah + BM * LDK;
+      uint32_t* Bh = Al + BM * LDK;
+      uint32_t* Bl = Bh + BN * LDK;
+#pragma unroll
+      for (int i = 0; i < IA; ++i)
+        if (t + NT * i < ea_elems) {
+          uint2 wv = ra[i];
+          if (g.fa != TN_FMT_SPLIT) {
+            const float2 v = __builtin_bit_cast(float2, wv);
+            wv = split_pair(v.x * sc.fa, v.y * sc.fa, bf);
+          }
+          Ah[ia_pos[i]] = wv.x;
+          Al[ia_pos[i]] = wv.y;
+        }
+#pragma unroll
+      for (int i = 0; i < IB; ++i)
+        if (t + NT * i < eb_elems) {
+          uint2 wv = rb[i];
+          if (g.fb != TN_FMT_SPLIT) {
+            const float2 v = __builtin_bit_cast(float2, wv);
+            wv = split_pair(v.x * sc.fb, v.y * sc.fb, bf);
+          }
+          Bh[ib_pos[i]] = wv.x;
+          Bl[ib_pos[i]] = wv.y;
+        }
+    }
+  };
+
+  load_stage(0);
+  store_stage(smem);
+  __syncthreads();
+
+  const int rot = (lane & 1) ? 16 : 0;
+  const uint32_t msk = (lane & 1) ? 0u : 0x80000000u;
+  const int c_half = lane >> 5, dd = lane & 1;
+  const bool use_im = (c_half ^ dd) != 0;
+  const float sgn = (c_half == 1 && dd == 0) ? -1.f : 1.f;
+
+  for (int64_t kit = 0; kit < n_iters; ++kit) {
+    uint32_t* cur = smem + (kit & 1) * T::BUF;
+    uint32_t* nxt = smem + ((kit + 1) & 1) * T::BUF;
+    const bool more = kit + 1 < n_iters;
+    if (more) load_stage(kit + 1);
+    if constexpr (P == 0) {
+      const float* As = reinterpret_cast<const float*>(cur);
+      const float* Bs = As + KB * T::LDA0;
       const int kk_n = 1 << lk;
-      const int c = lane >> 5, dd = lane & 1;
-      const bool use_im = (c ^ dd) != 0;
-      const float sgn = (c == 1 && dd == 0) ? -1.f : 1.f;
       for (int kk = 0; kk < kk_n; ++kk) {
-        float a[2], b[2];
+        float a[2], b[4];
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi) a[mi] = As[kk * LDA_F + 2 * (wm * 64 + mi * 32 + (lane & 31)) + c];
+        for (int mi = 0; mi < 2; ++mi) a[mi] = As[kk * T::LDA0 + 2 * (wm * 64 + mi * 32 + (lane & 31)) + c_half];
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni) {
-          const float2 bv = *reinterpret_cast<const float2*>(Bs + kk * LDB_F + 2 * (wn * 32 + ni * 16 + ((lane & 31) >> 1)));
+        for (int ni = 0; ni < 4; ++ni) {
+          const float2 bv =
+              *reinterpret_cast<const float2*>(Bs + kk * T::LDB0 + 2 * (wn * 64 + ni * 16 + ((lane & 31) >> 1)));
           b[ni] = sgn * (use_im ? bv.y : bv.x);
         }
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-          for (int ni = 0; ni < 2; ++ni)
+          for (int ni = 0; ni < 4; ++ni)
             acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
       }
     } else {
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += 8) {
-        u32x4 ah[2], al[2], bh[2], bl[2];
-        const int kw = kk + (lane >> 5) * 4;
+      const uint32_t* Ah = cur;
+      const uint32_t* Al = Ah + BM * LDK;
+      const uint32_t* Bh = Al + BM * LDK;
+      const uint32_t* Bl = Bh + BN * LDK;
+      const int ks_n = lk >= 3 ? (1 << lk) >> 3 : 1;
+      for (int ks = 0; ks < ks_n; ++ks) {
+        const int kw = ks * 8 + (lane >> 5) * 4;
+        u32x4 ah[2], al[2], bh[4], bl[4];
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) {
           const int r = wm * 64 + mi * 32 + (lane & 31);
-          ah[mi] = *reinterpret_cast<const u32x4*>(Ahi + r * LDW + kw);
-          al[mi] = *reinterpret_cast<const u32x4*>(Alo + r * LDW + kw);
+          ah[mi] = *reinterpret_cast<const u32x4*>(Ah + r * LDK + kw);
+          al[mi] = *reinterpret_cast<const u32x4*>(Al + r * LDK + kw);
         }
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni) {
-          const int r = wn * 64 + ni * 32 + (lane & 31);
-          bh[ni] = *reinterpret_cast<const u32x4*>(Bhi + r * LDW + kw);
-          bl[ni] = *reinterpret_cast<const u32x4*>(Blo + r * LDW + kw);
+        for (int ni = 0; ni < 4; ++ni) {
+          const int r = wn * 64 + ni * 16 + ((lane & 31) >> 1);
+          u32x4 x = *reinterpret_cast<const u32x4*>(Bh + r * LDK + kw);
+          u32x4 y = *reinterpret_cast<const u32x4*>(Bl + r * LDK + kw);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            x[q] = __builtin_amdgcn_alignbit(x[q], x[q], rot) ^ msk;
+            y[q] = __builtin_amdgcn_alignbit(y[q], y[q], rot) ^ msk;
+          }
+          bh[ni] = x;
+          bl[ni] = y;
         }
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-          for (int ni = 0; ni < 2; ++ni) {
-            acc[mi][ni] = mfma16<P>(ah[mi], bh[ni], acc[mi][ni]);
-            acc[mi][ni] = mfma16<P>(ah[mi], bl[ni], acc[mi][ni]);
-            acc[mi][ni] = mfma16<P>(al[mi], bh[ni], acc[mi][ni]);
-          }
+          for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(ah[mi], bh[ni], acc[mi][ni]);
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(ah[mi], bl[ni], acc[mi][ni]);
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(al[mi], bh[ni], acc[mi][ni]);
       }
     }
+    if (more) store_stage(nxt);
     __syncthreads();
   }
 
   // ---- epilogue: accumulators -> LDS (64 rows per pass) -> global ----
   float* Cs = reinterpret_cast<float*>(smem);
-  const int64_t M_loc = (int64_t)1 << lm, N_loc = (int64_t)1 << ln;
+  const int64_t N_loc = (int64_t)1 << ln;
   const int64_t Mtot = (int64_t)1 << d->mb, Ntot = (int64_t)1 << d->nb;
-  const int64_t s_base = ((((int64_t)split << nbb) + (int64_t)bidx) * Mtot + ((int64_t)tile_m << lm)) * Ntot +
-                         ((int64_t)tile_n << ln);
-  const int64_t c_base = bits_offset(bidx, d->c_b, nbb) + bits_offset(tile_m << lm, d->c_m, d->mb) +
-                         bits_offset(tile_n << ln, d->c_n, d->nb);
+  const int npass = lm > 6 ? 1 << (lm - 6) : 1;
   const int nc = d->ec.n;
   const int ec_elems = 1 << nc;
-  const ThreadEnum tc = thread_part(d->ec, t);
-  const int it_c = ec_elems > 256 ? ec_elems >> 8 : 1;
+  const ThreadEnum tc = thread_part<TB>(d->ec, t);
+  const int it_c = ec_elems > NT ? ec_elems >> TB : 1;
+  // the pass bits (local m bits >= 6) are the top bits of the C enumeration
+  const bool pass_major = (nc - (lm > 6 ? lm - 6 : 0)) >= TB;
+  const int it_per_pass = pass_major ? it_c / npass : it_c;
+  int64_t c_base = 0, s_base = 0;
+  if (g.write_scratch) {
+    s_base = ((((int64_t)split << nbb) + (int64_t)bidx) * Mtot + ((int64_t)tile_m << lm)) * Ntot +
+             ((int64_t)tile_n << ln);
+  } else {
+    c_base = bits_offset(bidx, d->c_b, nbb) + bits_offset(tile_m << lm, d->c_m, d->mb) +
+             bits_offset(tile_n << ln, d->c_n, d->nb);
+  }
   uint32_t mx = 0;
-  for (int pass = 0; pass < 2; ++pass) {
+  for (int pass = 0; pass < npass; ++pass) {
     if (wm == pass) {
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
+        for (int ni = 0; ni < 4; ++ni)
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const int row = mi * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-            const int col = wn * 64 + ni * 32 + (lane & 31);
-            Cs[row * LDC_F + col] = acc[mi][ni][v];
+            const int col = wn * 128 + ni * 32 + (lane & 31);
+            Cs[row * T::LDC + col] = acc[mi][ni][v];
           }
     }
     __syncthreads();
     if (g.write_scratch) {
-      // partials [split][batch][M][N] row-major
       float2* S = reinterpret_cast<float2*>(g.scratch);
-      for (int64_t e = t; e < M_loc * N_loc; e += 256) {
+      const int64_t M_loc = (int64_t)1 << lm;
+      const int64_t rows = M_loc - pass * 64 < 64 ? M_loc - pass * 64 : 64;
+      for (int64_t e = t; e < rows * N_loc; e += NT) {
         const int r = (int)(e >> ln), c = (int)(e & (N_loc - 1));
-        if ((r >> 6) != pass) continue;
-        S[s_base + (int64_t)r * Ntot + c] = *reinterpret_cast<const float2*>(Cs + (r & 63) * LDC_F + 2 * c);
+        S[s_base + (int64_t)(pass * 64 + r) * Ntot + c] = *reinterpret_cast<const float2*>(Cs + r * T::LDC + 2 * c);
       }
     } else {
-      float2* C = reinterpret_cast<float2*>(g.C);
-      for (int it = 0; it < it_c; ++it) {
+      const int it0 = pass_major ? pass * it_per_pass : 0;
+      for (int it = it0; it < it0 + it_per_pass; ++it) {
         if (t < ec_elems) {
-          const ThreadEnum ip = iter_part(d->ec, it);
+          const ThreadEnum ip = iter_part<TB>(d->ec, it);
           const int r = tc.row + ip.row, c = tc.col + ip.col;
           if ((r >> 6) == pass) {
-            const float2 v = *reinterpret_cast<const float2*>(Cs + (r & 63) * LDC_F + 2 * c);
-            C[c_base + tc.off + ip.off] = v;
-            const uint32_t b = abs_bits(v);
+            const float2 v = *reinterpret_cast<const float2*>(Cs + (r & 63) * T::LDC + 2 * c);
+            const uint32_t b = store_c(g.C, c_base + tc.off + ip.off, v, g, sc.ft);
             mx = b > mx ? b : mx;
           }
         }
@@ -446,10 +546,8 @@ __global__ __launch_bounds__(256, 2) void k_gett_mfma(const GettDesc* __restrict
     __syncthreads();
   }
   if (!g.write_scratch) {
-    if (g.scale_mode && tile_m == 0 && tile_n == 0 && t == 0 &&
-        (bidx & ((1ull << d->own_bb) - 1)) == 0) {
-      g.expC[g.c_ps ? sl : 0] = g.expA[g.a_ps ? sl : 0] + g.expB[g.b_ps ? sl : 0] - sha - shb;
-    }
+    if (g.scale_mode && tile_m == 0 && tile_n == 0 && t == 0 && (bidx & ((1ull << d->own_bb) - 1)) == 0)
+      write_exp(g, sl, sc);
     if (g.maxC) block_umax_atomic(mx, g.maxC + (g.c_ps ? sl : 0), red);
   }
 }
@@ -477,6 +575,7 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const GettDesc* __restric
       }
     }
     sl = (int)(bidx >> d->own_bb);
+    const Scales sc = step_scales(d, g, sl);
     const int64_t MN = (int64_t)1 << (d->mb + d->nb);
     const int64_t per_split = MN << nbb;
     const int64_t off = ((int64_t)bidx * MN) + ((int64_t)m << d->nb) + (int64_t)n;
@@ -487,14 +586,9 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const GettDesc* __restric
       cr += v.x;
       ci += v.y;
     }
-    reinterpret_cast<float2*>(g.C)[e] = make_float2(cr, ci);
-    mx = abs_bits(make_float2(cr, ci));
+    mx = store_c(g.C, e, make_float2(cr, ci), g, sc.ft);
     const uint64_t own_mask = (1ull << d->own_bb) - 1;
-    if (g.scale_mode && m == 0 && n == 0 && (bidx & own_mask) == 0) {
-      const int sha = scale_shift(g.maxA[g.a_ps ? sl : 0], g.target_exp);
-      const int shb = scale_shift(g.maxB[g.b_ps ? sl : 0], g.target_exp);
-      g.expC[g.c_ps ? sl : 0] = g.expA[g.a_ps ? sl : 0] + g.expB[g.b_ps ? sl : 0] - sha - shb;
-    }
+    if (g.scale_mode && m == 0 && n == 0 && (bidx & own_mask) == 0) write_exp(g, sl, sc);
   }
   if (g.maxC) {
     if (d->c_nbits >= 8) {
@@ -513,7 +607,7 @@ __global__ __launch_bounds__(256) void k_permute(const PermDesc* __restrict__ p,
                                                  float2* __restrict__ out) {
   __shared__ float2 tile[1 << PERM_LOCAL_MAX];
   const int t = threadIdx.x;
-  uint64_t bid = blockIdx.x;
+  const uint64_t bid = blockIdx.x;
   int64_t ib = 0, ob = 0;
   for (int j = 0; j < p->nh; ++j)
     if ((bid >> j) & 1) {
@@ -522,19 +616,19 @@ __global__ __launch_bounds__(256) void k_permute(const PermDesc* __restrict__ p,
     }
   const int n = p->ein.n;
   const int elems = 1 << n;
-  const ThreadEnum ti = thread_part(p->ein, t);
-  const ThreadEnum to = thread_part(p->eout, t);
+  const ThreadEnum ti = thread_part<8>(p->ein, t);
+  const ThreadEnum to = thread_part<8>(p->eout, t);
   const int iters = elems > 256 ? elems >> 8 : 1;
   for (int it = 0; it < iters; ++it) {
     if (t < elems) {
-      const ThreadEnum ip = iter_part(p->ein, it);
+      const ThreadEnum ip = iter_part<8>(p->ein, it);
       tile[ti.row + ip.row] = in[ib + ti.off + ip.off];
     }
   }
   __syncthreads();
   for (int it = 0; it < iters; ++it) {
     if (t < elems) {
-      const ThreadEnum ip = iter_part(p->eout, it);
+      const ThreadEnum ip = iter_part<8>(p->eout, it);
       out[ob + to.off + ip.off] = tile[to.row + ip.row];
     }
   }
@@ -601,34 +695,52 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t tn_launch_gett(int kind, const GettDesc* d, const GettArgs& g, int64_t blocks,
-                          hipStream_t s) {
+namespace {
+template <int P, int WM, int WN>
+hipError_t launch_mfma(const GettDesc* d, const GettArgs& g, int64_t blocks, hipStream_t s) {
+  using T = Tile<P, WM, WN>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gett_mfma<P, WM, WN>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, T::SMEM);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_gett_mfma<P, WM, WN>), dim3((unsigned)blocks), dim3(T::NT), T::SMEM, s, d, g);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_mfma_tile(int tile, const GettDesc* d, const GettArgs& g, int64_t blocks, hipStream_t s) {
+  switch (tile) {
+    case TN_TILE_256x128: return launch_mfma<P, 4, 2>(d, g, blocks, s);
+    case TN_TILE_128x128: return launch_mfma<P, 2, 2>(d, g, blocks, s);
+    case TN_TILE_128x64: return launch_mfma<P, 2, 1>(d, g, blocks, s);
+    case TN_TILE_64x64: return launch_mfma<P, 1, 1>(d, g, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace
+
+hipError_t tn_launch_gett(int kind, int tile, const GettDesc* d, const GettArgs& g, int64_t blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   switch (kind) {
     case TN_K_SMALL:
       hipLaunchKernelGGL(k_gett_small, dim3((unsigned)blocks), dim3(256), 0, s, d, g);
-      break;
-    case TN_K_MFMA_F32:
-      hipLaunchKernelGGL(k_gett_mfma<0>, dim3((unsigned)blocks), dim3(256), SMEM_BYTES, s, d, g);
-      break;
-    case TN_K_MFMA_F16X3:
-      hipLaunchKernelGGL(k_gett_mfma<1>, dim3((unsigned)blocks), dim3(256), SMEM_BYTES, s, d, g);
-      break;
-    case TN_K_MFMA_BF16X3:
-      hipLaunchKernelGGL(k_gett_mfma<2>, dim3((unsigned)blocks), dim3(256), SMEM_BYTES, s, d, g);
-      break;
+      return hipGetLastError();
+    case TN_K_MFMA_F32: return launch_mfma_tile<0>(tile, d, g, blocks, s);
+    case TN_K_MFMA_F16X3: return launch_mfma_tile<1>(tile, d, g, blocks, s);
+    case TN_K_MFMA_BF16X3: return launch_mfma_tile<2>(tile, d, g, blocks, s);
     case TN_K_SPLITK_REDUCE:
       hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, s, d, g);
-      break;
-    default:
-      return hipErrorInvalidValue;
+      return hipGetLastError();
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t tn_launch_permute(const PermDesc* p, int64_t blocks, const void* in, void* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)blocks), dim3(256), 0, s, p,
-                     reinterpret_cast<const float2*>(in), reinterpret_cast<float2*>(out));
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)blocks), dim3(256), 0, s, p, reinterpret_cast<const float2*>(in),
+                     reinterpret_cast<float2*>(out));
   return hipGetLastError();
 }
 
@@ -660,6 +772,15 @@ hipError_t tn_launch_scale_pow2(void* x, int64_t n, const int32_t* e, hipStream_
   return hipGetLastError();
 }
 
-int tn_mfma_tile_m() { return BM; }
-int tn_mfma_tile_n() { return BN; }
-int tn_mfma_tile_k() { return BK; }
+void tn_tile_shape(int tile, int* bm, int* bn, int* threads) {
+  int wm = 2, wn = 2;
+  switch (tile) {
+    case TN_TILE_256x128: wm = 4; wn = 2; break;
+    case TN_TILE_128x128: wm = 2; wn = 2; break;
+    case TN_TILE_128x64: wm = 2; wn = 1; break;
+    case TN_TILE_64x64: wm = 1; wn = 1; break;
+  }
+  *bm = 64 * wm;
+  *bn = 64 * wn;
+  *threads = 64 * wm * wn;
+}

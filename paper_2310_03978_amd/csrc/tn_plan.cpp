@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <set>
@@ -66,6 +67,7 @@ struct Tensor {
   bool leaf = false;
   bool layout_set = false;
   int64_t elems = 1;         // 2^bits.size()
+  int fmt = TN_FMT_C64;      // storage format, chosen for the consumer
   int arena = 0;             // 0 leaves, 1 invariant, 2 per-slice
   int64_t offset = 0;        // elements
   std::vector<int> user_layout;  // leaves: bits of the caller's row-major data, LSB first
@@ -78,6 +80,7 @@ struct Step {
   std::vector<int> bb, mb, nb, kb;   // bit lists in GEMM order, LSB first
   bool per_slice = false;
   int kernel = TN_K_SMALL;
+  int tile = TN_TILE_128x128;
   int splits = 1;
   int k_split_bits = 0;
   int tiles_m_bits = 0, tiles_n_bits = 0;
@@ -219,10 +222,12 @@ int64_t slice_stride(const tn_plan_s* p, const Tensor& T, int j) {
   return T.elems << j;
 }
 
-void fill_enum(TileEnum& en, std::vector<std::pair<int64_t, std::pair<int, int>>> bitsv) {
-  // bitsv: (stride, (row increment, col increment)); sort by stride
+void fill_enum(TileEnum& en, std::vector<std::pair<int64_t, std::pair<int, int>>> bitsv,
+               const std::vector<std::pair<int64_t, std::pair<int, int>>>& tail = {}) {
+  // bitsv: (stride, (row increment, col increment)); sorted by stride, then `tail` appended as is
   std::stable_sort(bitsv.begin(), bitsv.end(),
                    [](const auto& a, const auto& b) { return a.first < b.first; });
+  bitsv.insert(bitsv.end(), tail.begin(), tail.end());
   memset(&en, 0, sizeof(en));
   en.n = (int)bitsv.size();
   for (size_t j = 0; j < bitsv.size(); ++j) {
@@ -291,20 +296,42 @@ void build_desc(tn_plan_s* p, Step& st) {
     d.c_pos[pos] = code;
   }
   for (int j = 0; j < sb; ++j) d.c_pos[C.bits.size() + j] = (0 << 8) | (own + j);
-  // tile enumerations for the MFMA kernels
-  const int lm = std::min(d.mb, 7), ln = std::min(d.nb, 6), lk = std::min(d.kb, 4);
-  std::vector<std::pair<int64_t, std::pair<int, int>>> va, vb, vc;
+  // tile enumerations for the MFMA kernels (the step's tile shape)
+  int bm = 128, bn = 128, nt = 256;
+  tn_tile_shape(st.tile, &bm, &bn, &nt);
+  const int lm = std::min(d.mb, ilog2_exact(bm)), ln = std::min(d.nb, ilog2_exact(bn)), lk = std::min(d.kb, 4);
+  std::vector<std::pair<int64_t, std::pair<int, int>>> va, vb, vc, vpass;
   for (int j = 0; j < lm; ++j) va.push_back({d.a_m[j], {1 << j, 0}});
   for (int j = 0; j < lk; ++j) va.push_back({d.a_k[j], {0, 1 << j}});
   for (int j = 0; j < ln; ++j) vb.push_back({d.b_n[j], {1 << j, 0}});
   for (int j = 0; j < lk; ++j) vb.push_back({d.b_k[j], {0, 1 << j}});
-  for (int j = 0; j < lm; ++j) vc.push_back({d.c_m[j], {1 << j, 0}});
+  // the epilogue stages 64 rows at a time: local m bits >= 6 go last
+  for (int j = 0; j < lm; ++j) (j < 6 ? vc : vpass).push_back({d.c_m[j], {1 << j, 0}});
   for (int j = 0; j < ln; ++j) vc.push_back({d.c_n[j], {0, 1 << j}});
   fill_enum(d.ea, va);
   fill_enum(d.eb, vb);
-  fill_enum(d.ec, vc);
+  fill_enum(d.ec, vc, vpass);
   st.a_contig = contig_run(d.ea);
   st.b_contig = contig_run(d.eb);
+}
+
+// Tile shape and K split of an MFMA step.
+void set_tile(const tn_plan_s* p, Step& st, int tile) {
+  const int bbits = (int)st.bb.size() + (st.per_slice ? p->s_bits : 0);
+  const int mb = (int)st.mb.size(), nb = (int)st.nb.size(), kb = (int)st.kb.size();
+  int bm, bn, nt;
+  tn_tile_shape(tile, &bm, &bn, &nt);
+  st.tile = tile;
+  const int lm = std::min(mb, ilog2_exact(bm)), ln = std::min(nb, ilog2_exact(bn)), lk = std::min(kb, 4);
+  st.tiles_m_bits = mb - lm;
+  st.tiles_n_bits = nb - ln;
+  const int tile_bits = st.tiles_m_bits + st.tiles_n_bits + bbits;
+  int s = 0;
+  // split K when the grid is small and K long: aim for >= 1024 blocks, >= 8 K stages per split
+  while (tile_bits + s < 10 && kb - (s + 1) >= lk + 3) ++s;
+  st.splits = 1 << s;
+  st.k_split_bits = kb - s;
+  st.scratch_elems = st.splits > 1 ? (int64_t(st.splits) << (bbits + mb + nb)) : 0;
 }
 
 void choose_kernel(tn_plan_s* p, Step& st) {
@@ -323,16 +350,12 @@ void choose_kernel(tn_plan_s* p, Step& st) {
   }
   st.kernel = split_prec ? (p->precision == TN_PREC_F16X3 ? TN_K_MFMA_F16X3 : TN_K_MFMA_BF16X3)
                          : TN_K_MFMA_F32;
-  const int lm = std::min(mb, 7), ln = std::min(nb, 6), lk = std::min(kb, 4);
-  st.tiles_m_bits = mb - lm;
-  st.tiles_n_bits = nb - ln;
-  const int tile_bits = st.tiles_m_bits + st.tiles_n_bits + bbits;
-  int s = 0;
-  // split K when the grid is small and K long: aim for >= 1024 blocks, >= 8 K iterations per split
-  while (tile_bits + s < 10 && kb - (s + 1) >= lk + 3) ++s;
-  st.splits = 1 << s;
-  st.k_split_bits = kb - s;
-  st.scratch_elems = st.splits > 1 ? (int64_t(st.splits) << (bbits + mb + nb)) : 0;
+  int tile;
+  if (nb >= 7 && mb >= 8) tile = TN_TILE_256x128;
+  else if (nb >= 7 && mb >= 7) tile = TN_TILE_128x128;
+  else if (mb >= 7) tile = TN_TILE_128x64;
+  else tile = TN_TILE_64x64;
+  set_tile(p, st, tile);
 }
 
 // Every address a kernel forms is a sum of per-bit strides.  Check, for every
@@ -676,6 +699,12 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
       p->bytes_inv += st.bytes;
     }
   }
+  // intermediates read by a split-precision MFMA step are stored split
+  for (auto& st : p->steps) {
+    if (st.kernel != TN_K_MFMA_F16X3 && st.kernel != TN_K_MFMA_BF16X3) continue;
+    for (int x : {st.ta, st.tb})
+      if (!p->tensors[x].leaf) p->tensors[x].fmt = TN_FMT_SPLIT;
+  }
   for (size_t s = 0; s < p->steps.size(); ++s)
     (p->steps[s].per_slice ? p->ps_order : p->inv_order).push_back((int)s);
   // memory: leaves, invariant arena, per-slice arena (S copies of each tensor)
@@ -832,7 +861,8 @@ int64_t leaf_chunk_offset(const tn_plan_s* p, const Tensor& T, int64_t base, int
 
 tn_status timed_launch(tn_plan_s* p, int s, int kind, const GettDesc* d, const GettArgs& g, int64_t blocks,
                        const char* what) {
-  if (!p->opts.record_steps) return check(tn_launch_gett(kind, d, g, blocks, p->stream), what);
+  const int tile = p->steps[s].tile;
+  if (!p->opts.record_steps) return check(tn_launch_gett(kind, tile, d, g, blocks, p->stream), what);
   std::pair<hipEvent_t, hipEvent_t> ev;
   if (!p->event_pool.empty()) {
     ev = p->event_pool.back();
@@ -843,7 +873,7 @@ tn_status timed_launch(tn_plan_s* p, int s, int kind, const GettDesc* d, const G
     if (st) return st;
   }
   tn_status st = check(hipEventRecord(ev.first, p->stream), "event record");
-  if (!st) st = check(tn_launch_gett(kind, d, g, blocks, p->stream), what);
+  if (!st) st = check(tn_launch_gett(kind, tile, d, g, blocks, p->stream), what);
   if (!st) st = check(hipEventRecord(ev.second, p->stream), "event record");
   p->pending.push_back({s, ev.first, ev.second});
   return st;
@@ -883,6 +913,10 @@ tn_status run_step(tn_plan_s* p, int s, int64_t chunk_base, int chunk_bits) {
   }
   g.target_exp = (st.kernel == TN_K_MFMA_F16X3 || st.kernel == TN_K_MFMA_BF16X3) ? 14 : 0;
   g.chunk_bits = st.per_slice ? chunk_bits : 0;
+  g.fa = A.fmt;
+  g.fb = B.fmt;
+  g.fc = C.fmt;
+  g.split_bf16 = p->precision == TN_PREC_BF16X3 ? 1 : 0;
   const GettDesc* d = p->d_desc + s;
   const int bbits = (int)st.bb.size() + g.chunk_bits;
   if (st.kernel == TN_K_SMALL) {
@@ -902,7 +936,7 @@ tn_status run_step(tn_plan_s* p, int s, int64_t chunk_base, int chunk_bits) {
     if (r) return r;
     g.write_scratch = 0;
     const int64_t total = int64_t(1) << (C.bits.size() + g.chunk_bits);
-    return check(tn_launch_gett(TN_K_SPLITK_REDUCE, d, g, (total + 255) / 256, p->stream), "split-K reduce");
+    return check(tn_launch_gett(TN_K_SPLITK_REDUCE, 0, d, g, (total + 255) / 256, p->stream), "split-K reduce");
   }
   return timed_launch(p, s, st.kernel, d, g, blocks, "mfma step");
 }
@@ -1035,8 +1069,10 @@ tn_status tn_plan_steps(tn_plan p, tn_step_info* steps, int32_t cap) {
     o.n = int64_t(1) << st.nb.size();
     o.k = int64_t(1) << st.kb.size();
     o.split_k = st.splits;
-    o.tile_m = st.kernel == TN_K_SMALL ? 1 : (int)std::min<int64_t>(o.m, tn_mfma_tile_m());
-    o.tile_n = st.kernel == TN_K_SMALL ? 1 : (int)std::min<int64_t>(o.n, tn_mfma_tile_n());
+    int bm = 1, bn = 1, nt = 0;
+    if (st.kernel != TN_K_SMALL) tn_tile_shape(st.tile, &bm, &bn, &nt);
+    o.tile_m = (int)std::min<int64_t>(o.m, bm);
+    o.tile_n = (int)std::min<int64_t>(o.n, bn);
     o.a_contig = st.a_contig;
     o.b_contig = st.b_contig;
     o.flops = st.flops;
@@ -1183,18 +1219,13 @@ tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_
   st.tb = 1;
   st.tc = 2;
   choose_kernel(&tmp, st);
-  if (st.kernel == TN_K_SMALL && (precision != 0)) {
-    // keep the split arithmetic on small diagnostic problems too
+  if (precision != 0 && st.kernel != (precision == 1 ? TN_K_MFMA_F16X3 : TN_K_MFMA_BF16X3)) {
+    // keep the split arithmetic on every diagnostic problem
     st.kernel = precision == 1 ? TN_K_MFMA_F16X3 : TN_K_MFMA_BF16X3;
-    const int lm = std::min(mb, 7), ln = std::min(nb, 6);
-    st.tiles_m_bits = mb - lm;
-    st.tiles_n_bits = nb - ln;
-    st.splits = 1;
-    st.k_split_bits = kb;
-    st.scratch_elems = 0;
-  } else if (st.kernel == TN_K_MFMA_F32 && precision != 0) {
-    st.kernel = precision == 1 ? TN_K_MFMA_F16X3 : TN_K_MFMA_BF16X3;
+    set_tile(&tmp, st, mb >= 7 ? TN_TILE_128x64 : TN_TILE_64x64);
   }
+  const char* tile_env = getenv("TN_GEMM_TILE");
+  if (tile_env && st.kernel != TN_K_SMALL) set_tile(&tmp, st, atoi(tile_env) % TN_N_TILES);
   build_desc(&tmp, st);
   // device scratch: desc, max/exp slots, split partials
   const size_t desc_bytes = (sizeof(GettDesc) + 255) & ~size_t(255);
@@ -1225,11 +1256,12 @@ tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_
     g.expB = reinterpret_cast<int32_t*>(slots + 4);
     g.expC = reinterpret_cast<int32_t*>(slots + 5);
     g.target_exp = (st.kernel == TN_K_MFMA_F16X3 || st.kernel == TN_K_MFMA_BF16X3) ? 14 : 0;
+    g.split_bf16 = precision == TN_PREC_BF16X3 ? 1 : 0;
   }
   const GettDesc* d = dd;
   if (!r) {
     if (st.kernel == TN_K_SMALL) {
-      r = check(tn_launch_gett(TN_K_SMALL, d, g, ((int64_t(1) << (bb + mb + nb)) + 255) / 256, s), "gemm");
+      r = check(tn_launch_gett(TN_K_SMALL, 0, d, g, ((int64_t(1) << (bb + mb + nb)) + 255) / 256, s), "gemm");
     } else {
       g.splits = st.splits;
       g.k_split_bits = st.k_split_bits;
@@ -1239,13 +1271,13 @@ tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_
       if (st.splits > 1) {
         g.scratch = reinterpret_cast<float*>(buf + desc_bytes + slot_bytes);
         g.write_scratch = 1;
-        r = check(tn_launch_gett(st.kernel, d, g, blocks, s), "gemm");
+        r = check(tn_launch_gett(st.kernel, st.tile, d, g, blocks, s), "gemm");
         g.write_scratch = 0;
         if (!r)
-          r = check(tn_launch_gett(TN_K_SPLITK_REDUCE, d, g, ((int64_t(1) << (bb + mb + nb)) + 255) / 256, s),
+          r = check(tn_launch_gett(TN_K_SPLITK_REDUCE, 0, d, g, ((int64_t(1) << (bb + mb + nb)) + 255) / 256, s),
                     "gemm reduce");
       } else {
-        r = check(tn_launch_gett(st.kernel, d, g, blocks, s), "gemm");
+        r = check(tn_launch_gett(st.kernel, st.tile, d, g, blocks, s), "gemm");
       }
     }
   }

@@ -244,3 +244,41 @@ def _rqc30_oracle_slice(sid):
         _ORACLE_CACHE[sid] = contract.contract_slice(net.tensors, net.labels, net.open_labels,
                                                      best["path"], best["sliced"], sid)
     return _ORACLE_CACHE[sid]
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+@pytest.mark.parametrize("prec", ["c64", "f16x3", "bf16x3"])
+@pytest.mark.parametrize("b,m,n,k", [(1, 512, 256, 64), (2, 64, 16, 4096), (1, 256, 8, 32)])
+def test_gemm_every_tile_shape(tile, prec, b, m, n, k, monkeypatch):
+    """Each MFMA tile shape (256x128, 128x128, 128x64, 64x64), with partial tiles and split K."""
+    print(f"gemm tile {tile} {prec} b={b} m={m} n={n} k={k}", flush=True)
+    monkeypatch.setenv("TN_GEMM_TILE", str(tile))
+    rng = np.random.default_rng(tile * 13 + m + k)
+    A, B = _crandn(rng, (b, m, k)), _crandn(rng, (b, k, n))
+    C = torch.zeros((b, m, n), dtype=torch.complex64, device="cuda")
+    tn.tn_gemm(_dev(A), _dev(B), C, precision=prec)
+    got = C.cpu().numpy().astype(np.complex128)
+    ref = np.matmul(A.astype(np.complex128), B.astype(np.complex128))
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err <= GEMM_TOL[prec] * max(1.0, np.sqrt(k / 64)), err
+
+
+@pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
+def test_split_storage_chain_matches_oracle(prec):
+    """Intermediates feeding split-precision steps are stored split; a chain of such steps."""
+    print(f"split chain {prec}", flush=True)
+    rng = np.random.default_rng(9)
+    # X[a(2^8) k1(2^6)] Y[k1(2^6) k2(2^6) b(2^1)] Z[k2(2^6) c(2^6)] W[c(2^6) d(2^5)]
+    shapes = [(256, 64), (64, 64, 2), (64, 64), (64, 32)]
+    tensors = [(_crandn(rng, s) / 4).astype(np.complex128) for s in shapes]
+    labels = [(0, 1), (1, 2, 3), (2, 4), (4, 5)]
+    net = Network(tensors=tensors, labels=labels, open_labels=(0, 3, 5))
+    path = [(0, 1), (0, 2), (0, 3)]
+    ref = contract.amplitudes(net.tensors, net.labels, net.open_labels, path)
+    with tn.Plan(net.tensors, net.labels, net.open_labels, path, (), precision=prec,
+                 split_policy=1) as p:
+        kinds = [s["kernel"] for s in p.steps()]
+        p.contract()
+        got, _ = p.amplitudes()
+    assert kinds.count(2 if prec == "f16x3" else 3) >= 2, kinds
+    assert metrics.rel_l2(got, ref) <= 1e-5 if prec == "f16x3" else 1e-3
