@@ -36,10 +36,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_precision(tn, torch, net, best, prec, steps, warmup, sample_slice):
+def run_precision(tn, torch, net, best, prec, steps, warmup, sample_slice, tuning):
     stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
     plan = tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best["sliced"],
-                   precision=prec, stream=stream, record_steps=True)
+                   precision=prec, stream=stream, record_steps=True, tuning=tuning)
+    plan_s = time.perf_counter() - t0
     info = plan.describe()
     st = plan.steps()
     n_slices = info["n_slices"]
@@ -72,7 +74,15 @@ def run_precision(tn, torch, net, best, prec, steps, warmup, sample_slice):
         d["ms"] += float(ms)
         d["flops"] += s["flops"] * reps
         d["launches"] += int(nl)
-    return {"info": info, "ms_per_step": ms_per_step, "flops_step": flops_step,
+    top = sorted(range(len(st)), key=lambda i: -step_ms[i])[:8]
+    for i in top:
+        s = st[i]
+        reps = steps * (n_slices if s["per_slice"] else 1)
+        tf = s["flops"] * reps / (step_ms[i] * 1e-3) / 1e12 if step_ms[i] > 0 else 0.0
+        log(f"    step {i:3d} {KERNEL_NAME[s['kernel']]:16s} tile {s['tile_m']}x{s['tile_n']} "
+            f"split {s['split_k']:3d} m={s['m']} n={s['n']} k={s['k']} b={s['batch']} "
+            f"{step_ms[i] / steps:8.2f} ms/pass {tf:7.1f} TFLOPS")
+    return {"info": info, "ms_per_step": ms_per_step, "flops_step": flops_step, "plan_s": plan_s,
             "tflops": flops_step / (ms_per_step * 1e-3) / 1e12,
             "slices_per_s": n_slices / (ms_per_step * 1e-3),
             "by_kind": by_kind, "amps": amps, "partial": part}
@@ -107,6 +117,7 @@ def main():
     ap.add_argument("--precisions", default="f16x3,c64")
     ap.add_argument("--sample-slice", type=int, default=137)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning", type=int, default=1, help="1 = autotune tile shapes at plan creation")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: slices are independent sub-tasks and the "
@@ -131,7 +142,7 @@ def main():
     for prec in precs:
         log(f"running {prec}: warmup {args.warmup}, steps {args.steps}")
         runs[prec] = run_precision(tn, torch, net, best, prec, args.steps, args.warmup,
-                                   args.sample_slice)
+                                   args.sample_slice, args.tuning)
         r = runs[prec]
         log(f"  {prec}: {r['ms_per_step']:.1f} ms/step, {r['tflops']:.1f} TFLOPS, "
             f"{r['slices_per_s']:.1f} slices/s")
@@ -168,7 +179,8 @@ def main():
            "slices_per_s": round(main_run["slices_per_s"], 2)}
     for prec, r in runs.items():
         out[prec] = {"tflops": round(r["tflops"], 3), "slices_per_s": round(r["slices_per_s"], 2),
-                     "ms_per_step": round(r["ms_per_step"], 3)}
+                     "ms_per_step": round(r["ms_per_step"], 3),
+                     "plan_and_tuning_s": round(r["plan_s"], 3)}
     if "c64" in runs and head != "c64":
         out["speedup_vs_c64"] = round(runs["c64"]["ms_per_step"] / main_run["ms_per_step"], 3)
         out["rel_l2_vs_c64_full"] = metrics.rel_l2(main_run["amps"], runs["c64"]["amps"])

@@ -75,7 +75,10 @@ typedef struct {
                               1 = split products on every MFMA step */
   int32_t record_steps;    /* 1 = time every step's main kernel launch with HIP events on the
                               plan's stream (read with tn_plan_step_times) */
-  int32_t reserved[6];
+  int32_t tuning;          /* 0 = tile shapes from the shape heuristic; 1 = autotune: time every
+                              MFMA step with each tile shape at plan creation and keep the
+                              fastest (cached per step signature for the life of the process) */
+  int32_t reserved[5];
 } tn_options;
 
 /* Plan summary.  Operation counts follow Sec. 2.4: flops = 8*B*M*N*K per step

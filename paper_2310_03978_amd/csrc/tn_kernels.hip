@@ -262,7 +262,12 @@ __global__ __launch_bounds__(256) void k_gett_small(const GettDesc* __restrict__
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int KB = 16;        // complex k per LDS stage
-constexpr int LDK = KB + 4;   // split: words per LDS row ([row][k] tiles)
+constexpr int LDK = KB;       // split: words per LDS row ([row][k] tiles, 4-word chunks XOR-swizzled)
+
+// Word index of (row, k) in a swizzled [row][16] tile: the 16-byte chunk k/4 is
+// XORed with (row / 4) % 4, so 16 consecutive rows read at one chunk hit 16
+// distinct bank groups.
+__device__ __forceinline__ int swz(int row, int k) { return row * LDK + ((((k >> 2) ^ (row >> 2)) & 3) << 2) + (k & 3); }
 
 template <int P, int WM, int WN>
 struct Tile {
@@ -271,7 +276,8 @@ struct Tile {
   static constexpr int BM = 64 * WM, BN = 64 * WN;
   static constexpr int IA = BM * KB / NT, IB = BN * KB / NT;
   static constexpr int LDA0 = 2 * BM + 2, LDB0 = 2 * BN + 2;   // c64: floats per k row
-  static constexpr int BUF = P == 0 ? KB * LDA0 + KB * LDB0 : 2 * BM * LDK + 2 * BN * LDK;  // words
+  // split: A hi/lo [BM][16]; B hi/lo expanded to real columns [2 BN][16]
+  static constexpr int BUF = P == 0 ? KB * LDA0 + KB * LDB0 : 2 * BM * LDK + 4 * BN * LDK;  // words
   static constexpr int LDC = 2 * BN + 8;                        // epilogue floats per row (64 rows)
   static constexpr int SMEM = 4 * (2 * BUF > 64 * LDC ? 2 * BUF : 64 * LDC);
 };
@@ -288,12 +294,18 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_gett_mfma(const GettDesc* _
   const int wm = w / WN, wn = w % WN;
   const int nbb = d->own_bb + g.chunk_bits;
 
-  // block -> (tile_m, tile_n, batch, split)
+  // block -> (tile_m, tile_n, batch, split).  Blocks are dealt to the 8 XCDs
+  // round-robin; renumber so that each XCD owns a contiguous range, and order
+  // tiles in groups of 4 (m) x 8 (n) so that the blocks resident on one XCD
+  // share A and B panels in that XCD's L2.
   uint64_t bid = blockIdx.x;
-  const uint64_t tile_m = bid & ((1ull << g.tiles_m_bits) - 1);
-  bid >>= g.tiles_m_bits;
-  const uint64_t tile_n = bid & ((1ull << g.tiles_n_bits) - 1);
-  bid >>= g.tiles_n_bits;
+  if ((gridDim.x & 7u) == 0) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
+  const int tmb = g.tiles_m_bits, tnb = g.tiles_n_bits;
+  const uint64_t tix = bid & ((1ull << (tmb + tnb)) - 1);
+  bid >>= tmb + tnb;
+  const int gm = tmb < 2 ? tmb : 2, gn = tnb < 3 ? tnb : 3;
+  const uint64_t tile_m = (tix & ((1ull << gm) - 1)) | (((tix >> (gm + gn)) & ((1ull << (tmb - gm)) - 1)) << gm);
+  const uint64_t tile_n = ((tix >> gm) & ((1ull << gn) - 1)) | ((tix >> (gm + gn + tmb - gm)) << gn);
   const uint64_t bidx = bid & ((1ull << nbb) - 1);
   const int split = (int)(bid >> nbb);
 
@@ -314,21 +326,30 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_gett_mfma(const GettDesc* _
   const int ea_elems = 1 << d->ea.n, eb_elems = 1 << d->eb.n;
   const ThreadEnum ta = thread_part<TB>(d->ea, t);
   const ThreadEnum tb = thread_part<TB>(d->eb, t);
+  // Per-thread element offsets and LDS positions.  Elements beyond a small
+  // operand tile load from offset 0 (always valid) and are not stored, so the
+  // loads are unconditional and stay in flight together.
   int64_t ia_off[IA], ib_off[IB];
-  int ia_pos[IA], ib_pos[IB];
+  int ia_pos[IA], ib_pos[IB], ib_pos2[IB];
+  uint32_t a_valid = 0, b_valid = 0;
 #pragma unroll
   for (int i = 0; i < IA; ++i) {
     const ThreadEnum ip = iter_part<TB>(d->ea, i);
-    ia_off[i] = ta.off + ip.off;
+    const bool ok = t + NT * i < ea_elems;
+    a_valid |= ok ? 1u << i : 0u;
+    ia_off[i] = ok ? ta.off + ip.off : 0;
     const int r = ta.row + ip.row, c = ta.col + ip.col;   // r = m_loc, c = k_loc
-    ia_pos[i] = P == 0 ? c * T::LDA0 + 2 * r : r * LDK + c;
+    ia_pos[i] = P == 0 ? c * T::LDA0 + 2 * r : swz(r, c);
   }
 #pragma unroll
   for (int i = 0; i < IB; ++i) {
     const ThreadEnum ip = iter_part<TB>(d->eb, i);
-    ib_off[i] = tb.off + ip.off;
+    const bool ok = t + NT * i < eb_elems;
+    b_valid |= ok ? 1u << i : 0u;
+    ib_off[i] = ok ? tb.off + ip.off : 0;
     const int r = tb.row + ip.row, c = tb.col + ip.col;   // r = n_loc, c = k_loc
-    ib_pos[i] = P == 0 ? c * T::LDB0 + 2 * r : r * LDK + c;
+    ib_pos[i] = P == 0 ? c * T::LDB0 + 2 * r : swz(2 * r, c);
+    ib_pos2[i] = P == 0 ? 0 : swz(2 * r + 1, c);
   }
 
   floatx16 acc[2][4];
@@ -353,11 +374,9 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_gett_mfma(const GettDesc* _
     const int64_t ak = a_base + bits_offset(k0, d->a_k, d->kb);
     const int64_t bk = b_base + bits_offset(k0, d->b_k, d->kb);
 #pragma unroll
-    for (int i = 0; i < IA; ++i)
-      if (t + NT * i < ea_elems) ra[i] = A[ak + ia_off[i]];
+    for (int i = 0; i < IA; ++i) ra[i] = A[ak + ia_off[i]];
 #pragma unroll
-    for (int i = 0; i < IB; ++i)
-      if (t + NT * i < eb_elems) rb[i] = B[bk + ib_off[i]];
+    for (int i = 0; i < IB; ++i) rb[i] = B[bk + ib_off[i]];
   };
   auto store_stage = [&](uint32_t* buf) {
     if constexpr (P == 0) {
@@ -365,13 +384,13 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_gett_mfma(const GettDesc* _
       float* Bs = As + KB * T::LDA0;
 #pragma unroll
       for (int i = 0; i < IA; ++i)
-        if (t + NT * i < ea_elems) {
+        if ((a_valid >> i) & 1) {
           const float2 v = __builtin_bit_cast(float2, ra[i]);
           *reinterpret_cast<float2*>(As + ia_pos[i]) = make_float2(v.x * sc.fa, v.y * sc.fa);
         }
 #pragma unroll
       for (int i = 0; i < IB; ++i)
-        if (t + NT * i < eb_elems) {
+        if ((b_valid >> i) & 1) {
           const float2 v = __builtin_bit_cast(float2, rb[i]);
           *reinterpret_cast<float2*>(Bs + ib_pos[i]) = make_float2(v.x * sc.fb, v.y * sc.fb);
         }
@@ -379,10 +398,10 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_gett_mfma(const GettDesc* _
       uint32_t* Ah = buf;
       uint32_t* Al = Ah + BM * LDK;
       uint32_t* Bh = Al + BM * LDK;
-      uint32_t* Bl = Bh + BN * LDK;
+      uint32_t* Bl = Bh + 2 * BN * LDK;
 #pragma unroll
       for (int i = 0; i < IA; ++i)
-        if (t + NT * i < ea_elems) {
+        if ((a_valid >> i) & 1) {
           uint2 wv = ra[i];
           if (g.fa != TN_FMT_SPLIT) {
             const float2 v = __builtin_bit_cast(float2, wv);
@@ -391,16 +410,19 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_gett_mfma(const GettDesc* _
           Ah[ia_pos[i]] = wv.x;
           Al[ia_pos[i]] = wv.y;
         }
+      // B as real columns: column 2n holds (Br, -Bi), column 2n+1 holds (Bi, Br)
 #pragma unroll
       for (int i = 0; i < IB; ++i)
-        if (t + NT * i < eb_elems) {
+        if ((b_valid >> i) & 1) {
           uint2 wv = rb[i];
           if (g.fb != TN_FMT_SPLIT) {
             const float2 v = __builtin_bit_cast(float2, wv);
             wv = split_pair(v.x * sc.fb, v.y * sc.fb, bf);
           }
-          Bh[ib_pos[i]] = wv.x;
-          Bl[ib_pos[i]] = wv.y;
+          Bh[ib_pos[i]] = wv.x ^ 0x80000000u;
+          Bh[ib_pos2[i]] = __builtin_amdgcn_alignbit(wv.x, wv.x, 16);
+          Bl[ib_pos[i]] = wv.y ^ 0x80000000u;
+          Bl[ib_pos2[i]] = __builtin_amdgcn_alignbit(wv.y, wv.y, 16);
         }
     }
   };
@@ -409,8 +431,6 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_gett_mfma(const GettDesc* _
   store_stage(smem);
   __syncthreads();
 
-  const int rot = (lane & 1) ? 16 : 0;
-  const uint32_t msk = (lane & 1) ? 0u : 0x80000000u;
   const int c_half = lane >> 5, dd = lane & 1;
   const bool use_im = (c_half ^ dd) != 0;
   const float sgn = (c_half == 1 && dd == 0) ? -1.f : 1.f;
@@ -444,7 +464,7 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_gett_mfma(const GettDesc* _
       const uint32_t* Ah = cur;
       const uint32_t* Al = Ah + BM * LDK;
       const uint32_t* Bh = Al + BM * LDK;
-      const uint32_t* Bl = Bh + BN * LDK;
+      const uint32_t* Bl = Bh + 2 * BN * LDK;
       const int ks_n = lk >= 3 ? (1 << lk) >> 3 : 1;
       for (int ks = 0; ks < ks_n; ++ks) {
         const int kw = ks * 8 + (lane >> 5) * 4;
@@ -452,21 +472,14 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_gett_mfma(const GettDesc* _
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) {
           const int r = wm * 64 + mi * 32 + (lane & 31);
-          ah[mi] = *reinterpret_cast<const u32x4*>(Ah + r * LDK + kw);
-          al[mi] = *reinterpret_cast<const u32x4*>(Al + r * LDK + kw);
+          ah[mi] = *reinterpret_cast<const u32x4*>(Ah + swz(r, kw));
+          al[mi] = *reinterpret_cast<const u32x4*>(Al + swz(r, kw));
         }
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) {
-          const int r = wn * 64 + ni * 16 + ((lane & 31) >> 1);
-          u32x4 x = *reinterpret_cast<const u32x4*>(Bh + r * LDK + kw);
-          u32x4 y = *reinterpret_cast<const u32x4*>(Bl + r * LDK + kw);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            x[q] = __builtin_amdgcn_alignbit(x[q], x[q], rot) ^ msk;
-            y[q] = __builtin_amdgcn_alignbit(y[q], y[q], rot) ^ msk;
-          }
-          bh[ni] = x;
-          bl[ni] = y;
+          const int r = wn * 128 + ni * 32 + (lane & 31);   // real column
+          bh[ni] = *reinterpret_cast<const u32x4*>(Bh + swz(r, kw));
+          bl[ni] = *reinterpret_cast<const u32x4*>(Bl + swz(r, kw));
         }
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi)

@@ -26,6 +26,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
 #include <string>
 #include <vector>
@@ -86,8 +87,7 @@ struct Step {
   int tiles_m_bits = 0, tiles_n_bits = 0;
   int a_contig = 0, b_contig = 0;
   double flops = 0, bytes = 0;
-  int64_t scratch_off = -1;          // elements in the step's arena
-  int64_t scratch_elems = 0;
+  int64_t scratch_elems = 0;         // split-K partials (elements)
   GettDesc desc;
 };
 
@@ -174,6 +174,8 @@ struct tn_plan_s {
   double* d_acc = nullptr;
   double* d_part = nullptr;        // [S][n_amp] complex128 partials
   int32_t* d_flag = nullptr;
+  float* d_scratch = nullptr;      // split-K partials, shared by all steps (one stream)
+  int64_t scratch_elems = 0;
   int64_t slices_acc = 0;
   size_t device_bytes = 0;
 
@@ -190,7 +192,8 @@ struct tn_plan_s {
   ~tn_plan_s() {
     if (stream) hipStreamSynchronize(stream);
     else if (!host_only) hipDeviceSynchronize();
-    void* ptrs[] = {d_leaves, d_inv, d_ps, d_desc, d_max_inv, d_max_ps, d_exp_inv, d_exp_ps, d_acc, d_part, d_flag};
+    void* ptrs[] = {d_leaves, d_inv, d_ps, d_desc, d_max_inv, d_max_ps, d_exp_inv, d_exp_ps, d_acc, d_part, d_flag,
+                    d_scratch};
     for (void* p : ptrs)
       if (p) hipFree(p);
     for (auto& t : pending) event_pool.push_back({t.start, t.stop});
@@ -400,7 +403,8 @@ tn_status validate_bounds(const tn_plan_s* p) {
     }
     if (st.kernel != TN_K_SMALL && st.splits > 1) {
       const int64_t need = int64_t(st.splits) << (d.nbb + d.mb + d.nb);
-      if (need > st.scratch_elems) return fail(TN_E_STATE, "internal: split-K scratch too small");
+      if (need > st.scratch_elems || (!p->host_only && need > p->scratch_elems))
+        return fail(TN_E_STATE, "internal: split-K scratch too small");
     }
   }
   return TN_OK;
@@ -451,6 +455,8 @@ tn_status permute_bits(const std::vector<int>& in_pos, const std::vector<int>& o
   if (st) return st;
   return check(hipStreamSynchronize(s), "permute sync");
 }
+
+tn_status autotune(tn_plan_s* p);
 
 tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, const int32_t* const* labels,
                      const int64_t* const* extents, const double* const* data, int32_t n_open,
@@ -722,8 +728,6 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
     Tensor& C = p->tensors[st.tc];
     C.arena = 1;
     C.offset = inv.alloc(C.elems);
-    if (st.scratch_elems) st.scratch_off = inv.alloc(st.scratch_elems);
-    if (st.scratch_elems) inv.release(st.scratch_off, st.scratch_elems);
     for (int x : {st.ta, st.tb}) {
       Tensor& X = p->tensors[x];
       if (!X.leaf && X.arena == 1) inv.release(X.offset, X.elems);
@@ -735,8 +739,6 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
     Tensor& C = p->tensors[st.tc];
     C.arena = 2;
     C.offset = ps.alloc(C.elems * S);
-    if (st.scratch_elems) st.scratch_off = ps.alloc(st.scratch_elems);
-    if (st.scratch_elems) ps.release(st.scratch_off, st.scratch_elems);
     for (int x : {st.ta, st.tb}) {
       Tensor& X = p->tensors[x];
       if (!X.leaf && X.arena == 2) ps.release(X.offset, X.elems * S);
@@ -746,6 +748,7 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
   p->ps_elems = std::max<int64_t>(ps.peak, 64);
   for (auto& st : p->steps) build_desc(p, st);
   p->S = (int)S;
+  for (auto& st : p->steps) p->scratch_elems = std::max(p->scratch_elems, st.scratch_elems);
   if (tn_status vb = validate_bounds(p)) return vb;
   if (p->host_only) return TN_OK;
 
@@ -772,6 +775,7 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
   if ((st = dmalloc((void**)&p->d_acc, p->n_amp * 16))) return st;
   if ((st = dmalloc((void**)&p->d_part, p->n_amp * 16 * S))) return st;
   if ((st = dmalloc((void**)&p->d_flag, 64))) return st;
+  if (p->scratch_elems > 0 && (st = dmalloc((void**)&p->d_scratch, p->scratch_elems * 8))) return st;
   if ((st = check(hipMemsetAsync(p->d_acc, 0, p->n_amp * 16, s), "memset acc"))) return st;
   if ((st = check(hipMemsetAsync(p->d_flag, 0, 64, s), "memset flag"))) return st;
   if ((st = check(hipMemsetAsync(p->d_max_inv, 0, nt * 4, s), "memset max"))) return st;
@@ -842,6 +846,14 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
   st = check(hipStreamSynchronize(s), "setup sync");
   hipFree(d_stage);
   p->device_bytes -= max_leaf * 8;
+  if (st) return st;
+  if (p->opts.tuning == 1) {
+    // timing runs read the (zeroed) arenas before any real data is there
+    if ((st = check(hipMemsetAsync(p->d_inv, 0, p->inv_elems * 8, s), "arena clear"))) return st;
+    if ((st = check(hipMemsetAsync(p->d_ps, 0, p->ps_elems * 8, s), "arena clear"))) return st;
+    if ((st = check(hipMemsetAsync(p->d_max_ps, 0, nt * S * 4, s), "max clear"))) return st;
+    st = autotune(p);
+  }
   return st;
 }
 
@@ -929,8 +941,7 @@ tn_status run_step(tn_plan_s* p, int s, int64_t chunk_base, int chunk_bits) {
   g.tiles_n_bits = st.tiles_n_bits;
   const int64_t blocks = (int64_t(st.splits)) << (st.tiles_m_bits + st.tiles_n_bits + bbits);
   if (st.splits > 1) {
-    float* base = st.per_slice ? p->d_ps : p->d_inv;
-    g.scratch = base + 2 * st.scratch_off;
+    g.scratch = p->d_scratch;
     g.write_scratch = 1;
     tn_status r = timed_launch(p, s, st.kernel, d, g, blocks, "mfma step");
     if (r) return r;
@@ -939,6 +950,108 @@ tn_status run_step(tn_plan_s* p, int s, int64_t chunk_base, int chunk_bits) {
     return check(tn_launch_gett(TN_K_SPLITK_REDUCE, 0, d, g, (total + 255) / 256, p->stream), "split-K reduce");
   }
   return timed_launch(p, s, st.kernel, d, g, blocks, "mfma step");
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: time each MFMA step with every tile shape on the device and keep
+// the fastest.  Choices are cached per step signature for the process.
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+
+std::string step_signature(const tn_plan_s* p, const Step& st) {
+  char buf[160];
+  const Tensor& A = p->tensors[st.ta];
+  const Tensor& B = p->tensors[st.tb];
+  const Tensor& C = p->tensors[st.tc];
+  snprintf(buf, sizeof(buf), "k%d b%d m%d n%d k%d s%d f%d%d%d c%d%d", st.kernel,
+           (int)st.bb.size() + (st.per_slice ? p->s_bits : 0), (int)st.mb.size(), (int)st.nb.size(),
+           (int)st.kb.size(), st.per_slice ? 1 : 0, A.fmt, B.fmt, C.fmt, st.a_contig, st.b_contig);
+  return buf;
+}
+
+tn_status ensure_scratch(tn_plan_s* p, int64_t elems) {
+  if (elems <= p->scratch_elems) return TN_OK;
+  tn_status st = check(hipStreamSynchronize(p->stream), "scratch sync");
+  if (st) return st;
+  if (p->d_scratch) {
+    hipFree(p->d_scratch);
+    p->device_bytes -= p->scratch_elems * 8;
+    p->d_scratch = nullptr;
+  }
+  if (hipMalloc((void**)&p->d_scratch, elems * 8) != hipSuccess) {
+    hipGetLastError();
+    p->scratch_elems = 0;
+    return fail(TN_E_NOMEM, "split-K scratch allocation failed");
+  }
+  p->device_bytes += elems * 8;
+  p->scratch_elems = elems;
+  return TN_OK;
+}
+
+tn_status apply_tile(tn_plan_s* p, int s, int tile) {
+  Step& st = p->steps[s];
+  set_tile(p, st, tile);
+  build_desc(p, st);
+  tn_status r = ensure_scratch(p, st.scratch_elems);
+  if (r) return r;
+  return check(hipMemcpyAsync(p->d_desc + s, &st.desc, sizeof(GettDesc), hipMemcpyHostToDevice, p->stream),
+               "desc upload");
+}
+
+tn_status autotune(tn_plan_s* p) {
+  hipEvent_t e0, e1;
+  tn_status r = check(hipEventCreate(&e0), "event");
+  if (r) return r;
+  if ((r = check(hipEventCreate(&e1), "event"))) {
+    hipEventDestroy(e0);
+    return r;
+  }
+  const int keep_record = p->opts.record_steps;
+  p->opts.record_steps = 0;
+  for (size_t s = 0; s < p->steps.size() && !r; ++s) {
+    Step& st = p->steps[s];
+    if (st.kernel == TN_K_SMALL) continue;
+    const std::string sig = step_signature(p, st);
+    int cached = -1;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_cache.find(sig);
+      if (it != g_tune_cache.end()) cached = it->second;
+    }
+    if (cached >= 0) {
+      r = apply_tile(p, (int)s, cached);
+      continue;
+    }
+    const int bits = st.per_slice ? p->s_bits : 0;
+    int best = st.tile;
+    float best_ms = 1e30f;
+    for (int tile = 0; tile < TN_N_TILES && !r; ++tile) {
+      if ((r = apply_tile(p, (int)s, tile))) break;
+      if ((r = run_step(p, (int)s, 0, bits))) break;   // warm-up
+      if ((r = check(hipEventRecord(e0, p->stream), "event"))) break;
+      for (int rep = 0; rep < 2 && !r; ++rep) r = run_step(p, (int)s, 0, bits);
+      if (r || (r = check(hipEventRecord(e1, p->stream), "event"))) break;
+      if ((r = check(hipEventSynchronize(e1), "event sync"))) break;
+      float ms = 0.f;
+      if ((r = check(hipEventElapsedTime(&ms, e0, e1), "event time"))) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = tile;
+      }
+    }
+    if (!r) r = apply_tile(p, (int)s, best);
+    if (!r) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune_cache[sig] = best;
+    }
+  }
+  p->opts.record_steps = keep_record;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (!r) r = check(hipStreamSynchronize(p->stream), "tuning sync");
+  if (!r) r = validate_bounds(p);
+  return r;
 }
 
 tn_status run_invariant(tn_plan_s* p) {

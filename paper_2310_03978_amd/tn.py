@@ -45,7 +45,7 @@ class tn_options(ctypes.Structure):
                 ("mem_cap_elems", ctypes.c_int64), ("stream", ctypes.c_void_p),
                 ("slice_batch", ctypes.c_int32), ("host_only", ctypes.c_int32),
                 ("split_policy", ctypes.c_int32), ("record_steps", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("tuning", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class tn_plan_info(ctypes.Structure):
@@ -128,7 +128,8 @@ def _stream_handle(stream):
 
 def tn_plan_create(tensors, labels, open_labels, path, sliced_labels=(), precision="c64",
                    mem_cap_elems: int = 0, stream=None, slice_batch: int = 0,
-                   host_only: bool = False, split_policy: int = 0, record_steps: bool = False):
+                   host_only: bool = False, split_policy: int = 0, record_steps: bool = False,
+                   tuning: int = 0):
     """Create a plan; returns an opaque handle (int).  Leaves are copied."""
     n = len(labels)
     ranks = (ctypes.c_int32 * n)(*[len(l) for l in labels])
@@ -167,6 +168,7 @@ def tn_plan_create(tensors, labels, open_labels, path, sliced_labels=(), precisi
     opts.host_only = 1 if host_only else 0
     opts.split_policy = int(split_policy)
     opts.record_steps = 1 if record_steps else 0
+    opts.tuning = int(tuning)
     handle = ctypes.c_void_p()
     status = _lib.tn_plan_create(ctypes.byref(handle), n, ranks, lab_pp, ext_pp, data_pp,
                                  len(open_labels), op, len(path), pa, len(sliced_labels), sl,

@@ -282,3 +282,20 @@ def test_split_storage_chain_matches_oracle(prec):
         got, _ = p.amplitudes()
     assert kinds.count(2 if prec == "f16x3" else 3) >= 2, kinds
     assert metrics.rel_l2(got, ref) <= 1e-5 if prec == "f16x3" else 1e-3
+
+
+@pytest.mark.parametrize("prec", ["c64", "f16x3"])
+def test_autotuned_plan_matches_oracle(prec):
+    """tuning=1 times every tile shape per MFMA step at plan creation; results still match."""
+    print(f"autotune {prec}", flush=True)
+    rng = np.random.default_rng(21)
+    shapes = [(512, 256), (256, 128, 2), (128, 64)]
+    tensors = [(_crandn(rng, s) / 4).astype(np.complex128) for s in shapes]
+    net = Network(tensors=tensors, labels=[(0, 1), (1, 2, 3), (2, 4)], open_labels=(0, 3, 4))
+    path = [(0, 1), (0, 2)]
+    ref = contract.amplitudes(net.tensors, net.labels, net.open_labels, path)
+    with tn.Plan(net.tensors, net.labels, net.open_labels, path, (), precision=prec,
+                 split_policy=1, tuning=1) as p:
+        p.contract()
+        got, _ = p.amplitudes()
+    assert metrics.rel_l2(got, ref) <= TOL[prec]
