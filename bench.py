@@ -108,6 +108,29 @@ def cpu_baseline(net, best, sample_slice, flops_slice):
                            f"tensordot along the same path; flops counted as for the GPU"}
 
 
+def counter_run(tn, torch, net, best, precs):
+    """One chunk of slices per precision plus a plain copy of known size.
+
+    Meant to run under rocprofv3 --pmc: the copy (an identity permutation of
+    2^26 complex64 = 512 MiB read and 512 MiB written) calibrates FETCH_SIZE and
+    WRITE_SIZE against known byte counts.
+    """
+    stream = torch.cuda.current_stream()
+    for prec in precs:
+        with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best["sliced"],
+                     precision=prec, stream=stream) as plan:
+            info = plan.describe()
+            plan.contract(0, info["slice_batch"])
+            plan.amplitudes()
+            log(f"counter run {prec}: one chunk of {info['slice_batch']} slices")
+    n = 1 << 26
+    x = torch.zeros(n, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    tn.tn_permute(x.view(1 << 13, 1 << 13), [0, 1], y)
+    torch.cuda.synchronize()
+    log(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +141,8 @@ def main():
     ap.add_argument("--sample-slice", type=int, default=137)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", type=int, default=1, help="1 = autotune tile shapes at plan creation")
+    ap.add_argument("--counter-run", action="store_true",
+                    help="one chunk per precision and a calibration copy, for rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: slices are independent sub-tasks and the "
@@ -138,6 +163,9 @@ def main():
     w = configs.WORKLOADS[args.workload]
     log(f"workload {args.workload}: {w.description}; path found in {time.perf_counter() - t0:.1f}s")
     precs = [p for p in args.precisions.split(",") if p]
+    if args.counter_run:
+        counter_run(tn, torch, net, best, precs)
+        return
     runs = {}
     for prec in precs:
         log(f"running {prec}: warmup {args.warmup}, steps {args.steps}")

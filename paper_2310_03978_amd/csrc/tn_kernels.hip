@@ -427,73 +427,82 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_gett_mfma(const GettDesc* _
     }
   };
 
-  load_stage(0);
-  store_stage(smem);
-  __syncthreads();
-
   const int c_half = lane >> 5, dd = lane & 1;
   const bool use_im = (c_half ^ dd) != 0;
   const float sgn = (c_half == 1 && dd == 0) ? -1.f : 1.f;
 
+  // One K step of 8 complex (split) from the LDS stage `cur`.
+  auto mfma_ks = [&](const uint32_t* cur, int ks) {
+    const uint32_t* Ah = cur;
+    const uint32_t* Al = Ah + BM * LDK;
+    const uint32_t* Bh = Al + BM * LDK;
+    const uint32_t* Bl = Bh + 2 * BN * LDK;
+    const int kw = ks * 8 + (lane >> 5) * 4;
+    u32x4 ah[2], al[2], bh[4], bl[4];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi) {
+      const int r = wm * 64 + mi * 32 + (lane & 31);
+      ah[mi] = *reinterpret_cast<const u32x4*>(Ah + swz(r, kw));
+      al[mi] = *reinterpret_cast<const u32x4*>(Al + swz(r, kw));
+    }
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) {
+      const int r = wn * 128 + ni * 32 + (lane & 31);   // real column
+      bh[ni] = *reinterpret_cast<const u32x4*>(Bh + swz(r, kw));
+      bl[ni] = *reinterpret_cast<const u32x4*>(Bl + swz(r, kw));
+    }
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(ah[mi], bh[ni], acc[mi][ni]);
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(ah[mi], bl[ni], acc[mi][ni]);
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(al[mi], bh[ni], acc[mi][ni]);
+  };
+  // One complex k (FP32 MFMA) from the LDS stage `cur`.
+  auto mfma_kk = [&](const uint32_t* cur, int kk) {
+    const float* As = reinterpret_cast<const float*>(cur);
+    const float* Bs = As + KB * T::LDA0;
+    float a[2], b[4];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi) a[mi] = As[kk * T::LDA0 + 2 * (wm * 64 + mi * 32 + (lane & 31)) + c_half];
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) {
+      const float2 bv = *reinterpret_cast<const float2*>(Bs + kk * T::LDB0 + 2 * (wn * 64 + ni * 16 + ((lane & 31) >> 1)));
+      b[ni] = sgn * (use_im ? bv.y : bv.x);
+    }
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni)
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+  };
+
+  // Pipeline: stage k+1 is requested into registers, stage k is multiplied
+  // from LDS, then stage k+1 is written to the other LDS buffer.  One barrier
+  // per stage.
+  load_stage(0);
+  store_stage(smem);
+  __syncthreads();
+
   for (int64_t kit = 0; kit < n_iters; ++kit) {
-    uint32_t* cur = smem + (kit & 1) * T::BUF;
+    const uint32_t* cur = smem + (kit & 1) * T::BUF;
     uint32_t* nxt = smem + ((kit + 1) & 1) * T::BUF;
     const bool more = kit + 1 < n_iters;
     if (more) load_stage(kit + 1);
     if constexpr (P == 0) {
-      const float* As = reinterpret_cast<const float*>(cur);
-      const float* Bs = As + KB * T::LDA0;
-      const int kk_n = 1 << lk;
-      for (int kk = 0; kk < kk_n; ++kk) {
-        float a[2], b[4];
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi) a[mi] = As[kk * T::LDA0 + 2 * (wm * 64 + mi * 32 + (lane & 31)) + c_half];
-#pragma unroll
-        for (int ni = 0; ni < 4; ++ni) {
-          const float2 bv =
-              *reinterpret_cast<const float2*>(Bs + kk * T::LDB0 + 2 * (wn * 64 + ni * 16 + ((lane & 31) >> 1)));
-          b[ni] = sgn * (use_im ? bv.y : bv.x);
-        }
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-          for (int ni = 0; ni < 4; ++ni)
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
-      }
+#pragma unroll 1
+      for (int kk = 0; kk < (1 << lk); ++kk) mfma_kk(cur, kk);
     } else {
-      const uint32_t* Ah = cur;
-      const uint32_t* Al = Ah + BM * LDK;
-      const uint32_t* Bh = Al + BM * LDK;
-      const uint32_t* Bl = Bh + 2 * BN * LDK;
-      const int ks_n = lk >= 3 ? (1 << lk) >> 3 : 1;
-      for (int ks = 0; ks < ks_n; ++ks) {
-        const int kw = ks * 8 + (lane >> 5) * 4;
-        u32x4 ah[2], al[2], bh[4], bl[4];
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi) {
-          const int r = wm * 64 + mi * 32 + (lane & 31);
-          ah[mi] = *reinterpret_cast<const u32x4*>(Ah + swz(r, kw));
-          al[mi] = *reinterpret_cast<const u32x4*>(Al + swz(r, kw));
-        }
-#pragma unroll
-        for (int ni = 0; ni < 4; ++ni) {
-          const int r = wn * 128 + ni * 32 + (lane & 31);   // real column
-          bh[ni] = *reinterpret_cast<const u32x4*>(Bh + swz(r, kw));
-          bl[ni] = *reinterpret_cast<const u32x4*>(Bl + swz(r, kw));
-        }
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-          for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(ah[mi], bh[ni], acc[mi][ni]);
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-          for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(ah[mi], bl[ni], acc[mi][ni]);
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-          for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(al[mi], bh[ni], acc[mi][ni]);
-      }
+      // K < 16: one step of 8, columns beyond K are zero
+      const int ks_n = lk == 4 ? 2 : 1;
+#pragma unroll 1
+      for (int ks = 0; ks < ks_n; ++ks) mfma_ks(cur, ks);
     }
     if (more) store_stage(nxt);
     __syncthreads();
