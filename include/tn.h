@@ -35,6 +35,7 @@ extern "C" {
 #endif
 
 typedef struct tn_plan_s* tn_plan;
+typedef struct tn_group_s* tn_group;
 
 typedef enum {
   TN_OK = 0,
@@ -109,6 +110,8 @@ typedef struct {
   int32_t tile_m, tile_n;      /* output tile in complex elements */
   int32_t a_contig, b_contig;  /* log2 of the contiguous run (elements) of A and B along the tile */
   double flops, bytes;
+  int32_t tile;                /* tile id (0..3, see TN_N_TILE_SHAPES) of an MFMA step; -1 for the small kernel */
+  int32_t reserved;
 } tn_step_info;
 
 /* Build a plan.
@@ -148,8 +151,9 @@ tn_status tn_plan_steps(tn_plan plan, tn_step_info* steps, int32_t cap);
 /* Per-step kernel times recorded since the last call (options.record_steps = 1):
  * synchronises the stream, then writes for step i < cap the summed duration in
  * milliseconds of its main kernel launches (ms_total[i], may be NULL) and their
- * number (launches[i], may be NULL), and clears the record.  Split-K reduction
- * launches are not included.  TN_E_STATE if recording is off. */
+ * number (launches[i], may be NULL), and clears the record.  A step split along K
+ * is timed from its main launch to the end of its reduction launch.  TN_E_STATE if
+ * recording is off. */
 tn_status tn_plan_step_times(tn_plan plan, double* ms_total, int64_t* launches, int32_t cap);
 
 /* Contract slices [first_slice, first_slice + n_slices) and ADD their amplitudes into the
@@ -176,6 +180,106 @@ tn_status tn_accumulator_set(tn_plan plan, const double* acc, int64_t n_amp,
 
 /* Zero the accumulator and the slice count. */
 tn_status tn_reset(tn_plan plan);
+
+/* Batching form: many independent contractions -- slice ranges of one network and
+ * many small, uneven sub-networks -- submitted as ONE replay of a captured hipGraph
+ * (Sec. 4.1 batched execution; slices and sub-networks are independent sub-tasks,
+ * Sec. 3.2).  The group captures, once per set of ranges, every plan's kernel chain
+ * (its slice-independent steps, then per chunk of slices its slice-dependent steps
+ * and the FP64 cross-slice sum) into one graph whose parallel branches each run
+ * the chains of a subset of the plans in sequence.  Plans go to branches by
+ * longest-processing-time-first on their flop counts, so branches carry similar
+ * work; branches run concurrently on the device.  Every kernel is the one the plan
+ * runs on its own, with the plan's own tiles, so a group adds exactly what
+ * tn_contract_slices on each plan adds.
+ *
+ * tn_group_create: plans[0..n) must be device plans of one precision; they stay
+ *   owned by the caller and must outlive the group, and must not be used for
+ *   contraction concurrently with it.  opts may be NULL; opts->stream orders the
+ *   group after and before the caller's stream; opts->slice_batch, when > 0, is the
+ *   number of graph branches (default min(n, 8)).
+ * tn_group_contract: for every plan i, contracts slices [first[i], first[i] +
+ *   count[i]) and ADDS them into plan i's accumulator, like tn_contract_slices.
+ *   Asynchronous; read results with tn_amplitudes on each plan.  The graph is
+ *   captured on the first call with a given set of ranges and replayed (one
+ *   hipGraphLaunch) on later calls with the same ranges.
+ * tn_group_describe: kernel nodes and branches of the graph of the last call. */
+tn_status tn_group_create(tn_group* out, const tn_plan* plans, int32_t n_plans, const tn_options* opts);
+tn_status tn_group_contract(tn_group group, const int64_t* first, const int64_t* count);
+tn_status tn_group_describe(tn_group group, int64_t* n_kernels, int32_t* n_branches);
+void tn_group_destroy(tn_group group);
+
+/* ---- Learned step-time cost model ----
+ * The paper orders contraction candidates by their measured time on the device
+ * (Sec. 4.1) and scores trees with a cost that weighs compute and memory
+ * traffic (Sec. 3.2).  Here a small MLP learns the time of one kernel launch of
+ * a step from that step's shape, layout and kernel configuration, trained on
+ * the library's own timings; it picks tile shapes without timing every
+ * candidate, and can score whole plans (e.g. candidate slicings, planned on the
+ * host only).
+ *
+ * Features (TN_COST_FEATURES floats per (step, tile)), in this order:
+ *   0 batch bits (own + slice-local chunk bits)   1 m bits   2 n bits   3 k bits
+ *   4 log2 flops per launch   5 log2 operand+result bytes per launch   6 (4) - (5)
+ *   7 tile-grid m bits   8 tile-grid n bits   9 log2 K splits   10 log2 blocks per launch
+ *   11 slice-dependent step   12..15 kernel one-hot (small, FP32 MFMA, split FP16, split BF16)
+ *   16..19 tile one-hot (256x128, 128x128, 128x64, 64x64; all 0 for the small kernel)
+ *   20 contiguous run bits of A's tile   21 of B's tile   22 of C's tile
+ *   23..25 split storage of A, B, C   26 min(0, m bits - tile m bits)
+ *   27 min(0, n bits - tile n bits)   28 log2 K stages (16 complex each) per split
+ * The target is ln(microseconds per launch). */
+#define TN_COST_FEATURES 29
+#define TN_N_TILE_SHAPES 4 /* tile ids 0..3: 256x128, 128x128, 128x64, 64x64 complex */
+
+typedef struct tn_costmodel_s* tn_costmodel;
+
+/* Features of step `step` run with tile id `tile` (-1 = the step's current tile) into
+ * out[0..TN_COST_FEATURES); cap must be >= TN_COST_FEATURES.  Works on host-only plans.
+ * The tile id is ignored for steps on the small kernel.  TN_E_ARG on a bad step or tile. */
+tn_status tn_plan_step_features(tn_plan plan, int32_t step, int32_t tile, float* out, int32_t cap);
+
+/* Run MFMA step `step` with tile id `tile` from now on (the K split follows the tile).
+ * TN_E_ARG for a step on the small kernel or a bad tile id.  Device plans: may grow the
+ * split-K scratch buffer; ordered on the plan's stream. */
+tn_status tn_plan_set_tile(tn_plan plan, int32_t step, int32_t tile);
+
+/* Choose every MFMA step's tile as the argmin of the model's predicted time over the
+ * tile ids and apply it (tn_plan_set_tile).  predicted_us (may be NULL; cap entries)
+ * receives the predicted microseconds per launch of every step with its chosen tile.
+ * The model must have TN_COST_FEATURES inputs.  Works on host-only plans. */
+tn_status tn_plan_tune_with_model(tn_plan plan, tn_costmodel model, float* predicted_us, int32_t cap);
+
+/* MLP with n_features inputs (1..32), two hidden layers of 64 ReLU units and one output,
+ * FP32, trained with MSE loss and Adam (beta1 0.9, beta2 0.999, eps 1e-8) by the library's
+ * HIP kernels (forward, per-sample deltas, per-weight gradient sums in sample order, Adam).
+ * Parameters are one flat FP32 array: W1 [64 x F] row-major, b1 [64], W2 [64 x 64], b2 [64],
+ * w3 [64], b3.  Inputs are standardised as (x - mean) / std before the first layer.
+ * create: He-uniform weights from a counter-based generator (splitmix64) seeded by `seed`,
+ *   zero biases, mean 0, std 1.  All calls are synchronous and use the null stream. */
+tn_status tn_costmodel_create(tn_costmodel* out, int32_t n_features, uint64_t seed);
+void tn_costmodel_destroy(tn_costmodel model);
+tn_status tn_costmodel_describe(tn_costmodel model, int32_t* n_features, int32_t* hidden,
+                                int64_t* n_params);
+/* mean, std: n_features host floats each; std must be > 0. */
+tn_status tn_costmodel_set_normalization(tn_costmodel model, const float* mean, const float* std);
+/* n must equal n_params.  set_params also clears the Adam moments and step count. */
+tn_status tn_costmodel_get_params(tn_costmodel model, float* out, int64_t n);
+tn_status tn_costmodel_set_params(tn_costmodel model, const float* params, int64_t n);
+/* y[i] = model(X[i]) for n rows of X (host, row-major [n x n_features]). */
+tn_status tn_costmodel_predict(tn_costmodel model, const float* X, int64_t n, float* y);
+/* Gradient of the mean squared error over n samples (host X [n x F], t [n]) into grad
+ * (n_params floats, may be NULL) and the loss into *loss (may be NULL); parameters unchanged. */
+tn_status tn_costmodel_gradient(tn_costmodel model, const float* X, const float* t, int64_t n,
+                                float* grad, float* loss);
+/* One Adam update of the parameters with the given gradient (n_params host floats). */
+tn_status tn_costmodel_adam_step(tn_costmodel model, const float* grad, int64_t n, float lr);
+/* Minibatch training: `epochs` passes over the n samples in an order shuffled per epoch
+ * (Fisher-Yates driven by splitmix64 of `seed`), one Adam step per batch of `batch`
+ * samples (the last batch of an epoch may be smaller).  *final_loss (may be NULL) receives
+ * the MSE over all n samples after training. */
+tn_status tn_costmodel_train(tn_costmodel model, const float* X, const float* t, int64_t n,
+                             int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                             float* final_loss);
 
 /* Diagnostic entry points on caller-owned device memory (complex64 interleaved),
  * asynchronous on `stream` (hipStream_t or NULL).  They run the same kernels as plan

@@ -10,11 +10,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libtnmi.so")
-SOURCES = ["tn_kernels.hip", "tn_plan.cpp"]
+SOURCES = ["tn_kernels.hip", "tn_plan.cpp", "tn_costmodel.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-result"]
+         "-Wno-unused-result", "-Wno-unused-value"]
 
 
 def build(verbose: bool = False) -> str:

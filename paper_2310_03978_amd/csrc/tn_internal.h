@@ -82,3 +82,7 @@ struct ReduceArgs {
   int64_t n_amp;
   int32_t n_slices;             // slices in this chunk
 };
+
+// Detail text for tn_last_error_message() on the calling thread (defined with the planner).
+void tn_set_error_detail(const char* msg);
+

@@ -11,7 +11,9 @@ enum {
   TN_K_MFMA_F32 = 1,
   TN_K_MFMA_F16X3 = 2,
   TN_K_MFMA_BF16X3 = 3,
-  TN_K_SPLITK_REDUCE = 4
+  TN_K_SPLITK_REDUCE = 4,
+  TN_K_SLICE_REDUCE = 5,
+  TN_K_FILL = 6
 };
 
 // MFMA tile shapes (complex outputs per block, waves)
@@ -43,3 +45,4 @@ hipError_t tn_launch_absmax(const void* x, int64_t n, uint32_t* dst, hipStream_t
 hipError_t tn_launch_fill_u32(void* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t tn_launch_scale_pow2(void* x, int64_t n, const int32_t* e, hipStream_t s);
 void tn_tile_shape(int tile, int* bm, int* bn, int* threads);
+hipError_t tn_prepare_kernels();

@@ -207,12 +207,13 @@ __device__ __forceinline__ ThreadEnum iter_part(const TileEnum& en, int it) {
 // ---------------------------------------------------------------------------
 // Small steps: one thread per element of C, enumerated in C's storage order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gett_small(const GettDesc* __restrict__ d, GettArgs g) {
-  __shared__ uint32_t red[8];
+__device__ __forceinline__ int block_bits() { return blockDim.x == 512 ? 9 : blockDim.x == 256 ? 8 : 7; }
+
+__device__ void gett_small_block(const GettDesc* __restrict__ d, const GettArgs& g, int64_t block, uint32_t* red) {
   const int nbb = d->own_bb + g.chunk_bits;
   const int cbits = d->c_nbits + g.chunk_bits;
   const int64_t total = (int64_t)1 << cbits;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = block * blockDim.x + threadIdx.x;
   uint32_t mx = 0;
   int sl = 0;
   if (e < total) {
@@ -248,13 +249,18 @@ __global__ __launch_bounds__(256) void k_gett_small(const GettDesc* __restrict__
     if (g.scale_mode && m == 0 && n == 0 && (bidx & own_mask) == 0) write_exp(g, sl, sc);
   }
   if (g.maxC) {
-    if (d->c_nbits >= 8) {
+    if (d->c_nbits >= block_bits()) {
       // the whole block lies in one slice
-      block_umax_atomic(mx, g.maxC + (g.c_ps ? (int)(((int64_t)blockIdx.x * blockDim.x) >> d->c_nbits) : 0), red);
+      block_umax_atomic(mx, g.maxC + (g.c_ps ? (int)((block * blockDim.x) >> d->c_nbits) : 0), red);
     } else if (e < total) {
       atomicMax(g.maxC + (g.c_ps ? sl : 0), mx);
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_gett_small(const GettDesc* __restrict__ d, GettArgs g) {
+  __shared__ uint32_t red[8];
+  gett_small_block(d, g, blockIdx.x, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -283,23 +289,19 @@ struct Tile {
 };
 }  // namespace
 
+// One output tile of an MFMA step; `bid` is the step's block index.
 template <int P, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN, 2) void k_gett_mfma(const GettDesc* __restrict__ d, GettArgs g) {
+__device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g, uint64_t bid, uint32_t* smem,
+                               uint32_t* red) {
   using T = Tile<P, WM, WN>;
   constexpr int NT = T::NT, TB = T::TB, BM = T::BM, BN = T::BN, IA = T::IA, IB = T::IB;
-  extern __shared__ __align__(16) uint32_t smem[];
-  __shared__ uint32_t red[16];
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int wm = w / WN, wn = w % WN;
   const int nbb = d->own_bb + g.chunk_bits;
 
-  // block -> (tile_m, tile_n, batch, split).  Blocks are dealt to the 8 XCDs
-  // round-robin; renumber so that each XCD owns a contiguous range, and order
-  // tiles in groups of 4 (m) x 8 (n) so that the blocks resident on one XCD
-  // share A and B panels in that XCD's L2.
-  uint64_t bid = blockIdx.x;
-  if ((gridDim.x & 7u) == 0) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
+  // block -> (tile_m, tile_n, batch, split): tiles in groups of 4 (m) x 8 (n)
+  // so that blocks resident together share A and B panels in L2.
   const int tmb = g.tiles_m_bits, tnb = g.tiles_n_bits;
   const uint64_t tix = bid & ((1ull << (tmb + tnb)) - 1);
   bid >>= tmb + tnb;
@@ -574,15 +576,25 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_gett_mfma(const GettDesc* _
   }
 }
 
+template <int P, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN, 2) void k_gett_mfma(const GettDesc* __restrict__ d, GettArgs g) {
+  extern __shared__ __align__(16) uint32_t smem[];
+  __shared__ uint32_t red[16];
+  // Blocks are dealt to the 8 XCDs round-robin; renumber so that each XCD owns
+  // a contiguous range of tiles (and so shares panels in its own L2).
+  uint64_t bid = blockIdx.x;
+  if ((gridDim.x & 7u) == 0) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
+  gett_mfma_tile<P, WM, WN>(d, g, bid, smem, red);
+}
+
 // ---------------------------------------------------------------------------
 // Split-K reduction: C[e] = sum_s partial[s][b][m][n] in increasing s.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_splitk_reduce(const GettDesc* __restrict__ d, GettArgs g) {
-  __shared__ uint32_t red[8];
+__device__ void splitk_reduce_block(const GettDesc* __restrict__ d, const GettArgs& g, int64_t block, uint32_t* red) {
   const int nbb = d->own_bb + g.chunk_bits;
   const int cbits = d->c_nbits + g.chunk_bits;
   const int64_t total = (int64_t)1 << cbits;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = block * blockDim.x + threadIdx.x;
   uint32_t mx = 0;
   int sl = 0;
   if (e < total) {
@@ -613,12 +625,17 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const GettDesc* __restric
     if (g.scale_mode && m == 0 && n == 0 && (bidx & own_mask) == 0) write_exp(g, sl, sc);
   }
   if (g.maxC) {
-    if (d->c_nbits >= 8) {
-      block_umax_atomic(mx, g.maxC + (g.c_ps ? (int)(((int64_t)blockIdx.x * blockDim.x) >> d->c_nbits) : 0), red);
+    if (d->c_nbits >= block_bits()) {
+      block_umax_atomic(mx, g.maxC + (g.c_ps ? (int)((block * blockDim.x) >> d->c_nbits) : 0), red);
     } else if (e < total) {
       atomicMax(g.maxC + (g.c_ps ? sl : 0), mx);
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_splitk_reduce(const GettDesc* __restrict__ d, GettArgs g) {
+  __shared__ uint32_t red[8];
+  splitk_reduce_block(d, g, blockIdx.x, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -659,8 +676,8 @@ __global__ __launch_bounds__(256) void k_permute(const PermDesc* __restrict__ p,
 // ---------------------------------------------------------------------------
 // FP64 cross-slice sum (or per-slice partials) with the slice exponents.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_slice_reduce(ReduceArgs r) {
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void slice_reduce_block(const ReduceArgs& r, int64_t block) {
+  const int64_t o = block * blockDim.x + threadIdx.x;
   if (o >= r.n_amp) return;
   const float2* root = reinterpret_cast<const float2*>(r.root);
   bool bad = false;
@@ -689,6 +706,8 @@ __global__ __launch_bounds__(256) void k_slice_reduce(ReduceArgs r) {
   if (bad) atomicOr(r.flag, 1);
 }
 
+__global__ __launch_bounds__(256) void k_slice_reduce(ReduceArgs r) { slice_reduce_block(r, blockIdx.x); }
+
 // max(|re|, |im|) over a buffer, as float bits
 __global__ __launch_bounds__(256) void k_absmax(const float2* __restrict__ x, int64_t n, uint32_t* dst) {
   __shared__ uint32_t red[8];
@@ -709,10 +728,12 @@ __global__ void k_scale_pow2(float2* __restrict__ x, int64_t n, const int32_t* _
   }
 }
 
-__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fill_block(uint32_t* p, uint32_t v, int64_t n, int64_t block) {
+  const int64_t i = block * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) { fill_block(p, v, n, blockIdx.x); }
 
 // ---------------------------------------------------------------------------
 // Launchers
@@ -721,13 +742,8 @@ namespace {
 template <int P, int WM, int WN>
 hipError_t launch_mfma(const GettDesc* d, const GettArgs& g, int64_t blocks, hipStream_t s) {
   using T = Tile<P, WM, WN>;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gett_mfma<P, WM, WN>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, T::SMEM);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  hipError_t e = tn_prepare_kernels();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_gett_mfma<P, WM, WN>), dim3((unsigned)blocks), dim3(T::NT), T::SMEM, s, d, g);
   return hipGetLastError();
 }
@@ -792,6 +808,24 @@ hipError_t tn_launch_scale_pow2(void* x, int64_t n, const int32_t* e, hipStream_
   const int64_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(k_scale_pow2, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<float2*>(x), n, e);
   return hipGetLastError();
+}
+
+// Set the dynamic-LDS limit of every MFMA kernel instance (before any launch
+// is captured into a graph: attributes are not stream operations).
+hipError_t tn_prepare_kernels() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* f, int bytes) {
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  };
+#define TN_SET_ATTR(P, WM, WN) set(reinterpret_cast<const void*>(&k_gett_mfma<P, WM, WN>), Tile<P, WM, WN>::SMEM)
+  TN_SET_ATTR(0, 4, 2); TN_SET_ATTR(0, 2, 2); TN_SET_ATTR(0, 2, 1); TN_SET_ATTR(0, 1, 1);
+  TN_SET_ATTR(1, 4, 2); TN_SET_ATTR(1, 2, 2); TN_SET_ATTR(1, 2, 1); TN_SET_ATTR(1, 1, 1);
+  TN_SET_ATTR(2, 4, 2); TN_SET_ATTR(2, 2, 2); TN_SET_ATTR(2, 2, 1); TN_SET_ATTR(2, 1, 1);
+#undef TN_SET_ATTR
+  if (e == hipSuccess) done = true;
+  return e;
 }
 
 void tn_tile_shape(int tile, int* bm, int* bn, int* threads) {

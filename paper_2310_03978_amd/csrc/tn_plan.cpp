@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -43,6 +44,12 @@ tn_status fail(tn_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
+
+}  // namespace
+
+void tn_set_error_detail(const char* msg) { g_err = msg ? msg : ""; }
+
+namespace {
 
 int ilog2_exact(int64_t v) {
   if (v < 1) return -1;
@@ -364,10 +371,10 @@ void choose_kernel(tn_plan_s* p, Step& st) {
 // Every address a kernel forms is a sum of per-bit strides.  Check, for every
 // step and operand, that the largest reachable offset stays inside its buffer
 // and that no two bits share a non-zero stride.
-tn_status validate_bounds(const tn_plan_s* p) {
+tn_status validate_steps(const tn_plan_s* p, const std::vector<Step>& steps) {
   const int64_t S = int64_t(1) << p->s_bits;
-  for (size_t s = 0; s < p->steps.size(); ++s) {
-    const Step& st = p->steps[s];
+  for (size_t s = 0; s < steps.size(); ++s) {
+    const Step& st = steps[s];
     const GettDesc& d = st.desc;
     struct Op {
       const Tensor* T;
@@ -409,6 +416,8 @@ tn_status validate_bounds(const tn_plan_s* p) {
   }
   return TN_OK;
 }
+
+tn_status validate_bounds(const tn_plan_s* p) { return validate_steps(p, p->steps); }
 
 tn_status check(hipError_t e, const char* what) {
   if (e != hipSuccess) return fail(TN_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -871,10 +880,17 @@ int64_t leaf_chunk_offset(const tn_plan_s* p, const Tensor& T, int64_t base, int
   return off;
 }
 
+// Main launch of step s, followed by its split-K reduction when `rg` is set; with
+// record_steps both are bracketed by one pair of events (the step's time).
 tn_status timed_launch(tn_plan_s* p, int s, int kind, const GettDesc* d, const GettArgs& g, int64_t blocks,
-                       const char* what) {
+                       const char* what, const GettArgs* rg, int64_t rblocks) {
   const int tile = p->steps[s].tile;
-  if (!p->opts.record_steps) return check(tn_launch_gett(kind, tile, d, g, blocks, p->stream), what);
+  auto launch = [&]() -> tn_status {
+    tn_status r = check(tn_launch_gett(kind, tile, d, g, blocks, p->stream), what);
+    if (!r && rg) r = check(tn_launch_gett(TN_K_SPLITK_REDUCE, 0, d, *rg, rblocks, p->stream), "split-K reduce");
+    return r;
+  };
+  if (!p->opts.record_steps) return launch();
   std::pair<hipEvent_t, hipEvent_t> ev;
   if (!p->event_pool.empty()) {
     ev = p->event_pool.back();
@@ -885,18 +901,41 @@ tn_status timed_launch(tn_plan_s* p, int s, int kind, const GettDesc* d, const G
     if (st) return st;
   }
   tn_status st = check(hipEventRecord(ev.first, p->stream), "event record");
-  if (!st) st = check(tn_launch_gett(kind, tile, d, g, blocks, p->stream), what);
+  if (!st) st = launch();
   if (!st) st = check(hipEventRecord(ev.second, p->stream), "event record");
   p->pending.push_back({s, ev.first, ev.second});
   return st;
 }
 
-tn_status run_step(tn_plan_s* p, int s, int64_t chunk_base, int chunk_bits) {
-  Step& st = p->steps[s];
+// One launch-equivalent of the contraction: a kernel launch in the ordinary
+// path, an instance of the persistent executor in a group.
+struct Launch {
+  int kind = TN_K_SMALL;
+  int tile = 0;
+  int step = -1;           // step index for a step's main launch (timed), else -1
+  const GettDesc* desc = nullptr;
+  GettArgs g{};
+  ReduceArgs r{};
+  uint32_t* fill_ptr = nullptr;
+  int64_t fill_n = 0;
+  int64_t elems = 0;       // element-wise kinds: elements covered
+  int64_t blocks = 0;      // MFMA kinds: tile blocks
+  int64_t nblocks(int threads) const {
+    return (kind == TN_K_MFMA_F32 || kind == TN_K_MFMA_F16X3 || kind == TN_K_MFMA_BF16X3)
+               ? blocks
+               : (elems + threads - 1) / threads;
+  }
+};
+
+// Launches of step `st` (descriptor d) for one chunk: the main launch and, with
+// split K, its reduction.
+void step_launches(const tn_plan_s* p, const Step& st, const GettDesc* d, int s, int64_t chunk_base, int chunk_bits,
+                   std::vector<Launch>& out) {
   const Tensor& A = p->tensors[st.ta];
   const Tensor& B = p->tensors[st.tb];
   const Tensor& C = p->tensors[st.tc];
-  GettArgs g;
+  Launch L;
+  GettArgs& g = L.g;
   memset(&g, 0, sizeof(g));
   g.A = tensor_ptr(p, A) + 2 * (A.leaf ? leaf_chunk_offset(p, A, chunk_base, chunk_bits) : 0);
   g.B = tensor_ptr(p, B) + 2 * (B.leaf ? leaf_chunk_offset(p, B, chunk_base, chunk_bits) : 0);
@@ -929,27 +968,126 @@ tn_status run_step(tn_plan_s* p, int s, int64_t chunk_base, int chunk_bits) {
   g.fb = B.fmt;
   g.fc = C.fmt;
   g.split_bf16 = p->precision == TN_PREC_BF16X3 ? 1 : 0;
-  const GettDesc* d = p->d_desc + s;
-  const int bbits = (int)st.bb.size() + g.chunk_bits;
+  L.desc = d;
+  L.step = s;
+  L.kind = st.kernel;
+  L.tile = st.tile;
+  const int64_t c_total = int64_t(1) << (C.bits.size() + g.chunk_bits);
   if (st.kernel == TN_K_SMALL) {
-    const int64_t total = int64_t(1) << (C.bits.size() + g.chunk_bits);
-    return timed_launch(p, s, TN_K_SMALL, d, g, (total + 255) / 256, "small step");
+    L.elems = c_total;
+    out.push_back(L);
+    return;
   }
+  const int bbits = (int)st.bb.size() + g.chunk_bits;
   g.splits = st.splits;
   g.k_split_bits = st.k_split_bits;
   g.tiles_m_bits = st.tiles_m_bits;
   g.tiles_n_bits = st.tiles_n_bits;
-  const int64_t blocks = (int64_t(st.splits)) << (st.tiles_m_bits + st.tiles_n_bits + bbits);
+  L.blocks = (int64_t(st.splits)) << (st.tiles_m_bits + st.tiles_n_bits + bbits);
   if (st.splits > 1) {
     g.scratch = p->d_scratch;
     g.write_scratch = 1;
-    tn_status r = timed_launch(p, s, st.kernel, d, g, blocks, "mfma step");
-    if (r) return r;
-    g.write_scratch = 0;
-    const int64_t total = int64_t(1) << (C.bits.size() + g.chunk_bits);
-    return check(tn_launch_gett(TN_K_SPLITK_REDUCE, 0, d, g, (total + 255) / 256, p->stream), "split-K reduce");
+    out.push_back(L);
+    Launch R = L;
+    R.g.write_scratch = 0;
+    R.kind = TN_K_SPLITK_REDUCE;
+    R.step = -1;
+    R.elems = c_total;
+    out.push_back(R);
+    return;
   }
-  return timed_launch(p, s, st.kernel, d, g, blocks, "mfma step");
+  out.push_back(L);
+}
+
+Launch fill_launch(uint32_t* ptr, int64_t n) {
+  Launch L;
+  L.kind = TN_K_FILL;
+  L.fill_ptr = ptr;
+  L.fill_n = n;
+  L.elems = n;
+  return L;
+}
+
+// Launches of the slice-independent phase.
+void invariant_launches(const tn_plan_s* p, const std::vector<Step>& steps, const GettDesc* d_desc,
+                        std::vector<Launch>& out) {
+  if (scaled(p)) {
+    const int64_t nt = (int64_t)p->tensors.size();
+    if (nt > p->n_leaves) out.push_back(fill_launch(p->d_max_inv + p->n_leaves, nt - p->n_leaves));
+  }
+  for (int s : p->inv_order) step_launches(p, steps[s], d_desc + s, s, 0, 0, out);
+}
+
+// Launches of one chunk of 2^bits slices starting at base (aligned); the chunk
+// ends by adding into the accumulator, or writing partials when partial_out is set.
+void chunk_launches(const tn_plan_s* p, const std::vector<Step>& steps, const GettDesc* d_desc, int64_t base,
+                    int bits, double* partial_out, std::vector<Launch>& out) {
+  if (scaled(p) && !p->ps_order.empty())
+    out.push_back(fill_launch(p->d_max_ps, (int64_t)p->tensors.size() * p->S));
+  for (int s : p->ps_order) step_launches(p, steps[s], d_desc + s, s, base, bits, out);
+  const Tensor& R = p->tensors[p->root];
+  Launch L;
+  L.kind = TN_K_SLICE_REDUCE;
+  ReduceArgs& r = L.r;
+  memset(&r, 0, sizeof(r));
+  r.root = tensor_ptr(p, R);
+  if (scaled(p)) r.exp = R.per_slice ? p->d_exp_ps + (int64_t)p->root * p->S : p->d_exp_inv + p->root;
+  r.acc = p->d_acc;
+  r.out = partial_out;
+  r.flag = p->d_flag;
+  r.n_amp = p->n_amp;
+  r.n_slices = 1 << bits;
+  L.elems = p->n_amp;
+  out.push_back(L);
+}
+
+// Aligned power-of-two chunks of [first, first + n), each at most 2^s_bits slices.
+std::vector<std::pair<int64_t, int>> chunks_of(const tn_plan_s* p, int64_t first, int64_t n) {
+  std::vector<std::pair<int64_t, int>> out;
+  int64_t cur = first;
+  const int64_t end = first + n;
+  while (cur < end) {
+    int bits = 0;
+    while (bits < p->s_bits && (cur & ((int64_t(2) << bits) - 1)) == 0 && cur + (int64_t(2) << bits) <= end) ++bits;
+    out.push_back({cur, bits});
+    cur += int64_t(1) << bits;
+  }
+  return out;
+}
+
+// Issue launches on stream `st`; with `timed` (the plan's own stream only), step
+// launches are bracketed by events when options.record_steps is set.
+tn_status execute_on(tn_plan_s* p, const std::vector<Launch>& ls, hipStream_t st, bool timed) {
+  for (size_t i = 0; i < ls.size(); ++i) {
+    const Launch& L = ls[i];
+    tn_status r = TN_OK;
+    if (timed && L.step >= 0 && L.kind != TN_K_SMALL && i + 1 < ls.size() && ls[i + 1].kind == TN_K_SPLITK_REDUCE) {
+      const Launch& R = ls[++i];
+      r = timed_launch(p, L.step, L.kind, L.desc, L.g, L.nblocks(256), "step", &R.g, R.nblocks(256));
+      if (r) return r;
+      continue;
+    }
+    switch (L.kind) {
+      case TN_K_FILL: r = check(tn_launch_fill_u32(L.fill_ptr, 0, L.fill_n, st), "fill"); break;
+      case TN_K_SLICE_REDUCE: r = check(tn_launch_slice_reduce(L.r, st), "slice reduce"); break;
+      case TN_K_SPLITK_REDUCE:
+        r = check(tn_launch_gett(TN_K_SPLITK_REDUCE, 0, L.desc, L.g, L.nblocks(256), st), "split-K reduce");
+        break;
+      default:
+        r = (timed && L.step >= 0) ? timed_launch(p, L.step, L.kind, L.desc, L.g, L.nblocks(256), "step", nullptr, 0)
+                                   : check(tn_launch_gett(L.kind, L.tile, L.desc, L.g, L.nblocks(256), st), "step");
+    }
+    if (r) return r;
+  }
+  return TN_OK;
+}
+
+tn_status execute(tn_plan_s* p, const std::vector<Launch>& ls) { return execute_on(p, ls, p->stream, true); }
+
+tn_status run_step(tn_plan_s* p, int s, int64_t chunk_base, int chunk_bits) {
+  std::vector<Launch> ls;
+  step_launches(p, p->steps[s], p->d_desc + s, s, chunk_base, chunk_bits, ls);
+  return execute(p, ls);
 }
 
 // ---------------------------------------------------------------------------
@@ -1054,38 +1192,61 @@ tn_status autotune(tn_plan_s* p) {
   return r;
 }
 
-tn_status run_invariant(tn_plan_s* p) {
-  tn_status st;
-  if (scaled(p)) {
-    const int64_t nt = (int64_t)p->tensors.size();
-    if ((st = check(tn_launch_fill_u32(p->d_max_inv + p->n_leaves, 0, nt - p->n_leaves, p->stream), "fill")))
-      return st;
+// Cost-model features of a step run with `tile` (layout in include/tn.h).
+void step_features(const tn_plan_s* p, const Step& st0, int tile, float* f) {
+  Step st = st0;
+  const bool mfma = st.kernel != TN_K_SMALL;
+  if (mfma && tile >= 0 && tile != st.tile) {
+    set_tile(p, st, tile);
+    build_desc(const_cast<tn_plan_s*>(p), st);
   }
-  for (int s : p->inv_order)
-    if ((st = run_step(p, s, 0, 0))) return st;
-  return TN_OK;
+  const Tensor& A = p->tensors[st.ta];
+  const Tensor& B = p->tensors[st.tb];
+  const Tensor& C = p->tensors[st.tc];
+  const int bb = (int)st.bb.size() + (st.per_slice ? p->s_bits : 0);
+  const int mb = (int)st.mb.size(), nb = (int)st.nb.size(), kb = (int)st.kb.size();
+  for (int i = 0; i < TN_COST_FEATURES; ++i) f[i] = 0.f;
+  f[0] = (float)bb;
+  f[1] = (float)mb;
+  f[2] = (float)nb;
+  f[3] = (float)kb;
+  f[4] = (float)(3 + bb + mb + nb + kb);
+  const double elems = std::ldexp(1.0, bb + mb + kb) + std::ldexp(1.0, bb + kb + nb) + std::ldexp(1.0, bb + mb + nb);
+  f[5] = (float)std::log2(8.0 * elems);
+  f[6] = f[4] - f[5];
+  f[11] = st.per_slice ? 1.f : 0.f;
+  f[12 + std::min(std::max(st.kernel, 0), 3)] = 1.f;
+  if (mfma) {
+    int bm = 128, bn = 128, nt = 256;
+    tn_tile_shape(st.tile, &bm, &bn, &nt);
+    const int sb = ilog2_exact(st.splits);
+    f[7] = (float)st.tiles_m_bits;
+    f[8] = (float)st.tiles_n_bits;
+    f[9] = (float)sb;
+    f[10] = (float)(bb + st.tiles_m_bits + st.tiles_n_bits + sb);
+    f[16 + st.tile] = 1.f;
+    f[20] = (float)st.a_contig;
+    f[21] = (float)st.b_contig;
+    f[22] = (float)contig_run(st.desc.ec);
+    f[26] = (float)std::min(0, mb - ilog2_exact(bm));
+    f[27] = (float)std::min(0, nb - ilog2_exact(bn));
+    f[28] = (float)(st.k_split_bits - 4);
+  } else {
+    // one thread per output element in blocks of 256
+    f[10] = (float)std::max(0, bb + mb + nb - 8);
+  }
+  f[23] = A.fmt == TN_FMT_SPLIT ? 1.f : 0.f;
+  f[24] = B.fmt == TN_FMT_SPLIT ? 1.f : 0.f;
+  f[25] = C.fmt == TN_FMT_SPLIT ? 1.f : 0.f;
 }
 
-// One chunk of 2^bits slices starting at base (aligned); reduce into acc or write partials.
-tn_status run_chunk(tn_plan_s* p, int64_t base, int bits, double* partial_out) {
-  tn_status st;
-  if (scaled(p) && !p->ps_order.empty()) {
-    if ((st = check(tn_launch_fill_u32(p->d_max_ps, 0, (int64_t)p->tensors.size() * p->S, p->stream), "fill")))
-      return st;
-  }
-  for (int s : p->ps_order)
-    if ((st = run_step(p, s, base, bits))) return st;
-  const Tensor& R = p->tensors[p->root];
-  ReduceArgs r;
-  memset(&r, 0, sizeof(r));
-  r.root = tensor_ptr(p, R);
-  if (scaled(p)) r.exp = R.per_slice ? p->d_exp_ps + (int64_t)p->root * p->S : p->d_exp_inv + p->root;
-  r.acc = p->d_acc;
-  r.out = partial_out;
-  r.flag = p->d_flag;
-  r.n_amp = p->n_amp;
-  r.n_slices = 1 << bits;
-  return check(tn_launch_slice_reduce(r, p->stream), "slice reduce");
+// Re-tile one MFMA step; device plans also upload its descriptor.
+tn_status retile_step(tn_plan_s* p, int s, int tile) {
+  if (!p->host_only) return apply_tile(p, s, tile);
+  Step& st = p->steps[s];
+  set_tile(p, st, tile);
+  build_desc(p, st);
+  return TN_OK;
 }
 
 }  // namespace
@@ -1190,6 +1351,7 @@ tn_status tn_plan_steps(tn_plan p, tn_step_info* steps, int32_t cap) {
     o.b_contig = st.b_contig;
     o.flops = st.flops;
     o.bytes = st.bytes;
+    o.tile = st.kernel == TN_K_SMALL ? -1 : st.tile;
   }
   return TN_OK;
 }
@@ -1220,20 +1382,72 @@ tn_status tn_plan_step_times(tn_plan p, double* ms_total, int64_t* launches, int
   return TN_OK;
 }
 
+tn_status tn_plan_step_features(tn_plan p, int32_t step, int32_t tile, float* out, int32_t cap) {
+  if (!p || !out || cap < TN_COST_FEATURES) return fail(TN_E_ARG, "bad arguments");
+  if (step < 0 || step >= (int32_t)p->steps.size()) return fail(TN_E_ARG, "step out of range");
+  if (tile < -1 || tile >= TN_N_TILES) return fail(TN_E_ARG, "tile id out of range");
+  step_features(p, p->steps[step], tile, out);
+  return TN_OK;
+}
+
+tn_status tn_plan_set_tile(tn_plan p, int32_t step, int32_t tile) {
+  if (!p) return fail(TN_E_ARG, "null plan");
+  if (step < 0 || step >= (int32_t)p->steps.size()) return fail(TN_E_ARG, "step out of range");
+  if (tile < 0 || tile >= TN_N_TILES) return fail(TN_E_ARG, "tile id out of range");
+  if (p->steps[step].kernel == TN_K_SMALL) return fail(TN_E_ARG, "step runs on the small kernel (no tile)");
+  tn_status st = retile_step(p, step, tile);
+  if (!st) st = validate_steps(p, p->steps);
+  return st;
+}
+
+tn_status tn_plan_tune_with_model(tn_plan p, tn_costmodel model, float* predicted_us, int32_t cap) {
+  if (!p || !model) return fail(TN_E_ARG, "null argument");
+  int32_t nf = 0;
+  tn_status st = tn_costmodel_describe(model, &nf, nullptr, nullptr);
+  if (st) return st;
+  if (nf != TN_COST_FEATURES) return fail(TN_E_ARG, "model must take the step features as input");
+  const int n = (int)p->steps.size();
+  // every (step, tile) candidate in one batch; small-kernel steps get one row
+  std::vector<float> X;
+  std::vector<std::pair<int, int>> rows;
+  for (int s = 0; s < n; ++s) {
+    const bool mfma = p->steps[s].kernel != TN_K_SMALL;
+    for (int t = 0; t < (mfma ? TN_N_TILES : 1); ++t) {
+      const size_t o = X.size();
+      X.resize(o + TN_COST_FEATURES);
+      step_features(p, p->steps[s], mfma ? t : -1, X.data() + o);
+      rows.push_back({s, mfma ? t : -1});
+    }
+  }
+  std::vector<float> y(rows.size());
+  if ((st = tn_costmodel_predict(model, X.data(), (int64_t)rows.size(), y.data()))) return st;
+  std::vector<int> best(n, -1);
+  std::vector<float> best_y(n, 1e30f);
+  for (size_t r = 0; r < rows.size(); ++r) {
+    const int s = rows[r].first;
+    if (y[r] < best_y[s]) {
+      best_y[s] = y[r];
+      best[s] = rows[r].second;
+    }
+  }
+  for (int s = 0; s < n && !st; ++s)
+    if (best[s] >= 0 && best[s] != p->steps[s].tile) st = retile_step(p, s, best[s]);
+  if (!st) st = validate_steps(p, p->steps);
+  if (!st && predicted_us)
+    for (int s = 0; s < n && s < cap; ++s) predicted_us[s] = std::exp(best_y[s]);
+  return st;
+}
+
 tn_status tn_contract_slices(tn_plan p, int64_t first, int64_t n) {
   if (!p) return fail(TN_E_ARG, "null plan");
   if (p->host_only) return fail(TN_E_STATE, "host-only plan");
   if (first < 0 || n < 0 || first + n > p->n_slices) return fail(TN_E_SLICE, "slice range out of bounds");
   if (n == 0) return TN_OK;
-  tn_status st = run_invariant(p);
+  std::vector<Launch> ls;
+  invariant_launches(p, p->steps, p->d_desc, ls);
+  for (auto& c : chunks_of(p, first, n)) chunk_launches(p, p->steps, p->d_desc, c.first, c.second, nullptr, ls);
+  tn_status st = execute(p, ls);
   if (st) return st;
-  int64_t cur = first, end = first + n;
-  while (cur < end) {
-    int bits = 0;
-    while (bits < p->s_bits && (cur & ((int64_t(2) << bits) - 1)) == 0 && cur + (int64_t(2) << bits) <= end) ++bits;
-    if ((st = run_chunk(p, cur, bits, nullptr))) return st;
-    cur += int64_t(1) << bits;
-  }
   p->slices_acc += n;
   return TN_OK;
 }
@@ -1244,10 +1458,14 @@ tn_status tn_slice_partials(tn_plan p, const int64_t* ids, int64_t n, double* ou
   for (int64_t i = 0; i < n; ++i)
     if (ids[i] < 0 || ids[i] >= p->n_slices) return fail(TN_E_SLICE, "slice id out of range");
   if (n == 0) return TN_OK;
-  tn_status st = run_invariant(p);
+  std::vector<Launch> ls;
+  invariant_launches(p, p->steps, p->d_desc, ls);
+  tn_status st = execute(p, ls);
   if (st) return st;
   for (int64_t i = 0; i < n; ++i) {
-    if ((st = run_chunk(p, ids[i], 0, p->d_part))) return st;
+    ls.clear();
+    chunk_launches(p, p->steps, p->d_desc, ids[i], 0, p->d_part, ls);
+    if ((st = execute(p, ls))) return st;
     if ((st = check(hipMemcpyAsync(out + 2 * p->n_amp * i, p->d_part, p->n_amp * 16, hipMemcpyDeviceToHost, p->stream),
                     "partials copy")))
       return st;
@@ -1296,6 +1514,202 @@ tn_status tn_reset(tn_plan p) {
   p->slices_acc = 0;
   return check(hipStreamSynchronize(p->stream), "reset sync");
 }
+
+// ---------------------------------------------------------------------------
+// Batching form (tn_group_*)
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct tn_group_s {
+  std::vector<tn_plan_s*> plans;
+  int precision = 0;
+  int n_branches = 1;
+  hipStream_t stream = nullptr;              // capture and replay stream
+  hipStream_t user_stream = nullptr;
+  std::vector<hipStream_t> branch;           // fork streams used while capturing
+  std::vector<hipEvent_t> branch_done;
+  hipEvent_t fork = nullptr, ev = nullptr;
+  struct Cached {
+    std::vector<int64_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t n_kernels = 0;
+    int32_t n_branches = 0;
+  };
+  std::vector<Cached> cache;
+  int64_t last_kernels = 0;
+  int32_t last_branches = 0;
+
+  ~tn_group_s() {
+    if (stream) hipStreamSynchronize(stream);
+    for (auto& c : cache) {
+      if (c.exec) hipGraphExecDestroy(c.exec);
+      if (c.graph) hipGraphDestroy(c.graph);
+    }
+    for (auto e : branch_done)
+      if (e) hipEventDestroy(e);
+    for (auto b : branch)
+      if (b) hipStreamDestroy(b);
+    if (fork) hipEventDestroy(fork);
+    if (ev) hipEventDestroy(ev);
+    if (stream) hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+// Capture every plan's launch chain for the ranges in `key` into one graph:
+// plans are assigned to branches longest-processing-time first (by flops),
+// each branch runs its plans' chains in sequence, branches fork from and join
+// into the group stream.
+tn_status group_build(tn_group_s* G, const std::vector<int64_t>& key, tn_group_s::Cached& C) {
+  const int P = (int)G->plans.size();
+  std::vector<std::vector<Launch>> chains(P);
+  std::vector<std::pair<double, int>> work;
+  for (int i = 0; i < P; ++i) {
+    tn_plan_s* p = G->plans[i];
+    const int64_t first = key[2 * i], n = key[2 * i + 1];
+    if (n == 0) continue;
+    invariant_launches(p, p->steps, p->d_desc, chains[i]);
+    for (auto& c : chunks_of(p, first, n)) chunk_launches(p, p->steps, p->d_desc, c.first, c.second, nullptr, chains[i]);
+    work.push_back({p->flops_inv + p->flops_ps * (double)n + 1.0, i});
+  }
+  std::sort(work.begin(), work.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+    return a.first != b.first ? a.first > b.first : a.second < b.second;
+  });
+  const int B = std::max(1, std::min<int>(G->n_branches, (int)work.size()));
+  std::vector<double> load(B, 0.0);
+  std::vector<std::vector<int>> assign(B);
+  for (auto& w : work) {
+    const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[b] += w.first;
+    assign[b].push_back(w.second);
+  }
+  C.key = key;
+  C.n_kernels = 0;
+  C.n_branches = B;
+  tn_status st = check(hipStreamBeginCapture(G->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  if (st) return st;
+  st = check(hipEventRecord(G->fork, G->stream), "fork");
+  for (int b = 0; b < B && !st; ++b) {
+    st = check(hipStreamWaitEvent(G->branch[b], G->fork, 0), "fork wait");
+    for (int i : assign[b]) {
+      if (st) break;
+      st = execute_on(G->plans[i], chains[i], G->branch[b], false);
+      C.n_kernels += (int64_t)chains[i].size();
+    }
+    if (!st) st = check(hipEventRecord(G->branch_done[b], G->branch[b]), "join");
+    if (!st) st = check(hipStreamWaitEvent(G->stream, G->branch_done[b], 0), "join wait");
+  }
+  hipGraph_t graph = nullptr;
+  const tn_status end = check(hipStreamEndCapture(G->stream, &graph), "end capture");
+  if (st || end) {
+    if (graph) hipGraphDestroy(graph);
+    return st ? st : end;
+  }
+  C.graph = graph;
+  return check(hipGraphInstantiate(&C.exec, graph, nullptr, nullptr, 0), "graph instantiate");
+}
+
+}  // namespace
+
+extern "C" {
+
+tn_status tn_group_create(tn_group* out, const tn_plan* plans, int32_t n, const tn_options* opts) {
+  if (!out || !plans || n < 1) return fail(TN_E_ARG, "bad arguments");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) return fail(TN_E_ARG, "null plan");
+    if (plans[i]->host_only) return fail(TN_E_STATE, "host-only plan in a group");
+    if (plans[i]->precision != plans[0]->precision) return fail(TN_E_ARG, "plans of a group must share a precision");
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return fail(TN_E_ARG, "a plan appears twice in a group");
+  }
+  if (opts && opts->struct_size < (int32_t)offsetof(tn_options, reserved))
+    return fail(TN_E_ARG, "tn_options.struct_size too small");
+  tn_group_s* G = new (std::nothrow) tn_group_s();
+  if (!G) return fail(TN_E_NOMEM, "host allocation failed");
+  G->precision = plans[0]->precision;
+  G->n_branches = std::min(n, 8);
+  if (opts) {
+    G->user_stream = reinterpret_cast<hipStream_t>(opts->stream);
+    if (opts->slice_batch > 0) G->n_branches = std::min<int>(opts->slice_batch, n);
+  }
+  for (int i = 0; i < n; ++i) G->plans.push_back(plans[i]);
+  tn_status st = check(tn_prepare_kernels(), "kernel attributes");
+  if (!st) st = check(hipStreamCreateWithFlags(&G->stream, hipStreamNonBlocking), "group stream");
+  if (!st) st = check(hipEventCreateWithFlags(&G->ev, hipEventDisableTiming), "group event");
+  if (!st) st = check(hipEventCreateWithFlags(&G->fork, hipEventDisableTiming), "group event");
+  for (int b = 0; b < G->n_branches && !st; ++b) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    st = check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "branch stream");
+    if (!st) G->branch.push_back(s);
+    if (!st) st = check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "branch event");
+    if (!st) G->branch_done.push_back(e);
+  }
+  if (st) {
+    std::string keep = g_err;
+    delete G;
+    g_err = keep;
+    return st;
+  }
+  *out = G;
+  return TN_OK;
+}
+
+tn_status tn_group_contract(tn_group G, const int64_t* first, const int64_t* count) {
+  if (!G || !first || !count) return fail(TN_E_ARG, "bad arguments");
+  const int P = (int)G->plans.size();
+  std::vector<int64_t> key(2 * P);
+  for (int i = 0; i < P; ++i) {
+    if (first[i] < 0 || count[i] < 0 || first[i] + count[i] > G->plans[i]->n_slices)
+      return fail(TN_E_SLICE, "slice range out of bounds for plan " + std::to_string(i));
+    key[2 * i] = first[i];
+    key[2 * i + 1] = count[i];
+  }
+  tn_group_s::Cached* C = nullptr;
+  for (auto& c : G->cache)
+    if (c.key == key) C = &c;
+  if (!C) {
+    G->cache.emplace_back();
+    C = &G->cache.back();
+    tn_status st = group_build(G, key, *C);
+    if (st) {
+      G->cache.pop_back();
+      return st;
+    }
+  }
+  G->last_kernels = C->n_kernels;
+  G->last_branches = C->n_branches;
+  tn_status st = TN_OK;
+  // after every plan's pending work (and the caller's stream) ...
+  for (int i = 0; i < P && !st; ++i) {
+    st = check(hipEventRecord(G->ev, G->plans[i]->stream), "event");
+    if (!st) st = check(hipStreamWaitEvent(G->stream, G->ev, 0), "wait");
+  }
+  if (!st && G->user_stream) {
+    st = check(hipEventRecord(G->ev, G->user_stream), "event");
+    if (!st) st = check(hipStreamWaitEvent(G->stream, G->ev, 0), "wait");
+  }
+  if (!st) st = check(hipGraphLaunch(C->exec, G->stream), "graph launch");
+  // ... and before anything later on those streams
+  if (!st) st = check(hipEventRecord(G->ev, G->stream), "event");
+  for (int i = 0; i < P && !st; ++i) st = check(hipStreamWaitEvent(G->plans[i]->stream, G->ev, 0), "wait");
+  if (!st && G->user_stream) st = check(hipStreamWaitEvent(G->user_stream, G->ev, 0), "wait");
+  if (st) return st;
+  for (int i = 0; i < P; ++i) G->plans[i]->slices_acc += count[i];
+  return TN_OK;
+}
+
+tn_status tn_group_describe(tn_group G, int64_t* n_kernels, int32_t* n_branches) {
+  if (!G) return fail(TN_E_ARG, "null group");
+  if (n_kernels) *n_kernels = G->last_kernels;
+  if (n_branches) *n_branches = G->last_branches;
+  return TN_OK;
+}
+
+void tn_group_destroy(tn_group G) { delete G; }
 
 tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_t k, const void* A, const void* B,
                   void* C, void* stream) {

@@ -30,7 +30,16 @@ STATUS = {0: "TN_OK", -1: "TN_E_ARG", -2: "TN_E_LABEL", -3: "TN_E_PATH", -4: "TN
 
 EXPORTED = ["tn_plan_create", "tn_plan_destroy", "tn_plan_describe", "tn_plan_steps",
             "tn_plan_step_times", "tn_contract_slices", "tn_slice_partials", "tn_amplitudes", "tn_accumulator_set",
-            "tn_reset", "tn_gemm", "tn_permute", "tn_status_string", "tn_last_error_message"]
+            "tn_reset", "tn_group_create", "tn_group_contract", "tn_group_describe",
+            "tn_group_destroy", "tn_plan_step_features", "tn_plan_set_tile",
+            "tn_plan_tune_with_model", "tn_costmodel_create", "tn_costmodel_destroy",
+            "tn_costmodel_describe", "tn_costmodel_set_normalization", "tn_costmodel_get_params",
+            "tn_costmodel_set_params", "tn_costmodel_predict", "tn_costmodel_gradient",
+            "tn_costmodel_adam_step", "tn_costmodel_train", "tn_gemm", "tn_permute",
+            "tn_status_string", "tn_last_error_message"]
+
+TN_COST_FEATURES = 29
+TN_N_TILE_SHAPES = 4
 
 
 class TnError(RuntimeError):
@@ -64,7 +73,7 @@ class tn_step_info(ctypes.Structure):
                 ("k", ctypes.c_int64), ("split_k", ctypes.c_int32), ("tile_m", ctypes.c_int32),
                 ("tile_n", ctypes.c_int32), ("a_contig", ctypes.c_int32),
                 ("b_contig", ctypes.c_int32), ("flops", ctypes.c_double),
-                ("bytes", ctypes.c_double)]
+                ("bytes", ctypes.c_double), ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _P = ctypes.POINTER
@@ -96,6 +105,45 @@ _lib.tn_accumulator_set.argtypes = [ctypes.c_void_p, _P(ctypes.c_double), ctypes
 _lib.tn_accumulator_set.restype = ctypes.c_int
 _lib.tn_reset.argtypes = [ctypes.c_void_p]
 _lib.tn_reset.restype = ctypes.c_int
+_lib.tn_group_create.argtypes = [_P(ctypes.c_void_p), _P(ctypes.c_void_p), ctypes.c_int32,
+                                 _P(tn_options)]
+_lib.tn_group_create.restype = ctypes.c_int
+_lib.tn_group_contract.argtypes = [ctypes.c_void_p, _P(ctypes.c_int64), _P(ctypes.c_int64)]
+_lib.tn_group_contract.restype = ctypes.c_int
+_lib.tn_group_describe.argtypes = [ctypes.c_void_p, _P(ctypes.c_int64), _P(ctypes.c_int32)]
+_lib.tn_group_describe.restype = ctypes.c_int
+_lib.tn_group_destroy.argtypes = [ctypes.c_void_p]
+_lib.tn_group_destroy.restype = None
+_F32P = _P(ctypes.c_float)
+_lib.tn_plan_step_features.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, _F32P,
+                                       ctypes.c_int32]
+_lib.tn_plan_step_features.restype = ctypes.c_int
+_lib.tn_plan_set_tile.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
+_lib.tn_plan_set_tile.restype = ctypes.c_int
+_lib.tn_plan_tune_with_model.argtypes = [ctypes.c_void_p, ctypes.c_void_p, _F32P, ctypes.c_int32]
+_lib.tn_plan_tune_with_model.restype = ctypes.c_int
+_lib.tn_costmodel_create.argtypes = [_P(ctypes.c_void_p), ctypes.c_int32, ctypes.c_uint64]
+_lib.tn_costmodel_create.restype = ctypes.c_int
+_lib.tn_costmodel_destroy.argtypes = [ctypes.c_void_p]
+_lib.tn_costmodel_destroy.restype = None
+_lib.tn_costmodel_describe.argtypes = [ctypes.c_void_p, _P(ctypes.c_int32), _P(ctypes.c_int32),
+                                       _P(ctypes.c_int64)]
+_lib.tn_costmodel_describe.restype = ctypes.c_int
+_lib.tn_costmodel_set_normalization.argtypes = [ctypes.c_void_p, _F32P, _F32P]
+_lib.tn_costmodel_set_normalization.restype = ctypes.c_int
+_lib.tn_costmodel_get_params.argtypes = [ctypes.c_void_p, _F32P, ctypes.c_int64]
+_lib.tn_costmodel_get_params.restype = ctypes.c_int
+_lib.tn_costmodel_set_params.argtypes = [ctypes.c_void_p, _F32P, ctypes.c_int64]
+_lib.tn_costmodel_set_params.restype = ctypes.c_int
+_lib.tn_costmodel_predict.argtypes = [ctypes.c_void_p, _F32P, ctypes.c_int64, _F32P]
+_lib.tn_costmodel_predict.restype = ctypes.c_int
+_lib.tn_costmodel_gradient.argtypes = [ctypes.c_void_p, _F32P, _F32P, ctypes.c_int64, _F32P, _F32P]
+_lib.tn_costmodel_gradient.restype = ctypes.c_int
+_lib.tn_costmodel_adam_step.argtypes = [ctypes.c_void_p, _F32P, ctypes.c_int64, ctypes.c_float]
+_lib.tn_costmodel_adam_step.restype = ctypes.c_int
+_lib.tn_costmodel_train.argtypes = [ctypes.c_void_p, _F32P, _F32P, ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_float, ctypes.c_uint64, _F32P]
+_lib.tn_costmodel_train.restype = ctypes.c_int
 _lib.tn_gemm.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                          ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                          ctypes.c_void_p]
@@ -237,6 +285,156 @@ def tn_reset(plan):
     _check(_lib.tn_reset(plan))
 
 
+def tn_group_create(plans, stream=None, branches: int = 0):
+    """Group plan handles; each tn_group_contract call replays one captured graph."""
+    arr = (ctypes.c_void_p * len(plans))(*plans)
+    opts = tn_options()
+    opts.struct_size = ctypes.sizeof(tn_options)
+    opts.stream = _stream_handle(stream)
+    opts.slice_batch = int(branches)
+    handle = ctypes.c_void_p()
+    _check(_lib.tn_group_create(ctypes.byref(handle), arr, len(plans), ctypes.byref(opts)))
+    return handle.value
+
+
+def tn_group_contract(group, first, count):
+    f = (ctypes.c_int64 * len(first))(*[int(x) for x in first])
+    c = (ctypes.c_int64 * len(count))(*[int(x) for x in count])
+    _check(_lib.tn_group_contract(group, f, c))
+
+
+def tn_group_describe(group) -> dict:
+    nk, nb = ctypes.c_int64(), ctypes.c_int32()
+    _check(_lib.tn_group_describe(group, ctypes.byref(nk), ctypes.byref(nb)))
+    return {"n_kernels": nk.value, "n_branches": nb.value}
+
+
+def tn_group_destroy(group):
+    _lib.tn_group_destroy(group)
+
+
+class Group:
+    """Owning wrapper around a group of plans (the plans must outlive it)."""
+
+    def __init__(self, plans, stream=None, branches: int = 0):
+        self.plans = list(plans)
+        self.handle = tn_group_create([p.handle for p in self.plans], stream, branches)
+
+    def contract(self, first=None, count=None):
+        if first is None:
+            first = [0] * len(self.plans)
+        if count is None:
+            count = [p.describe()["n_slices"] - f for p, f in zip(self.plans, first)]
+        tn_group_contract(self.handle, first, count)
+
+    def describe(self):
+        return tn_group_describe(self.handle)
+
+    def close(self):
+        if self.handle:
+            tn_group_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _f32(x, shape=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    if shape is not None and a.shape != shape:
+        a = a.reshape(shape)
+    return a
+
+
+def _fp(a):
+    return a.ctypes.data_as(_F32P)
+
+
+def tn_plan_step_features(plan, step: int, tile: int = -1) -> np.ndarray:
+    out = np.zeros(TN_COST_FEATURES, dtype=np.float32)
+    _check(_lib.tn_plan_step_features(plan, int(step), int(tile), _fp(out), TN_COST_FEATURES))
+    return out
+
+
+def tn_plan_set_tile(plan, step: int, tile: int):
+    _check(_lib.tn_plan_set_tile(plan, int(step), int(tile)))
+
+
+def tn_plan_tune_with_model(plan, model) -> np.ndarray:
+    n = tn_plan_describe(plan)["n_steps"]
+    out = np.zeros(max(n, 1), dtype=np.float32)
+    _check(_lib.tn_plan_tune_with_model(plan, model, _fp(out), n))
+    return out[:n]
+
+
+def tn_costmodel_create(n_features: int, seed: int = 0):
+    handle = ctypes.c_void_p()
+    _check(_lib.tn_costmodel_create(ctypes.byref(handle), int(n_features), int(seed)))
+    return handle.value
+
+
+def tn_costmodel_destroy(model):
+    _lib.tn_costmodel_destroy(model)
+
+
+def tn_costmodel_describe(model):
+    f, h, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check(_lib.tn_costmodel_describe(model, ctypes.byref(f), ctypes.byref(h), ctypes.byref(p)))
+    return f.value, h.value, p.value
+
+
+def tn_costmodel_set_normalization(model, mean, std):
+    m, s = _f32(mean), _f32(std)
+    _check(_lib.tn_costmodel_set_normalization(model, _fp(m), _fp(s)))
+
+
+def tn_costmodel_get_params(model, n: int) -> np.ndarray:
+    out = np.zeros(n, dtype=np.float32)
+    _check(_lib.tn_costmodel_get_params(model, _fp(out), n))
+    return out
+
+
+def tn_costmodel_set_params(model, theta):
+    t = _f32(theta)
+    _check(_lib.tn_costmodel_set_params(model, _fp(t), t.size))
+
+
+def tn_costmodel_predict(model, X) -> np.ndarray:
+    X = _f32(X)
+    n = X.shape[0] if X.ndim == 2 else 0
+    y = np.zeros(max(n, 1), dtype=np.float32)
+    _check(_lib.tn_costmodel_predict(model, _fp(X), n, _fp(y)))
+    return y[:n]
+
+
+def tn_costmodel_gradient(model, X, t):
+    X, t = _f32(X), _f32(t)
+    _, _, n_params = tn_costmodel_describe(model)
+    g = np.zeros(n_params, dtype=np.float32)
+    loss = ctypes.c_float()
+    _check(_lib.tn_costmodel_gradient(model, _fp(X), _fp(t), X.shape[0], _fp(g), ctypes.byref(loss)))
+    return g, float(loss.value)
+
+
+def tn_costmodel_adam_step(model, grad, lr: float):
+    g = _f32(grad)
+    _check(_lib.tn_costmodel_adam_step(model, _fp(g), g.size, float(lr)))
+
+
+def tn_costmodel_train(model, X, t, epochs: int, batch: int, lr: float, seed: int = 0) -> float:
+    X, t = _f32(X), _f32(t)
+    loss = ctypes.c_float()
+    _check(_lib.tn_costmodel_train(model, _fp(X), _fp(t), X.shape[0], int(epochs), int(batch),
+                                   float(lr), int(seed), ctypes.byref(loss)))
+    return float(loss.value)
+
+
 def tn_gemm(A, B, C, precision="c64", stream=None):
     """C[b] = A[b] @ B[b] on device complex64 torch tensors of shape (b, m, k), (b, k, n), (b, m, n)."""
     b, m, k = A.shape
@@ -306,3 +504,13 @@ class Plan:
 
     def set_accumulator(self, acc, slices):
         tn_accumulator_set(self.handle, acc, slices)
+
+    def step_features(self, step, tile=-1):
+        return tn_plan_step_features(self.handle, step, tile)
+
+    def set_tile(self, step, tile):
+        tn_plan_set_tile(self.handle, step, tile)
+
+    def tune_with_model(self, model):
+        """Tile every MFMA step by the model's predicted time; returns predicted us per step."""
+        return tn_plan_tune_with_model(self.handle, getattr(model, "handle", model))

@@ -118,3 +118,61 @@ def test_error_codes():
 def test_status_strings():
     for code, name in tn.STATUS.items():
         assert tn._lib.tn_status_string(code).decode() == name
+
+
+def test_step_features_describe_the_step_and_tile():
+    circ, net, best = configs.build("rqc30")
+    h = _host_plan(net, best["path"], best["sliced"], precision="f16x3")
+    try:
+        steps = tn.tn_plan_steps(h)
+        info = tn.tn_plan_describe(h)
+        sbits = int(np.log2(info["slice_batch"]))
+        for i, s in enumerate(steps):
+            f = tn.tn_plan_step_features(h, i, -1)
+            bb = int(np.log2(s["batch"])) + (sbits if s["per_slice"] else 0)
+            assert f[0] == bb and f[1] == np.log2(s["m"]) and f[2] == np.log2(s["n"])
+            assert f[3] == np.log2(s["k"])
+            assert f[4] == 3 + f[0] + f[1] + f[2] + f[3]
+            assert abs(f[6] - (f[4] - f[5])) < 1e-5
+            assert f[11] == s["per_slice"]
+            assert f[12:16].sum() == 1 and f[12 + s["kernel"]] == 1
+            if s["kernel"] == 0:
+                assert f[16:20].sum() == 0
+                continue
+            tile = s["tile"]
+            bm, bn = [(256, 128), (128, 128), (128, 64), (64, 64)][tile]
+            assert (s["tile_m"], s["tile_n"]) == (min(bm, s["m"]), min(bn, s["n"]))
+            assert f[16 + tile] == 1 and f[16:20].sum() == 1
+            assert f[9] == np.log2(s["split_k"])
+            assert f[20] == s["a_contig"] and f[21] == s["b_contig"]
+            # other tiles: only tile-dependent features move
+            for t in range(4):
+                g = tn.tn_plan_step_features(h, i, t)
+                assert np.array_equal(g[:7], f[:7]) and g[16 + t] == 1
+                bm, bn = [(256, 128), (128, 128), (128, 64), (64, 64)][t]
+                assert g[7] == max(0, f[1] - np.log2(bm)) and g[8] == max(0, f[2] - np.log2(bn))
+    finally:
+        tn.tn_plan_destroy(h)
+
+
+def test_set_tile_on_host_plan():
+    circ, net, best = configs.build("rqc30")
+    h = _host_plan(net, best["path"], best["sliced"], precision="c64")
+    try:
+        steps = tn.tn_plan_steps(h)
+        mfma = [i for i, s in enumerate(steps) if s["kernel"] != 0]
+        small = [i for i, s in enumerate(steps) if s["kernel"] == 0]
+        assert mfma and small
+        i = mfma[0]
+        for t, shape in enumerate([(256, 128), (128, 128), (128, 64), (64, 64)]):
+            tn.tn_plan_set_tile(h, i, t)
+            s = tn.tn_plan_steps(h)[i]
+            assert s["tile"] == t
+            assert (s["tile_m"], s["tile_n"]) == (min(shape[0], s["m"]), min(shape[1], s["n"]))
+            assert tn.tn_plan_step_features(h, i, -1)[16 + t] == 1
+        _expect("TN_E_ARG", lambda: tn.tn_plan_set_tile(h, small[0], 0))
+        _expect("TN_E_ARG", lambda: tn.tn_plan_set_tile(h, i, 4))
+        _expect("TN_E_ARG", lambda: tn.tn_plan_set_tile(h, len(steps), 0))
+        _expect("TN_E_ARG", lambda: tn.tn_plan_step_features(h, i, 7))
+    finally:
+        tn.tn_plan_destroy(h)

@@ -299,3 +299,61 @@ def test_autotuned_plan_matches_oracle(prec):
         p.contract()
         got, _ = p.amplitudes()
     assert metrics.rel_l2(got, ref) <= TOL[prec]
+
+
+def _small_circuits(n, seed=1040, open_k=4):
+    """Uneven 16-28 qubit lattice circuits, depth 8-14, unsliced (the batching form's sub-networks)."""
+    return configs.uneven_circuits(n, seed=seed, open_k=open_k, cap_log2=22)
+
+
+@pytest.mark.parametrize("prec", ["c64", "f16x3"])
+def test_group_graph_launch_matches_individual_plans(prec):
+    """Slices of one network plus uneven small networks in one graph replay: every plan's
+    amplitudes equal, bit for bit, those of the same plan contracted on its own."""
+    print(f"group {prec}", flush=True)
+    circ, net, best = configs.build("rqc12")
+    sliced = choose_slices(net.labels, net.open_labels, net.extents(), best["path"], cap_log2=6,
+                           min_sliced=4)
+    items = [(net, {"path": best["path"], "sliced": sliced})] + _small_circuits(6)
+    refs = [contract.amplitudes(n.tensors, n.labels, n.open_labels, b["path"], b.get("sliced", ()))
+            for n, b in items]
+
+    def make():
+        return [tn.Plan(n.tensors, n.labels, n.open_labels, b["path"], b.get("sliced", ()),
+                        precision=prec, slice_batch=4) for n, b in items]
+
+    alone = make()
+    plans = make()
+    try:
+        for p in alone:
+            p.contract()
+        singles = [p.amplitudes()[0] for p in alone]
+        with tn.Group(plans, branches=3) as g:
+            g.contract()
+            info = g.describe()
+            assert info["n_kernels"] > len(plans) and info["n_branches"] == 3
+            outs = [p.amplitudes() for p in plans]
+            for (amps, count), ref, one, p in zip(outs, refs, singles, plans):
+                assert count == p.describe()["n_slices"]
+                assert np.array_equal(amps, one)
+                assert metrics.rel_l2(amps, ref) <= TOL[prec]
+            # a replay of the captured graph adds the same amplitudes again
+            g.contract()
+            for (amps, _), p in zip(outs, plans):
+                again, count = p.amplitudes()
+                assert count == 2 * p.describe()["n_slices"]
+                assert metrics.rel_l2(again, 2 * amps) <= 1e-12
+            # a partial range through the group equals the same range contracted alone
+            for p in plans:
+                p.reset()
+            g.contract([3] + [0] * (len(plans) - 1), [5] + [0] * (len(plans) - 1))
+            part, c = plans[0].amplitudes()
+            assert c == 5
+            assert g.describe()["n_branches"] == 1
+        alone[0].reset()
+        alone[0].contract(3, 5)
+        ref5, _ = alone[0].amplitudes()
+        assert np.array_equal(part, ref5)
+    finally:
+        for p in plans + alone:
+            p.close()

@@ -1,0 +1,60 @@
+"""Pins of the FP64 cost-model MLP oracle (CPU): finite differences and closed forms."""
+import numpy as np
+
+from oracle import mlp
+
+
+def _setup(seed=0, n=40, F=7, H=9):
+    rng = np.random.default_rng(seed)
+    theta = rng.standard_normal(mlp.n_params(F, H)) * 0.5
+    X = rng.standard_normal((n, F))
+    t = rng.standard_normal(n)
+    mean, std = rng.standard_normal(F), rng.uniform(0.5, 2.0, F)
+    return theta, X, t, F, H, mean, std
+
+
+def test_gradient_matches_finite_differences():
+    theta, X, t, F, H, mean, std = _setup()
+    g = mlp.gradient(theta, X, t, F, H, mean, std)
+    h = 1e-6
+    fd = np.zeros_like(theta)
+    for i in range(theta.size):
+        e = np.zeros_like(theta)
+        e[i] = h
+        fd[i] = (mlp.loss(theta + e, X, t, F, H, mean, std) - mlp.loss(theta - e, X, t, F, H, mean, std)) / (2 * h)
+    assert np.max(np.abs(g - fd)) <= 1e-6 * max(1.0, np.max(np.abs(fd)))
+
+
+def test_forward_closed_form_linear_region():
+    """With non-negative weights and inputs every ReLU is active: the net is affine."""
+    F, H = 3, 4
+    rng = np.random.default_rng(2)
+    theta = np.abs(rng.standard_normal(mlp.n_params(F, H)))
+    W1, b1, W2, b2, w3, b3 = mlp.unpack(theta, F, H)
+    X = np.abs(rng.standard_normal((5, F)))
+    y, _ = mlp.forward(theta, X, F, H)
+    expect = ((X @ W1.T + b1) @ W2.T + b2) @ w3 + b3[0]
+    np.testing.assert_allclose(y, expect, rtol=1e-13)
+
+
+def test_adam_first_step_is_signed_lr():
+    """From zero moments the bias-corrected first step is lr * g / (|g| + eps)."""
+    g = np.array([3.0, -0.5, 2e-3, 0.0])
+    th, m, v = mlp.adam(np.zeros(4), g, np.zeros(4), np.zeros(4), step=1, lr=0.1)
+    np.testing.assert_allclose(th, -0.1 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_forward_hand_computed_with_clipped_units():
+    """A 1-input, 2-unit network evaluated by hand, with ReLUs that clip and standardisation.
+
+    W1 = [[1], [-1]], b1 = 0; W2 = [[1, 1], [-1, 0]], b2 = [0, 0.5]; w3 = [3, 5], b3 = -1;
+    mean 1, std 2.
+      x = 5:  x' = 2,  z1 = [2, -2] -> h1 = [2, 0],  z2 = [2, -1.5] -> h2 = [2, 0],  y = 5
+      x = -5: x' = -3, z1 = [-3, 3] -> h1 = [0, 3],  z2 = [3, 0.5]  -> h2 = [3, 0.5], y = 10.5
+    """
+    theta = np.array([1.0, -1.0, 0.0, 0.0, 1.0, 1.0, -1.0, 0.0, 0.0, 0.5, 3.0, 5.0, -1.0])
+    assert theta.size == mlp.n_params(1, 2)
+    y, _ = mlp.forward(theta, np.array([[5.0], [-5.0]]), 1, 2, mean=[1.0], std=[2.0])
+    np.testing.assert_allclose(y, [5.0, 10.5], rtol=0, atol=1e-15)
+    # and the loss against targets [4, 10.5] is ((5-4)^2 + 0) / 2
+    assert mlp.loss(theta, np.array([[5.0], [-5.0]]), [4.0, 10.5], 1, 2, [1.0], [2.0]) == 0.5

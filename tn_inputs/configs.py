@@ -53,3 +53,26 @@ def build(name: str):
     best = find_path(net, cap_log2=w.cap_log2, n_sliced=w.n_sliced, trials=w.trials,
                      seed=w.circuit_seed)
     return circ, net, best
+
+
+def uneven_circuits(n: int, seed: int = 1040, open_k: int = 4, cap_log2: int = 22,
+                    trials: int = 1):
+    """n seeded lattice circuits of uneven size: R x C grids with 16 <= R*C <= 28 and depth
+    drawn from 8..14, k open qubits, unsliced.  These stand in for the many independent
+    small sub-networks that share the GPU with the slices of a large one.
+
+    Returns a list of (network, path dict); circuit i uses seed + i (circuit),
+    seed + 1000 + i (closed bits) and seed + i (path search)."""
+    import numpy as np
+    shapes = [(r, c) for r in range(2, 8) for c in range(r, 10) if 16 <= r * c <= 28]
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        r, c = shapes[rng.integers(len(shapes))]
+        depth = int(rng.integers(8, 15))
+        circ = random_circuit(r, c, depth, seed + i)
+        oq, cb = open_and_closed(circ.n_qubits, open_k, seed + 1000 + i)
+        net = circuit_network(circ, oq, cb)
+        best = find_path(net, cap_log2=cap_log2, trials=trials, seed=seed + i)
+        out.append((net, best))
+    return out
