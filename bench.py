@@ -11,8 +11,10 @@ FP64 cross-slice sum.  Inputs are resident on the GPU before timing starts.
 Prints ONE JSON line with the split-FP16 throughput as ``value`` (TFLOPS,
 algorithmic: 8 real flops per complex multiply-add) and the complex64 run
 beside it, the roofline of the dominant kernel (its launches timed with HIP
-events on the plan's stream inside the timed region) and the CPU oracle timed
-on one slice of the same workload.
+events on the plan's stream inside the timed region), the batching form
+(a slice range of the workload plus uneven 16-28-qubit circuits, plan by plan
+against one graph replay) and the CPU oracle timed on one slice of the same
+workload.
 """
 from __future__ import annotations
 
@@ -21,6 +23,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -88,6 +92,52 @@ def run_precision(tn, torch, net, best, prec, steps, warmup, sample_slice, tunin
             "by_kind": by_kind, "amps": amps, "partial": part}
 
 
+def run_batching(tn, torch, configs, net, best, prec, n_small, n_slices, steps):
+    """Batching form: a slice range of the workload plus n_small uneven 16-28-qubit circuits,
+    contracted plan by plan (tn_contract_slices each) and as one graph replay (tn_group_*)."""
+    items = [(net, best, n_slices)] + [(n, b, 1) for n, b in
+                                        configs.uneven_circuits(n_small, seed=1040, cap_log2=22)]
+    stream = torch.cuda.current_stream()
+    plans = [tn.Plan(n.tensors, n.labels, n.open_labels, b["path"], b.get("sliced", ()),
+                     precision=prec, stream=stream) for n, b, _ in items]
+    counts = [c for _, _, c in items]
+    flops = sum(p.describe()["flops_invariant"] + c * p.describe()["flops_per_slice"]
+                for p, c in zip(plans, counts))
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()                                   # warm-up (and graph capture)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(steps):
+            fn()
+        end.record(stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(end) / steps
+
+    def sequential():
+        for p, c in zip(plans, counts):
+            p.contract(0, c)
+
+    seq_ms = timed(sequential)
+    seq_amps = [p.amplitudes()[0] for p in plans]
+    for p in plans:
+        p.reset()
+    with tn.Group(plans, stream=stream) as g:
+        grp_ms = timed(lambda: g.contract([0] * len(plans), counts))
+        info = g.describe()
+        grp_amps = [p.amplitudes()[0] for p in plans]
+    same = all(np.array_equal(a, b) for a, b in zip(seq_amps, grp_amps))
+    for p in plans:
+        p.close()
+    return {"plans": len(plans), "workload_slices": n_slices, "small_circuits": n_small,
+            "flops": flops, "sequential_ms": round(seq_ms, 3), "graph_ms": round(grp_ms, 3),
+            "speedup": round(seq_ms / grp_ms, 3), "graph_tflops": round(flops / (grp_ms * 1e-3) / 1e12, 3),
+            "graph_kernels": info["n_kernels"], "graph_branches": info["n_branches"],
+            "amplitudes_identical": bool(same), "precision": prec}
+
+
 def cpu_baseline(net, best, sample_slice, flops_slice):
     from oracle import contract
     threads = os.cpu_count()
@@ -141,6 +191,8 @@ def main():
     ap.add_argument("--sample-slice", type=int, default=137)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", type=int, default=1, help="1 = autotune tile shapes at plan creation")
+    ap.add_argument("--batching", type=int, default=64,
+                    help="uneven circuits in the batching-form measurement (0 = skip it)")
     ap.add_argument("--counter-run", action="store_true",
                     help="one chunk per precision and a calibration copy, for rocprofv3 --pmc")
     args = ap.parse_args()
@@ -148,13 +200,11 @@ def main():
         print("bench.py runs on one GPU only: slices are independent sub-tasks and the "
               "multi-GPU sum of partial amplitudes is not part of this build.", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     if not torch.cuda.is_available():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    from oracle import metrics
     from paper_2310_03978_amd import tn
     from tn_inputs import configs
 
@@ -211,14 +261,21 @@ def main():
                      "plan_and_tuning_s": round(r["plan_s"], 3)}
     if "c64" in runs and head != "c64":
         out["speedup_vs_c64"] = round(runs["c64"]["ms_per_step"] / main_run["ms_per_step"], 3)
-        out["rel_l2_vs_c64_full"] = metrics.rel_l2(main_run["amps"], runs["c64"]["amps"])
+        ref_c64 = runs["c64"]["amps"]
+        out["rel_l2_vs_c64_full"] = float(np.linalg.norm(main_run["amps"] - ref_c64) / np.linalg.norm(ref_c64))
     out["roofline"] = roof
+    if args.batching > 0:
+        log(f"batching form: {args.batching} uneven circuits + slices [0, 32) of {args.workload}")
+        out["batching"] = run_batching(tn, torch, configs, net, best, head, args.batching, 32, 3)
+        log(f"  {out['batching']}")
     if not args.no_cpu_baseline:
+        from oracle import metrics
         ref, cb = cpu_baseline(net, best, args.sample_slice,
                                info["flops_per_slice"] + info["flops_invariant"])
         out["cpu_baseline"] = cb
         for prec, r in runs.items():
             out[prec]["rel_l2_vs_oracle_slice"] = metrics.rel_l2(r["partial"], ref)
+            out[prec]["eps_l2sq_vs_oracle_slice"] = metrics.eps_l2sq(r["partial"], ref)
             out[prec]["fidelity_vs_oracle_slice"] = metrics.fidelity(r["partial"], ref)
     else:
         out["cpu_baseline"] = None

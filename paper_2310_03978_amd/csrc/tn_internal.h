@@ -40,6 +40,11 @@ struct GettDesc {
   int64_t a_b[TN_MAXB], a_m[TN_MAXR], a_k[TN_MAXK];
   int64_t b_b[TN_MAXB], b_k[TN_MAXK], b_n[TN_MAXR];
   int64_t c_b[TN_MAXB], c_m[TN_MAXR], c_n[TN_MAXR];
+  // K-stage advance of the MFMA kernels: a stage covers the 4 lowest k bits
+  // (16 complex), and going from stage s to s + 1 changes the operand offsets
+  // by a_kd[t] / b_kd[t], t = trailing one bits of s:
+  //   kd[t] = k_stride[4 + t] - sum_{j < t} k_stride[4 + j].
+  int64_t a_kd[TN_MAXK], b_kd[TN_MAXK];
   // role of each storage position of C, LSB first (own layout then slice-local bits):
   // (role << 8) | index, role 0 = batch, 1 = m, 2 = n
   int32_t c_pos[TN_MAXR + TN_MAXB];

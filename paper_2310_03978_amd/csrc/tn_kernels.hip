@@ -318,7 +318,7 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
   const int lk = d->kb < 4 ? d->kb : 4;
   const int sl = (int)(bidx >> d->own_bb);
   const Scales sc = step_scales(d, g, sl);
-  const bool bf = g.split_bf16 != 0;
+  constexpr bool bf = P == 2;
 
   const int64_t a_base = bits_offset(bidx, d->a_b, nbb) + bits_offset(tile_m << lm, d->a_m, d->mb);
   const int64_t b_base = bits_offset(bidx, d->b_b, nbb) + bits_offset(tile_n << ln, d->b_n, d->nb);
@@ -331,15 +331,17 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
   // Per-thread element offsets and LDS positions.  Elements beyond a small
   // operand tile load from offset 0 (always valid) and are not stored, so the
   // loads are unconditional and stay in flight together.
-  int64_t ia_off[IA], ib_off[IB];
-  int ia_pos[IA], ib_pos[IB], ib_pos2[IB];
+  // tile-local offsets stay below the operand's element count, which the planner
+  // keeps below 2^31 for MFMA steps
+  int32_t ia_off[IA], ib_off[IB];
+  int ia_pos[IA], ib_pos[IB];
   uint32_t a_valid = 0, b_valid = 0;
 #pragma unroll
   for (int i = 0; i < IA; ++i) {
     const ThreadEnum ip = iter_part<TB>(d->ea, i);
     const bool ok = t + NT * i < ea_elems;
     a_valid |= ok ? 1u << i : 0u;
-    ia_off[i] = ok ? ta.off + ip.off : 0;
+    ia_off[i] = ok ? (int32_t)(ta.off + ip.off) : 0;
     const int r = ta.row + ip.row, c = ta.col + ip.col;   // r = m_loc, c = k_loc
     ia_pos[i] = P == 0 ? c * T::LDA0 + 2 * r : swz(r, c);
   }
@@ -348,10 +350,11 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
     const ThreadEnum ip = iter_part<TB>(d->eb, i);
     const bool ok = t + NT * i < eb_elems;
     b_valid |= ok ? 1u << i : 0u;
-    ib_off[i] = ok ? tb.off + ip.off : 0;
+    ib_off[i] = ok ? (int32_t)(tb.off + ip.off) : 0;
     const int r = tb.row + ip.row, c = tb.col + ip.col;   // r = n_loc, c = k_loc
+    // split: real columns 2r and 2r + 1 are adjacent LDS rows with the same swizzle
+    // (rows 2r and 2r + 1 share row / 4), so column 2r + 1 sits LDK words further
     ib_pos[i] = P == 0 ? c * T::LDB0 + 2 * r : swz(2 * r, c);
-    ib_pos2[i] = P == 0 ? 0 : swz(2 * r + 1, c);
   }
 
   floatx16 acc[2][4];
@@ -371,10 +374,10 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
   }
 
   uint2 ra[IA], rb[IB];
-  auto load_stage = [&](int64_t kit) {
-    const int64_t k0 = k_first + (kit << lk);
-    const int64_t ak = a_base + bits_offset(k0, d->a_k, d->kb);
-    const int64_t bk = b_base + bits_offset(k0, d->b_k, d->kb);
+  // operand offsets of the current K stage, advanced with the per-stage deltas
+  int64_t ak = a_base + bits_offset(k_first, d->a_k, d->kb);
+  int64_t bk = b_base + bits_offset(k_first, d->b_k, d->kb);
+  auto load_stage = [&]() {
 #pragma unroll
     for (int i = 0; i < IA; ++i) ra[i] = A[ak + ia_off[i]];
 #pragma unroll
@@ -401,31 +404,44 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
       uint32_t* Al = Ah + BM * LDK;
       uint32_t* Bh = Al + BM * LDK;
       uint32_t* Bl = Bh + 2 * BN * LDK;
+      // operands stored split are used as loaded; complex64 operands are scaled and split
+      // here (one uniform branch per operand and stage)
+      if (g.fa == TN_FMT_SPLIT) {
 #pragma unroll
-      for (int i = 0; i < IA; ++i)
-        if ((a_valid >> i) & 1) {
-          uint2 wv = ra[i];
-          if (g.fa != TN_FMT_SPLIT) {
-            const float2 v = __builtin_bit_cast(float2, wv);
-            wv = split_pair(v.x * sc.fa, v.y * sc.fa, bf);
+        for (int i = 0; i < IA; ++i)
+          if ((a_valid >> i) & 1) {
+            Ah[ia_pos[i]] = ra[i].x;
+            Al[ia_pos[i]] = ra[i].y;
           }
-          Ah[ia_pos[i]] = wv.x;
-          Al[ia_pos[i]] = wv.y;
-        }
-      // B as real columns: column 2n holds (Br, -Bi), column 2n+1 holds (Bi, Br)
+      } else {
 #pragma unroll
-      for (int i = 0; i < IB; ++i)
-        if ((b_valid >> i) & 1) {
-          uint2 wv = rb[i];
-          if (g.fb != TN_FMT_SPLIT) {
-            const float2 v = __builtin_bit_cast(float2, wv);
-            wv = split_pair(v.x * sc.fb, v.y * sc.fb, bf);
+        for (int i = 0; i < IA; ++i)
+          if ((a_valid >> i) & 1) {
+            const float2 v = __builtin_bit_cast(float2, ra[i]);
+            const uint2 wv = split_pair(v.x * sc.fa, v.y * sc.fa, bf);
+            Ah[ia_pos[i]] = wv.x;
+            Al[ia_pos[i]] = wv.y;
           }
-          Bh[ib_pos[i]] = wv.x ^ 0x80000000u;
-          Bh[ib_pos2[i]] = __builtin_amdgcn_alignbit(wv.x, wv.x, 16);
-          Bl[ib_pos[i]] = wv.y ^ 0x80000000u;
-          Bl[ib_pos2[i]] = __builtin_amdgcn_alignbit(wv.y, wv.y, 16);
-        }
+      }
+      // B as real columns: column 2n holds (Br, -Bi), column 2n+1 (the next LDS row) (Bi, Br)
+      auto put_b = [&](int i, uint2 wv) {
+        Bh[ib_pos[i]] = wv.x ^ 0x80000000u;
+        Bh[ib_pos[i] + LDK] = __builtin_amdgcn_alignbit(wv.x, wv.x, 16);
+        Bl[ib_pos[i]] = wv.y ^ 0x80000000u;
+        Bl[ib_pos[i] + LDK] = __builtin_amdgcn_alignbit(wv.y, wv.y, 16);
+      };
+      if (g.fb == TN_FMT_SPLIT) {
+#pragma unroll
+        for (int i = 0; i < IB; ++i)
+          if ((b_valid >> i) & 1) put_b(i, rb[i]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < IB; ++i)
+          if ((b_valid >> i) & 1) {
+            const float2 v = __builtin_bit_cast(float2, rb[i]);
+            put_b(i, split_pair(v.x * sc.fb, v.y * sc.fb, bf));
+          }
+      }
     }
   };
 
@@ -488,7 +504,7 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
   // Pipeline: stage k+1 is requested into registers, stage k is multiplied
   // from LDS, then stage k+1 is written to the other LDS buffer.  One barrier
   // per stage.
-  load_stage(0);
+  load_stage();
   store_stage(smem);
   __syncthreads();
 
@@ -496,7 +512,12 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
     const uint32_t* cur = smem + (kit & 1) * T::BUF;
     uint32_t* nxt = smem + ((kit + 1) & 1) * T::BUF;
     const bool more = kit + 1 < n_iters;
-    if (more) load_stage(kit + 1);
+    if (more) {
+      const int t = __builtin_ctzll(~(uint64_t)kit);
+      ak += d->a_kd[t];
+      bk += d->b_kd[t];
+      load_stage();
+    }
     if constexpr (P == 0) {
 #pragma unroll 1
       for (int kk = 0; kk < (1 << lk); ++kk) mfma_kk(cur, kk);

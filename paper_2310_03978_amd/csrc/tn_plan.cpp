@@ -294,6 +294,16 @@ void build_desc(tn_plan_s* p, Step& st) {
     d.a_k[j] = bit_stride(A, st.kb[j]);
     d.b_k[j] = bit_stride(B, st.kb[j]);
   }
+  {
+    const int k0 = std::min(d.kb, 4);   // bits inside one K stage of the MFMA kernels
+    int64_t sa = 0, sb = 0;
+    for (int t = 0; k0 + t < d.kb; ++t) {
+      d.a_kd[t] = d.a_k[k0 + t] - sa;
+      d.b_kd[t] = d.b_k[k0 + t] - sb;
+      sa += d.a_k[k0 + t];
+      sb += d.b_k[k0 + t];
+    }
+  }
   for (size_t pos = 0; pos < C.bits.size(); ++pos) {
     const int q = C.bits[pos];
     int code = -1;
@@ -407,6 +417,15 @@ tn_status validate_steps(const tn_plan_s* p, const std::vector<Step>& steps) {
       if (mx >= cap)
         return fail(TN_E_STATE, "internal: step " + std::to_string(s) + " operand " + std::to_string(o) +
                                     " reaches offset " + std::to_string(mx) + " of " + std::to_string(cap));
+      if (st.kernel != TN_K_SMALL && o < 2) {
+        // the MFMA kernels keep operand-tile offsets (m or n bits plus k bits) in 32 bits
+        int64_t tile_span = 0;
+        for (int j = 0; j < ops[o].nr; ++j) tile_span += ops[o].r[j];
+        for (int j = 0; j < ops[o].nk; ++j) tile_span += ops[o].k[j];
+        if (tile_span > INT32_MAX)
+          return fail(TN_E_UNSUPPORTED, "step " + std::to_string(s) + ": an operand spans more than 2^31 elements "
+                                        "across its free and summed bits");
+      }
     }
     if (st.kernel != TN_K_SMALL && st.splits > 1) {
       const int64_t need = int64_t(st.splits) << (d.nbb + d.mb + d.nb);

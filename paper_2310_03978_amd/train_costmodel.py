@@ -1,0 +1,99 @@
+"""Harvest step timings on this GPU and train the step-time cost model.
+
+    python -m paper_2310_03978_amd.train_costmodel --out paper_2310_03978_amd/data/costmodel_mi355x.json
+
+Data: every step of the plans of seeded uneven lattice circuits (16-28 qubits, depth 8-14),
+the 30-qubit 12-cycle workload and the 30-qubit 14-cycle sliced workload (chunks of 8 slices
+and of 1 slice), in the three precisions, each MFMA step timed with all four tile shapes
+(HIP events on the plan's stream).  The model is trained on all circuits but the last
+`--held-out` ones and the 14-cycle workload; the saved file records the held-out error and
+the measured time of the tiles the model picks against the shape heuristic's picks.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_2310_03978_amd import costmodel, tn  # noqa: E402
+from tn_inputs import configs  # noqa: E402
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def harvest_all(n_circuits: int, precisions, reps: int):
+    circs = configs.uneven_circuits(n_circuits, seed=5000, cap_log2=25)
+    items = [(f"u{i}", net, best, 0) for i, (net, best) in enumerate(circs)]
+    for name in ["rqc30d12", "rqc30"]:
+        _, net, best = configs.build(name)
+        items.append((name, net, best, 0))
+    _, net, best = configs.build("rqc30")
+    items.append(("rqc30sb1", net, best, 1))
+    records, defaults = [], {}
+    for prec in precisions:
+        for tag, net, best, sb in items:
+            t0 = time.time()
+            with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best.get("sliced", ()),
+                         precision=prec, record_steps=True, slice_batch=sb) as p:
+                for i, t in enumerate(costmodel.step_tile_ids(p)):
+                    defaults[(f"{prec}:{tag}", i)] = t
+                recs = costmodel.harvest(p, tag=f"{prec}:{tag}", reps=reps)
+            records += recs
+            log(f"harvest {prec} {tag}: {len(recs)} records in {time.time() - t0:.1f}s "
+                f"(total {len(records)})")
+    return records, defaults
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--out", default=costmodel.DEFAULT_MODEL)
+    ap.add_argument("--records", default=None, help="also write the harvested records (JSON)")
+    ap.add_argument("--circuits", type=int, default=32)
+    ap.add_argument("--held-out", type=int, default=8)
+    ap.add_argument("--precisions", default="f16x3,c64,bf16x3")
+    ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    import torch
+    if not torch.cuda.is_available():
+        sys.exit("no GPU")
+    t0 = time.time()
+    records, defaults = harvest_all(args.circuits, args.precisions.split(","), args.reps)
+    if args.records:
+        with open(args.records, "w") as f:
+            json.dump({"records": records,
+                       "defaults": {f"{k[0]}:{k[1]}": v for k, v in defaults.items()}}, f)
+    held = {f"u{i}" for i in range(max(0, args.circuits - args.held_out), args.circuits)}
+    held |= {"rqc30", "rqc30sb1"}
+    train = [r for r in records if r["tag"].split(":")[1] not in held]
+    test = [r for r in records if r["tag"].split(":")[1] in held]
+    X, us = costmodel.records_to_arrays(train)
+    with costmodel.CostModel(seed=args.seed) as m:
+        loss = m.fit(X, us, epochs=args.epochs, batch=256, lr=2e-3, seed=args.seed + 1)
+        Xt, ust = costmodel.records_to_arrays(test)
+        err = m.predict(Xt) - np.log(ust)
+        held_rep = costmodel.tile_choice_report(test, m, defaults)
+        train_rep = costmodel.tile_choice_report(train, m, defaults)
+        meta = {"train_records": len(train), "held_out_records": len(test), "train_mse_ln_us": loss,
+                "held_out_rmse_ln_us": float(np.sqrt(np.mean(err ** 2))),
+                "held_out_median_abs_rel_err": float(np.median(np.abs(np.expm1(err)))),
+                "held_out_tile_choice_us": held_rep, "train_tile_choice_us": train_rep,
+                "harvest_and_training_s": round(time.time() - t0, 1),
+                "device": torch.cuda.get_device_name(0)}
+        m.save(args.out, meta=meta)
+    log(json.dumps(meta))
+
+
+if __name__ == "__main__":
+    main()

@@ -31,7 +31,8 @@ def _data(seed, n, F):
     X = X.astype(np.float32)
     t = (np.sin(X[:, 0]) + 0.3 * X[:, 1 % F] - 0.1 * X[:, 2 % F] ** 2).astype(np.float32)
     mean = X.mean(0).astype(np.float32)
-    std = X.std(0).astype(np.float32)
+    std = X.std(0)
+    std = np.where(std > 0, std, 1.0).astype(np.float32)   # one sample: unit scale
     return X, t, mean, std
 
 
@@ -65,8 +66,8 @@ def test_gradient_and_loss_match_oracle(F, n):
         ref_l = mlp.loss(theta, X, t, F, H, mean, std)
         assert _rel(g, ref_g) <= 1e-4, _rel(g, ref_g)
         assert abs(loss - ref_l) <= 1e-5 * max(1.0, ref_l)
-        # every parameter block receives gradient
-        assert np.count_nonzero(g) > 0.5 * g.size
+        if n > 1:   # (one sample standardises to x' = 0: only the later layers see gradient)
+            assert np.count_nonzero(g) > 0.5 * g.size
 
 
 def test_adam_steps_match_oracle():
