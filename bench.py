@@ -32,8 +32,20 @@ if ROOT not in sys.path:
 
 PEAK = {"f16x3": ("mfma", 2500.0, "fp16 MFMA"), "bf16x3": ("mfma", 2500.0, "bf16 MFMA"),
         "c64": ("mfma", 157.3, "fp32 MFMA")}
-KERNEL_NAME = {0: "k_gett_small", 1: "k_gett_mfma<0>", 2: "k_gett_mfma<1>", 3: "k_gett_mfma<2>"}
 PRODUCTS = {0: 1, 1: 1, 2: 3, 3: 3}
+WAVES = {0: (4, 2), 1: (2, 2), 2: (2, 1), 3: (1, 1)}
+
+
+def kernel_name(step) -> str:
+    """The kernel instance a step launches, as rocprofv3 names it (without arguments)."""
+    kind = step["kernel"]
+    if kind == 0:
+        return "k_gett_small"
+    p = kind - 1
+    if step.get("lds_copy"):
+        return f"void k_gett_dma<{p}>"
+    wm, wn = WAVES[step["tile"]]
+    return f"void k_gett_mfma<{p}, {wm}, {wn}>"
 
 
 def log(*a):
@@ -67,14 +79,15 @@ def run_precision(tn, torch, net, best, prec, steps, warmup, sample_slice, tunin
     amps, count = plan.amplitudes()
     assert count == steps * n_slices
     amps = amps / steps
-    part = plan.partials([sample_slice])[0]
+    part = plan.partials(sample_slice)
     plan.close()
     flops_step = info["flops_invariant"] + n_slices * info["flops_per_slice"]
     # per kernel kind: total algorithmic flops and measured time in the timed region
     by_kind = {}
     for s, ms, nl in zip(st, step_ms, launches):
         reps = steps * (n_slices if s["per_slice"] else 1)
-        d = by_kind.setdefault(s["kernel"], {"ms": 0.0, "flops": 0.0, "launches": 0})
+        d = by_kind.setdefault(kernel_name(s), {"ms": 0.0, "flops": 0.0, "launches": 0,
+                                                "products": PRODUCTS[s["kernel"]]})
         d["ms"] += float(ms)
         d["flops"] += s["flops"] * reps
         d["launches"] += int(nl)
@@ -83,7 +96,7 @@ def run_precision(tn, torch, net, best, prec, steps, warmup, sample_slice, tunin
         s = st[i]
         reps = steps * (n_slices if s["per_slice"] else 1)
         tf = s["flops"] * reps / (step_ms[i] * 1e-3) / 1e12 if step_ms[i] > 0 else 0.0
-        log(f"    step {i:3d} {KERNEL_NAME[s['kernel']]:16s} tile {s['tile_m']}x{s['tile_n']} "
+        log(f"    step {i:3d} {kernel_name(s):28s} tile {s['tile_m']}x{s['tile_n']} "
             f"split {s['split_k']:3d} m={s['m']} n={s['n']} k={s['k']} b={s['batch']} "
             f"{step_ms[i] / steps:8.2f} ms/pass {tf:7.1f} TFLOPS")
     return {"info": info, "ms_per_step": ms_per_step, "flops_step": flops_step, "plan_s": plan_s,
@@ -138,7 +151,40 @@ def run_batching(tn, torch, configs, net, best, prec, n_small, n_slices, steps):
             "amplitudes_identical": bool(same), "precision": prec}
 
 
-def cpu_baseline(net, best, sample_slice, flops_slice):
+def run_tuning_modes(tn, torch, net, best, prec, n_slices):
+    """Whole-plan time over n_slices slices with tiles from the shape heuristic, the learned
+    step-time model and measured autotuning (a9 / a10)."""
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, tuning in (("heuristic", 0), ("learned_model", 2), ("autotune", 1)):
+        t0 = time.perf_counter()
+        with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best["sliced"],
+                     precision=prec, stream=stream, tuning=tuning) as p:
+            plan_s = time.perf_counter() - t0
+            p.contract(0, 8)
+            torch.cuda.synchronize()
+            s = torch.cuda.Event(enable_timing=True)
+            e = torch.cuda.Event(enable_timing=True)
+            s.record(stream)
+            p.contract(0, n_slices)
+            e.record(stream)
+            torch.cuda.synchronize()
+            out[name] = {"ms": round(s.elapsed_time(e), 3), "plan_s": round(plan_s, 3)}
+            p.amplitudes()
+    out["slices"] = n_slices
+    out["precision"] = prec
+    out["learned_vs_heuristic_speedup"] = round(out["heuristic"]["ms"] / out["learned_model"]["ms"], 3)
+    return out
+
+
+def sample_slices(n_slices: int, count: int, seed: int = 137):
+    """Seeded sample of distinct slice ids (sorted)."""
+    rng = np.random.default_rng(seed)
+    return sorted(int(x) for x in rng.choice(n_slices, size=min(count, n_slices), replace=False))
+
+
+def cpu_baseline(net, best, ids, flops_slice):
+    """The complex128 oracle on the host cores over the sampled slices: (partials, record)."""
     from oracle import contract
     threads = os.cpu_count()
     try:
@@ -149,13 +195,15 @@ def cpu_baseline(net, best, sample_slice, flops_slice):
     except Exception:
         pass
     t0 = time.perf_counter()
-    ref = contract.contract_slice(net.tensors, net.labels, net.open_labels, best["path"],
-                                  best["sliced"], sample_slice)
+    refs = [contract.contract_slice(net.tensors, net.labels, net.open_labels, best["path"],
+                                    best["sliced"], sid) for sid in ids]
     dt = time.perf_counter() - t0
-    return ref, {"value": flops_slice / dt / 1e12, "unit": "TFLOPS", "cores": threads,
-                 "kind": "oracle", "slices_per_s": 1.0 / dt, "seconds": dt,
-                 "sample": f"1 slice (id {sample_slice}) of the same workload, complex128 numpy "
-                           f"tensordot along the same path; flops counted as for the GPU"}
+    n = len(ids)
+    return np.asarray(refs), {
+        "value": flops_slice * n / dt / 1e12, "unit": "TFLOPS", "cores": threads, "kind": "oracle",
+        "slices_per_s": n / dt, "seconds": dt,
+        "sample": f"{n} slices (seeded ids {ids}) of the same workload, complex128 numpy "
+                  f"tensordot along the same path; flops counted as for the GPU"}
 
 
 def counter_run(tn, torch, net, best, precs):
@@ -188,9 +236,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rqc30")
     ap.add_argument("--precisions", default="f16x3,c64")
-    ap.add_argument("--sample-slice", type=int, default=137)
+    ap.add_argument("--cpu-slices", type=int, default=8,
+                    help="slices in the CPU oracle sample (and in the per-slice error check)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", type=int, default=1, help="1 = autotune tile shapes at plan creation")
+    ap.add_argument("--no-tuning-modes", dest="tuning_modes", action="store_false",
+                    help="skip the heuristic / learned-model / autotune comparison")
     ap.add_argument("--batching", type=int, default=64,
                     help="uneven circuits in the batching-form measurement (0 = skip it)")
     ap.add_argument("--counter-run", action="store_true",
@@ -216,11 +267,15 @@ def main():
     if args.counter_run:
         counter_run(tn, torch, net, best, precs)
         return
+    n_slices_total = 1
+    for lab in best["sliced"]:
+        n_slices_total *= net.extents()[lab]
+    sample_ids = sample_slices(n_slices_total, args.cpu_slices)
     runs = {}
     for prec in precs:
         log(f"running {prec}: warmup {args.warmup}, steps {args.steps}")
         runs[prec] = run_precision(tn, torch, net, best, prec, args.steps, args.warmup,
-                                   args.sample_slice, args.tuning)
+                                   sample_ids, args.tuning)
         r = runs[prec]
         log(f"  {prec}: {r['ms_per_step']:.1f} ms/step, {r['tflops']:.1f} TFLOPS, "
             f"{r['slices_per_s']:.1f} slices/s")
@@ -233,16 +288,16 @@ def main():
     dom = max(kinds, key=lambda k: kinds[k]["ms"])
     dk = kinds[dom]
     achieved = dk["flops"] / (dk["ms"] * 1e-3) / 1e12
-    bound, peak, peak_name = PEAK[head] if dom != 0 else ("alu", 78.6, "fp32 vector")
-    roof = {"bound": bound, "kernel": KERNEL_NAME[dom], "achieved": round(achieved, 2),
+    bound, peak, peak_name = PEAK[head] if dom != "k_gett_small" else ("alu", 157.3, "fp32 vector")
+    roof = {"bound": bound, "kernel": dom, "achieved": round(achieved, 2),
             "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
             "launches": dk["launches"], "avg_launch_ms": round(dk["ms"] / max(dk["launches"], 1), 4),
             "flops_per_launch": dk["flops"] / max(dk["launches"], 1),
             "time_share": round(dk["ms"] / sum(v["ms"] for v in kinds.values()), 4),
             "peak_dtype": peak_name}
-    if PRODUCTS[dom] > 1:
-        roof["executed_mfma_tflops"] = round(achieved * PRODUCTS[dom], 2)
-        roof["executed_frac"] = round(achieved * PRODUCTS[dom] / peak, 4)
+    if dk["products"] > 1:
+        roof["executed_mfma_tflops"] = round(achieved * dk["products"], 2)
+        roof["executed_frac"] = round(achieved * dk["products"] / peak, 4)
 
     out = {"metric": "sliced-contraction TFLOPS & slices/s, FP16-scaled vs complex64, <=1e-3 amp err",
            "value": round(main_run["tflops"], 3), "unit": "TFLOPS", "n_gpus": 1,
@@ -264,19 +319,26 @@ def main():
         ref_c64 = runs["c64"]["amps"]
         out["rel_l2_vs_c64_full"] = float(np.linalg.norm(main_run["amps"] - ref_c64) / np.linalg.norm(ref_c64))
     out["roofline"] = roof
+    if args.tuning_modes:
+        log("tile choice: shape heuristic vs learned model vs autotune on 32 slices")
+        out["tile_choice"] = run_tuning_modes(tn, torch, net, best, head, 32)
+        log(f"  {out['tile_choice']}")
     if args.batching > 0:
         log(f"batching form: {args.batching} uneven circuits + slices [0, 32) of {args.workload}")
         out["batching"] = run_batching(tn, torch, configs, net, best, head, args.batching, 32, 3)
         log(f"  {out['batching']}")
     if not args.no_cpu_baseline:
         from oracle import metrics
-        ref, cb = cpu_baseline(net, best, args.sample_slice,
+        ref, cb = cpu_baseline(net, best, sample_ids,
                                info["flops_per_slice"] + info["flops_invariant"])
         out["cpu_baseline"] = cb
         for prec, r in runs.items():
-            out[prec]["rel_l2_vs_oracle_slice"] = metrics.rel_l2(r["partial"], ref)
-            out[prec]["eps_l2sq_vs_oracle_slice"] = metrics.eps_l2sq(r["partial"], ref)
-            out[prec]["fidelity_vs_oracle_slice"] = metrics.fidelity(r["partial"], ref)
+            # a11: errors of the sampled slices' amplitudes against the complex128 oracle
+            per = [metrics.rel_l2(a, b) for a, b in zip(r["partial"], ref)]
+            out[prec]["vs_oracle_slices"] = {
+                "slices": len(per), "rel_l2": metrics.rel_l2(r["partial"], ref),
+                "rel_l2_max_slice": max(per), "eps_l2sq": metrics.eps_l2sq(r["partial"], ref),
+                "fidelity": metrics.fidelity(r["partial"], ref)}
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

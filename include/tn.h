@@ -111,7 +111,8 @@ typedef struct {
   int32_t a_contig, b_contig;  /* log2 of the contiguous run (elements) of A and B along the tile */
   double flops, bytes;
   int32_t tile;                /* tile id (0..3, see TN_N_TILE_SHAPES) of an MFMA step; -1 for the small kernel */
-  int32_t reserved;
+  int32_t lds_copy;            /* 1 = split operands copied global -> LDS without registers (three-stage
+                                  pipeline; both operands stored split, k pairs contiguous, 256 x 128 tiles) */
 } tn_step_info;
 
 /* Build a plan.

@@ -41,6 +41,8 @@ DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
 class CostModel:
     """Owning wrapper of a tn_costmodel handle (parameters live on the GPU)."""
 
+    handle = None
+
     def __init__(self, n_features: int = N_FEATURES, seed: int = 0):
         self.handle = tn.tn_costmodel_create(n_features, seed)
         self.n_features, self.hidden, self.n_params = tn.tn_costmodel_describe(self.handle)

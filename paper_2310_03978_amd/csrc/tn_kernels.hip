@@ -10,6 +10,10 @@
 //                     FP32 (lo*lo dropped).  WM x WN waves, 64 x 64 complex outputs
 //                     per wave, K step 16 complex, double-buffered LDS with the next
 //                     stage prefetched into registers during the MFMA phase.
+//  k_gett_dma<P>      the split kernels' 256 x 128 tile for steps whose operands are
+//                     both stored split with k pairs contiguous: operands are copied
+//                     global -> LDS by the DMA path (no registers, no LDS stores),
+//                     three stages deep, one barrier per stage.
 //  k_splitk_reduce    sums K partitions in fixed order, writes C in its layout.
 //  k_permute          LDS-staged index permutation, coalesced on both sides.
 //  k_slice_reduce     FP64 cross-slice sum in increasing slice order.
@@ -289,6 +293,41 @@ struct Tile {
 };
 }  // namespace
 
+// Coordinates of one output tile: block -> (tile_m, tile_n, batch, K split), with
+// tiles in groups of 4 (m) x 8 (n) so that blocks resident together share A and B
+// panels in L2.
+struct TileCtx {
+  uint64_t tile_m, tile_n, bidx;
+  int split, nbb, lm, ln, lk, sl;
+  Scales sc;
+};
+
+template <int WM, int WN>
+__device__ __forceinline__ TileCtx tile_ctx(const GettDesc* __restrict__ d, const GettArgs& g, uint64_t bid) {
+  TileCtx c;
+  c.nbb = d->own_bb + g.chunk_bits;
+  const int tmb = g.tiles_m_bits, tnb = g.tiles_n_bits;
+  const uint64_t tix = bid & ((1ull << (tmb + tnb)) - 1);
+  bid >>= tmb + tnb;
+  const int gm = tmb < 2 ? tmb : 2, gn = tnb < 3 ? tnb : 3;
+  c.tile_m = (tix & ((1ull << gm) - 1)) | (((tix >> (gm + gn)) & ((1ull << (tmb - gm)) - 1)) << gm);
+  c.tile_n = ((tix >> gm) & ((1ull << gn) - 1)) | ((tix >> (gm + gn + tmb - gm)) << gn);
+  c.bidx = bid & ((1ull << c.nbb) - 1);
+  c.split = (int)(bid >> c.nbb);
+  constexpr int LMAX = WM == 4 ? 8 : WM == 2 ? 7 : 6;
+  constexpr int NMAX = WN == 4 ? 8 : WN == 2 ? 7 : 6;
+  c.lm = d->mb < LMAX ? d->mb : LMAX;
+  c.ln = d->nb < NMAX ? d->nb : NMAX;
+  c.lk = d->kb < 4 ? d->kb : 4;
+  c.sl = (int)(c.bidx >> d->own_bb);
+  c.sc = step_scales(d, g, c.sl);
+  return c;
+}
+
+template <int P, int WM, int WN>
+__device__ __forceinline__ void store_tile(const GettDesc* __restrict__ d, const GettArgs& g, const TileCtx& cx,
+                           floatx16 (&acc)[2][4], uint32_t* smem, uint32_t* red);
+
 // One output tile of an MFMA step; `bid` is the step's block index.
 template <int P, int WM, int WN>
 __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g, uint64_t bid, uint32_t* smem,
@@ -298,26 +337,10 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int wm = w / WN, wn = w % WN;
-  const int nbb = d->own_bb + g.chunk_bits;
-
-  // block -> (tile_m, tile_n, batch, split): tiles in groups of 4 (m) x 8 (n)
-  // so that blocks resident together share A and B panels in L2.
-  const int tmb = g.tiles_m_bits, tnb = g.tiles_n_bits;
-  const uint64_t tix = bid & ((1ull << (tmb + tnb)) - 1);
-  bid >>= tmb + tnb;
-  const int gm = tmb < 2 ? tmb : 2, gn = tnb < 3 ? tnb : 3;
-  const uint64_t tile_m = (tix & ((1ull << gm) - 1)) | (((tix >> (gm + gn)) & ((1ull << (tmb - gm)) - 1)) << gm);
-  const uint64_t tile_n = ((tix >> gm) & ((1ull << gn) - 1)) | ((tix >> (gm + gn + tmb - gm)) << gn);
-  const uint64_t bidx = bid & ((1ull << nbb) - 1);
-  const int split = (int)(bid >> nbb);
-
-  constexpr int LMAX = WM == 4 ? 8 : WM == 2 ? 7 : 6;
-  constexpr int NMAX = WN == 4 ? 8 : WN == 2 ? 7 : 6;
-  const int lm = d->mb < LMAX ? d->mb : LMAX;
-  const int ln = d->nb < NMAX ? d->nb : NMAX;
-  const int lk = d->kb < 4 ? d->kb : 4;
-  const int sl = (int)(bidx >> d->own_bb);
-  const Scales sc = step_scales(d, g, sl);
+  const TileCtx cx = tile_ctx<WM, WN>(d, g, bid);
+  const int nbb = cx.nbb, lm = cx.lm, ln = cx.ln, lk = cx.lk, split = cx.split;
+  const uint64_t tile_m = cx.tile_m, tile_n = cx.tile_n, bidx = cx.bidx;
+  const Scales& sc = cx.sc;
   constexpr bool bf = P == 2;
 
   const int64_t a_base = bits_offset(bidx, d->a_b, nbb) + bits_offset(tile_m << lm, d->a_m, d->mb);
@@ -531,7 +554,22 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
     __syncthreads();
   }
 
-  // ---- epilogue: accumulators -> LDS (64 rows per pass) -> global ----
+  store_tile<P, WM, WN>(d, g, cx, acc, smem, red);
+}
+
+// Epilogue: accumulators -> LDS (64 rows per pass) -> C in its layout and format
+// (or split-K partials to scratch), plus the tile's contribution to C's maximum.
+template <int P, int WM, int WN>
+__device__ __forceinline__ void store_tile(const GettDesc* __restrict__ d, const GettArgs& g, const TileCtx& cx,
+                           floatx16 (&acc)[2][4], uint32_t* smem, uint32_t* red) {
+  using T = Tile<P, WM, WN>;
+  constexpr int NT = T::NT, TB = T::TB;
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int wm = w / WN, wn = w % WN;
+  const int nbb = cx.nbb, lm = cx.lm, ln = cx.ln, split = cx.split, sl = cx.sl;
+  const uint64_t tile_m = cx.tile_m, tile_n = cx.tile_n, bidx = cx.bidx;
+  const Scales& sc = cx.sc;
   float* Cs = reinterpret_cast<float*>(smem);
   const int64_t N_loc = (int64_t)1 << ln;
   const int64_t Mtot = (int64_t)1 << d->mb, Ntot = (int64_t)1 << d->nb;
@@ -595,6 +633,172 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
       write_exp(g, sl, sc);
     if (g.maxC) block_umax_atomic(mx, g.maxC + (g.c_ps ? sl : 0), red);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Split-precision tile with operands copied global -> LDS by the DMA path
+// (global_load_lds_dwordx4), three LDS stages deep.  For steps whose operands
+// are both stored split and contiguous along k bit 0 (two consecutive k are one
+// 16-byte pair), tile 256 x 128 complex, 8 waves.  No operand data passes
+// through registers on its way to LDS, so the copy of stage k + 2 is in flight
+// while stage k is multiplied, with one barrier per stage.
+//
+// LDS stage: A rows [256][16 k], then B columns [128][16 k]; one 128-byte row
+// holds eight 16-byte slots of two elements (hi word, lo word each), and the
+// slot of element pair s in row r is s ^ (r & 7), so the 8 lanes of one LDS
+// read phase hit 8 distinct slots.  A DMA instruction of a wave fills 1 KiB of
+// LDS (8 rows) in lane order; each lane fetches the pair that belongs in its slot.
+// Fragments: lane (r, half) of A takes k = 4 * half .. 4 * half + 3 of row r as
+// hi and lo words; B's real column 2n + p is built from complex column n as
+// (Br, -Bi) for p = 0 and (Bi, Br) for p = 1, the same operands the staged
+// kernel forms in LDS.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int DMA_STAGES = 3;
+constexpr int DMA_A_BYTES = 256 * 128, DMA_B_BYTES = 128 * 128;
+constexpr int DMA_STAGE_BYTES = DMA_A_BYTES + DMA_B_BYTES;
+constexpr int DMA_SMEM = DMA_STAGES * DMA_STAGE_BYTES;    // 144 KiB (the epilogue reuses it)
+static_assert(DMA_SMEM >= 4 * 64 * (2 * 128 + 8), "epilogue staging must fit");
+
+// s_waitcnt with only the vector-memory counter constrained (gfx9 encoding:
+// vmcnt bits 3:0 and 15:14, expcnt 6:4 = 7, lgkmcnt 11:8 = 15).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  __builtin_amdgcn_s_waitcnt((N & 0xf) | (0x7 << 4) | (0xf << 8) | ((N >> 4) << 14));
+}
+}  // namespace
+
+template <int P>
+__device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g, uint64_t bid, uint32_t* smem,
+                              uint32_t* red) {
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const TileCtx cx = tile_ctx<4, 2>(d, g, bid);
+  const int nbb = cx.nbb;
+
+  const int64_t a_base = bits_offset(cx.bidx, d->a_b, nbb) + bits_offset(cx.tile_m << 8, d->a_m, d->mb);
+  const int64_t b_base = bits_offset(cx.bidx, d->b_b, nbb) + bits_offset(cx.tile_n << 7, d->b_n, d->nb);
+  const uint2* A = reinterpret_cast<const uint2*>(g.A);
+  const uint2* B = reinterpret_cast<const uint2*>(g.B);
+  char* lds = reinterpret_cast<char*>(smem);
+
+  // The pair each lane copies: DMA instruction i of wave w fills rows (8 i + w) * 8 + lane / 8
+  // (A: i < 4, 256 rows; B: i < 2, 128 columns); lane slot p = lane % 8 holds pair p ^ (row & 7).
+  const int prow = lane >> 3, pslot = lane & 7;
+  int32_t a_pair[4], b_pair[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = (8 * i + w) * 8 + prow;
+    const int k = 2 * (pslot ^ (r & 7));
+    a_pair[i] = (int32_t)(bits_offset((uint64_t)r, d->a_m, 8) + bits_offset((uint64_t)k, d->a_k, 4));
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int c = (8 * i + w) * 8 + prow;
+    const int k = 2 * (pslot ^ (c & 7));
+    b_pair[i] = (int32_t)(bits_offset((uint64_t)c, d->b_n, 7) + bits_offset((uint64_t)k, d->b_k, 4));
+  }
+
+  const int64_t n_iters = (int64_t)1 << (g.k_split_bits - 4);
+  const int64_t k_first = (int64_t)cx.split << g.k_split_bits;
+  int64_t ak = a_base + bits_offset(k_first, d->a_k, d->kb);
+  int64_t bk = b_base + bits_offset(k_first, d->b_k, d->kb);
+  int64_t next_it = 0;   // stage whose copy is issued next
+  auto issue = [&]() {
+    char* st = lds + (int)(next_it % DMA_STAGES) * DMA_STAGE_BYTES;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      __builtin_amdgcn_global_load_lds(A + ak + a_pair[i], st + (8 * i + w) * 1024, 16, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      __builtin_amdgcn_global_load_lds(B + bk + b_pair[i], st + DMA_A_BYTES + (8 * i + w) * 1024, 16, 0, 0);
+    if (next_it + 1 < n_iters) {
+      const int tz = __builtin_ctzll(~(uint64_t)next_it);
+      ak += d->a_kd[tz];
+      bk += d->b_kd[tz];
+    }
+    ++next_it;
+  };
+
+  floatx16 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+  // per-lane B expansion: real column parity p -> rotate by 16 bits (p = 1) or
+  // flip the sign of the imaginary half (p = 0)
+  const uint32_t b_rot = (lane & 1) ? 16u : 0u;
+  const uint32_t b_flip = (lane & 1) ? 0u : 0x80000000u;
+  const int half = lane >> 5;
+
+  issue();
+  if (n_iters > 1) issue();
+  for (int64_t it = 0; it < n_iters; ++it) {
+    if (it + 1 < n_iters) wait_vmcnt<6>();   // this stage's 6 copies are done, the next stage's may fly
+    else wait_vmcnt<0>();
+    // Every wave's copies of this stage have landed and every wave is done reading
+    // stage it - 1 (its reads completed before its last MFMA of that stage).  A plain
+    // barrier with a compiler memory clobber: a fence here would also wait for the
+    // copies of the next stage.
+    asm volatile("s_barrier" ::: "memory");
+    if (it + 2 < n_iters) issue();
+    const char* st = lds + (int)(it % DMA_STAGES) * DMA_STAGE_BYTES;
+#pragma unroll 1
+    for (int ks = 0; ks < 2; ++ks) {
+      const int s0 = ks * 4 + half * 2;      // first pair of this lane's 4 k
+      u32x4 ah[2], al[2], bh[4], bl[4];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) {
+        const int r = wm * 64 + mi * 32 + (lane & 31);
+        const u32x4 x0 = *reinterpret_cast<const u32x4*>(st + r * 128 + ((s0 ^ (r & 7)) << 4));
+        const u32x4 x1 = *reinterpret_cast<const u32x4*>(st + r * 128 + (((s0 + 1) ^ (r & 7)) << 4));
+        ah[mi] = u32x4{x0.x, x0.z, x1.x, x1.z};
+        al[mi] = u32x4{x0.y, x0.w, x1.y, x1.w};
+      }
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) {
+        const int n = (wn * 128 + ni * 32 + (lane & 31)) >> 1;
+        const char* bp = st + DMA_A_BYTES + n * 128;
+        const u32x4 x0 = *reinterpret_cast<const u32x4*>(bp + ((s0 ^ (n & 7)) << 4));
+        const u32x4 x1 = *reinterpret_cast<const u32x4*>(bp + (((s0 + 1) ^ (n & 7)) << 4));
+        bh[ni] = u32x4{__builtin_amdgcn_alignbit(x0.x, x0.x, b_rot) ^ b_flip,
+                       __builtin_amdgcn_alignbit(x0.z, x0.z, b_rot) ^ b_flip,
+                       __builtin_amdgcn_alignbit(x1.x, x1.x, b_rot) ^ b_flip,
+                       __builtin_amdgcn_alignbit(x1.z, x1.z, b_rot) ^ b_flip};
+        bl[ni] = u32x4{__builtin_amdgcn_alignbit(x0.y, x0.y, b_rot) ^ b_flip,
+                       __builtin_amdgcn_alignbit(x0.w, x0.w, b_rot) ^ b_flip,
+                       __builtin_amdgcn_alignbit(x1.y, x1.y, b_rot) ^ b_flip,
+                       __builtin_amdgcn_alignbit(x1.w, x1.w, b_rot) ^ b_flip};
+      }
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(ah[mi], bh[ni], acc[mi][ni]);
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(ah[mi], bl[ni], acc[mi][ni]);
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(al[mi], bh[ni], acc[mi][ni]);
+    }
+  }
+  __syncthreads();   // the epilogue reuses the stage buffers
+  store_tile<P, 4, 2>(d, g, cx, acc, smem, red);
+}
+
+template <int P>
+__global__ __launch_bounds__(512, 2) void k_gett_dma(const GettDesc* __restrict__ d, GettArgs g) {
+  extern __shared__ __align__(16) uint32_t smem[];
+  __shared__ uint32_t red[16];
+  uint64_t bid = blockIdx.x;
+  if ((gridDim.x & 7u) == 0) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
+  gett_dma_tile<P>(d, g, bid, smem, red);
 }
 
 template <int P, int WM, int WN>
@@ -770,7 +974,17 @@ hipError_t launch_mfma(const GettDesc* d, const GettArgs& g, int64_t blocks, hip
 }
 
 template <int P>
+hipError_t launch_dma(const GettDesc* d, const GettArgs& g, int64_t blocks, hipStream_t s) {
+  hipError_t e = tn_prepare_kernels();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_gett_dma<P>), dim3((unsigned)blocks), dim3(512), DMA_SMEM, s, d, g);
+  return hipGetLastError();
+}
+
+template <int P>
 hipError_t launch_mfma_tile(int tile, const GettDesc* d, const GettArgs& g, int64_t blocks, hipStream_t s) {
+  if constexpr (P != 0)
+    if (g.dma && tile == TN_TILE_256x128) return launch_dma<P>(d, g, blocks, s);
   switch (tile) {
     case TN_TILE_256x128: return launch_mfma<P, 4, 2>(d, g, blocks, s);
     case TN_TILE_128x128: return launch_mfma<P, 2, 2>(d, g, blocks, s);
@@ -845,6 +1059,8 @@ hipError_t tn_prepare_kernels() {
   TN_SET_ATTR(1, 4, 2); TN_SET_ATTR(1, 2, 2); TN_SET_ATTR(1, 2, 1); TN_SET_ATTR(1, 1, 1);
   TN_SET_ATTR(2, 4, 2); TN_SET_ATTR(2, 2, 2); TN_SET_ATTR(2, 2, 1); TN_SET_ATTR(2, 1, 1);
 #undef TN_SET_ATTR
+  set(reinterpret_cast<const void*>(&k_gett_dma<1>), DMA_SMEM);
+  set(reinterpret_cast<const void*>(&k_gett_dma<2>), DMA_SMEM);
   if (e == hipSuccess) done = true;
   return e;
 }

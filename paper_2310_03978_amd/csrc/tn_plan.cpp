@@ -93,6 +93,7 @@ struct Step {
   int k_split_bits = 0;
   int tiles_m_bits = 0, tiles_n_bits = 0;
   int a_contig = 0, b_contig = 0;
+  bool dma = false;                  // split tile 256x128 fed by global -> LDS copies
   double flops = 0, bytes = 0;
   int64_t scratch_elems = 0;         // split-K partials (elements)
   GettDesc desc;
@@ -333,6 +334,11 @@ void build_desc(tn_plan_s* p, Step& st) {
   fill_enum(d.ec, vc, vpass);
   st.a_contig = contig_run(d.ea);
   st.b_contig = contig_run(d.eb);
+  // the global -> LDS copy path: both operands stored split, pairs of consecutive k
+  // adjacent in memory, full 256 x 128 tiles and whole 16-k stages
+  st.dma = (st.kernel == TN_K_MFMA_F16X3 || st.kernel == TN_K_MFMA_BF16X3) && st.tile == TN_TILE_256x128 &&
+           A.fmt == TN_FMT_SPLIT && B.fmt == TN_FMT_SPLIT && d.mb >= 8 && d.nb >= 7 && d.kb >= 4 &&
+           st.k_split_bits >= 4 && d.a_k[0] == 1 && d.b_k[0] == 1;
 }
 
 // Tile shape and K split of an MFMA step.
@@ -987,6 +993,7 @@ void step_launches(const tn_plan_s* p, const Step& st, const GettDesc* d, int s,
   g.fb = B.fmt;
   g.fc = C.fmt;
   g.split_bf16 = p->precision == TN_PREC_BF16X3 ? 1 : 0;
+  g.dma = st.dma ? 1 : 0;
   L.desc = d;
   L.step = s;
   L.kind = st.kernel;
@@ -1371,6 +1378,7 @@ tn_status tn_plan_steps(tn_plan p, tn_step_info* steps, int32_t cap) {
     o.flops = st.flops;
     o.bytes = st.bytes;
     o.tile = st.kernel == TN_K_SMALL ? -1 : st.tile;
+    o.lds_copy = st.dma ? 1 : 0;
   }
   return TN_OK;
 }

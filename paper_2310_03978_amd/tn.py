@@ -12,6 +12,14 @@ import os
 
 import numpy as np
 
+# One HIP runtime per process: torch ships its own libamdhip64.so.7.  Loaded first, it
+# satisfies the library's dependency on that soname; loaded after the library, a second
+# runtime would come in beside /opt/rocm's and the two would not share devices' state.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libtnmi.so")
 
@@ -73,7 +81,7 @@ class tn_step_info(ctypes.Structure):
                 ("k", ctypes.c_int64), ("split_k", ctypes.c_int32), ("tile_m", ctypes.c_int32),
                 ("tile_n", ctypes.c_int32), ("a_contig", ctypes.c_int32),
                 ("b_contig", ctypes.c_int32), ("flops", ctypes.c_double),
-                ("bytes", ctypes.c_double), ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("bytes", ctypes.c_double), ("tile", ctypes.c_int32), ("lds_copy", ctypes.c_int32)]
 
 
 _P = ctypes.POINTER
@@ -316,6 +324,8 @@ def tn_group_destroy(group):
 class Group:
     """Owning wrapper around a group of plans (the plans must outlive it)."""
 
+    handle = None
+
     def __init__(self, plans, stream=None, branches: int = 0):
         self.plans = list(plans)
         self.handle = tn_group_create([p.handle for p in self.plans], stream, branches)
@@ -460,10 +470,23 @@ def tn_permute(x, perm, out, stream=None):
 
 
 class Plan:
-    """Owning wrapper around a plan handle."""
+    """Owning wrapper around a plan handle.
+
+    tuning: 0 = tile shapes from the shape heuristic, 1 = measured autotuning at creation
+    (both in the library), 2 = tiles chosen by the learned step-time model shipped with the
+    package (loaded here and applied with tn_plan_tune_with_model)."""
+
+    handle = None
 
     def __init__(self, tensors, labels, open_labels, path, sliced_labels=(), **kw):
+        learned = kw.get("tuning", 0) == 2
+        if learned:
+            kw["tuning"] = 0
         self.handle = tn_plan_create(tensors, labels, open_labels, path, sliced_labels, **kw)
+        if learned:
+            from .costmodel import CostModel
+            with CostModel.load() as model:
+                self.tune_with_model(model)
 
     def close(self):
         if self.handle:

@@ -141,3 +141,32 @@ def test_costmodel_errors():
         with pytest.raises(tn.TnError):
             m.set_params(np.zeros(3, np.float32))
         assert m.predict(np.zeros((0, 4), np.float32)).shape == (0,)
+
+
+def test_shipped_model_tiles_are_correct_and_beat_the_heuristic():
+    """The trained model shipped with the package (costmodel.DEFAULT_MODEL) picks tiles that
+    (a) give oracle-exact amplitudes and (b) on the 30-qubit sliced workload -- held out of
+    its training data -- measure faster than the shape heuristic's and near the fastest tile."""
+    from oracle import contract, metrics
+    from tn_inputs import configs
+    print("costmodel shipped model", flush=True)
+    with costmodel.CostModel.load() as m:
+        _, net, best = configs.build("rqc12")
+        ref = contract.amplitudes(net.tensors, net.labels, net.open_labels, best["path"])
+        with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], precision="f16x3",
+                     split_policy=1) as p:
+            pred = p.tune_with_model(m)
+            assert np.all(pred > 0)
+            p.contract()
+            got, _ = p.amplitudes()
+        assert metrics.rel_l2(got, ref) <= 1e-3
+        _, net, best = configs.build("rqc30")
+        with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best["sliced"],
+                     precision="f16x3", record_steps=True) as p:
+            dflt = {("rqc30", i): t for i, t in enumerate(costmodel.step_tile_ids(p))}
+            recs = costmodel.harvest(p, tag="rqc30", reps=2)
+        rep = costmodel.tile_choice_report(recs, m, dflt)
+        print(rep, flush=True)
+        assert rep["steps"] >= 10
+        assert rep["model"] <= 1.02 * rep["heuristic"], rep
+        assert rep["model"] <= 1.08 * rep["best"], rep

@@ -135,6 +135,29 @@ def test_large_random_steps_use_mfma_and_match():
         assert metrics.rel_l2(got, ref) <= TOL[prec], prec
 
 
+@pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
+@pytest.mark.parametrize("K", [16, 32, 256, 2048])
+def test_lds_copy_pipeline_matches_oracle(prec, K):
+    """Both operands of the last step are split-stored intermediates with contiguous k: the
+    step runs the global -> LDS copy pipeline (1, 2 and many K stages, split K, a batch label)."""
+    print(f"lds copy {prec} K={K}", flush=True)
+    rng = np.random.default_rng(K)
+    b, m, n, k1 = 2, 512, 256, 4
+    # X[b m k1] Y[b k1 k] -> P[b m k];  Z[b k k1'] W[b k1' n] -> Q[b k n];  P Q -> R[b m n]
+    labels = [(0, 1, 2), (0, 2, 3), (0, 3, 4), (0, 4, 5)]
+    shapes = [(b, m, k1), (b, k1, K), (b, K, k1), (b, k1, n)]
+    tensors = [(_crandn(rng, sh) / np.sqrt(sh[-1])).astype(np.complex128) for sh in shapes]
+    net = Network(tensors=tensors, labels=labels, open_labels=(0, 1, 5))
+    path = [(0, 1), (2, 3), (0, 2)]
+    ref = contract.amplitudes(net.tensors, net.labels, net.open_labels, path)
+    with tn.Plan(net.tensors, net.labels, net.open_labels, path, (), precision=prec) as p:
+        last = p.steps()[2]
+        p.contract()
+        got, _ = p.amplitudes()
+    assert last["lds_copy"] == 1, last
+    assert metrics.rel_l2(got, ref) <= TOL[prec]
+
+
 def test_chunking_accumulation_and_resume():
     print("chunking", flush=True)
     circ, net, best = configs.build("rqc12")
