@@ -750,42 +750,50 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
 #pragma unroll 1
     for (int ks = 0; ks < 2; ++ks) {
       const int s0 = ks * 4 + half * 2;      // first pair of this lane's 4 k
-      u32x4 ah[2], al[2], bh[4], bl[4];
+      // all LDS reads of the K step first (A, then B column by column), so that the
+      // products of the first columns can start while later columns are in flight
+      u32x4 xa[2][2], xb[4][2];
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi) {
         const int r = wm * 64 + mi * 32 + (lane & 31);
-        const u32x4 x0 = *reinterpret_cast<const u32x4*>(st + r * 128 + ((s0 ^ (r & 7)) << 4));
-        const u32x4 x1 = *reinterpret_cast<const u32x4*>(st + r * 128 + (((s0 + 1) ^ (r & 7)) << 4));
-        ah[mi] = u32x4{x0.x, x0.z, x1.x, x1.z};
-        al[mi] = u32x4{x0.y, x0.w, x1.y, x1.w};
+        xa[mi][0] = *reinterpret_cast<const u32x4*>(st + r * 128 + ((s0 ^ (r & 7)) << 4));
+        xa[mi][1] = *reinterpret_cast<const u32x4*>(st + r * 128 + (((s0 + 1) ^ (r & 7)) << 4));
       }
 #pragma unroll
       for (int ni = 0; ni < 4; ++ni) {
         const int n = (wn * 128 + ni * 32 + (lane & 31)) >> 1;
         const char* bp = st + DMA_A_BYTES + n * 128;
-        const u32x4 x0 = *reinterpret_cast<const u32x4*>(bp + ((s0 ^ (n & 7)) << 4));
-        const u32x4 x1 = *reinterpret_cast<const u32x4*>(bp + (((s0 + 1) ^ (n & 7)) << 4));
-        bh[ni] = u32x4{__builtin_amdgcn_alignbit(x0.x, x0.x, b_rot) ^ b_flip,
-                       __builtin_amdgcn_alignbit(x0.z, x0.z, b_rot) ^ b_flip,
-                       __builtin_amdgcn_alignbit(x1.x, x1.x, b_rot) ^ b_flip,
-                       __builtin_amdgcn_alignbit(x1.z, x1.z, b_rot) ^ b_flip};
-        bl[ni] = u32x4{__builtin_amdgcn_alignbit(x0.y, x0.y, b_rot) ^ b_flip,
-                       __builtin_amdgcn_alignbit(x0.w, x0.w, b_rot) ^ b_flip,
-                       __builtin_amdgcn_alignbit(x1.y, x1.y, b_rot) ^ b_flip,
-                       __builtin_amdgcn_alignbit(x1.w, x1.w, b_rot) ^ b_flip};
+        xb[ni][0] = *reinterpret_cast<const u32x4*>(bp + ((s0 ^ (n & 7)) << 4));
+        xb[ni][1] = *reinterpret_cast<const u32x4*>(bp + (((s0 + 1) ^ (n & 7)) << 4));
+      }
+      u32x4 ah[2], al[2], bh[4], bl[4];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) {
+        ah[mi] = u32x4{xa[mi][0].x, xa[mi][0].z, xa[mi][1].x, xa[mi][1].z};
+        al[mi] = u32x4{xa[mi][0].y, xa[mi][0].w, xa[mi][1].y, xa[mi][1].w};
+      }
+      auto expand = [&](uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3) {
+        return u32x4{__builtin_amdgcn_alignbit(w0, w0, b_rot) ^ b_flip, __builtin_amdgcn_alignbit(w1, w1, b_rot) ^ b_flip,
+                     __builtin_amdgcn_alignbit(w2, w2, b_rot) ^ b_flip, __builtin_amdgcn_alignbit(w3, w3, b_rot) ^ b_flip};
+      };
+      // hi x hi, column-major over the wave tile (dependent products on one
+      // accumulator stay 8 MFMAs apart)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) {
+        bh[ni] = expand(xb[ni][0].x, xb[ni][0].z, xb[ni][1].x, xb[ni][1].z);
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(ah[mi], bh[ni], acc[mi][ni]);
       }
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int ni = 0; ni < 4; ++ni) {
+        bl[ni] = expand(xb[ni][0].y, xb[ni][0].w, xb[ni][1].y, xb[ni][1].w);
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(ah[mi], bh[ni], acc[mi][ni]);
+        for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(ah[mi], bl[ni], acc[mi][ni]);
+      }
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int ni = 0; ni < 4; ++ni)
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(ah[mi], bl[ni], acc[mi][ni]);
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(al[mi], bh[ni], acc[mi][ni]);
+        for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(al[mi], bh[ni], acc[mi][ni]);
     }
   }
   __syncthreads();   // the epilogue reuses the stage buffers
