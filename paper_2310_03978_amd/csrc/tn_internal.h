@@ -45,6 +45,11 @@ struct GettDesc {
   // by a_kd[t] / b_kd[t], t = trailing one bits of s:
   //   kd[t] = k_stride[4 + t] - sum_{j < t} k_stride[4 + j].
   int64_t a_kd[TN_MAXK], b_kd[TN_MAXK];
+  // k_linear = 1 when the k bits above the stage have strides kstep << j in both
+  // operands: the offset of stage s is then s * kstep and no table is read
+  int64_t a_kstep, b_kstep;
+  int32_t k_linear;
+  int32_t pad_k;
   // role of each storage position of C, LSB first (own layout then slice-local bits):
   // (role << 8) | index, role 0 = batch, 1 = m, 2 = n
   int32_t c_pos[TN_MAXR + TN_MAXB];

@@ -324,7 +324,10 @@ __device__ __forceinline__ TileCtx tile_ctx(const GettDesc* __restrict__ d, cons
   return c;
 }
 
-template <int P, int WM, int WN>
+// PAIRED: the accumulator's 32 columns of block ni hold, in lanes 0-15, the real parts
+// and, in lanes 16-31, the imaginary parts of 16 complex columns (else real columns
+// 2n, 2n + 1 sit in adjacent lanes).
+template <int P, int WM, int WN, bool PAIRED = false>
 __device__ __forceinline__ void store_tile(const GettDesc* __restrict__ d, const GettArgs& g, const TileCtx& cx,
                            floatx16 (&acc)[2][4], uint32_t* smem, uint32_t* red);
 
@@ -400,6 +403,8 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
   // operand offsets of the current K stage, advanced with the per-stage deltas
   int64_t ak = a_base + bits_offset(k_first, d->a_k, d->kb);
   int64_t bk = b_base + bits_offset(k_first, d->b_k, d->kb);
+  const bool k_linear = d->k_linear != 0;
+  const int64_t a_kstep = d->a_kstep, b_kstep = d->b_kstep;
   auto load_stage = [&]() {
 #pragma unroll
     for (int i = 0; i < IA; ++i) ra[i] = A[ak + ia_off[i]];
@@ -536,9 +541,14 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
     uint32_t* nxt = smem + ((kit + 1) & 1) * T::BUF;
     const bool more = kit + 1 < n_iters;
     if (more) {
-      const int t = __builtin_ctzll(~(uint64_t)kit);
-      ak += d->a_kd[t];
-      bk += d->b_kd[t];
+      if (k_linear) {
+        ak += a_kstep;
+        bk += b_kstep;
+      } else {
+        const int t = __builtin_ctzll(~(uint64_t)kit);
+        ak += d->a_kd[t];
+        bk += d->b_kd[t];
+      }
       load_stage();
     }
     if constexpr (P == 0) {
@@ -559,7 +569,7 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
 
 // Epilogue: accumulators -> LDS (64 rows per pass) -> C in its layout and format
 // (or split-K partials to scratch), plus the tile's contribution to C's maximum.
-template <int P, int WM, int WN>
+template <int P, int WM, int WN, bool PAIRED>
 __device__ __forceinline__ void store_tile(const GettDesc* __restrict__ d, const GettArgs& g, const TileCtx& cx,
                            floatx16 (&acc)[2][4], uint32_t* smem, uint32_t* red) {
   using T = Tile<P, WM, WN>;
@@ -599,7 +609,7 @@ __device__ __forceinline__ void store_tile(const GettDesc* __restrict__ d, const
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const int row = mi * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-            const int col = wn * 128 + ni * 32 + (lane & 31);
+            const int col = wn * 128 + ni * 32 + (PAIRED ? 2 * (lane & 15) + ((lane >> 4) & 1) : (lane & 31));
             Cs[row * T::LDC + col] = acc[mi][ni][v];
           }
     }
@@ -644,14 +654,13 @@ __device__ __forceinline__ void store_tile(const GettDesc* __restrict__ d, const
 // while stage k is multiplied, with one barrier per stage.
 //
 // LDS stage: A rows [256][16 k], then B columns [128][16 k]; one 128-byte row
-// holds eight 16-byte slots of two elements (hi word, lo word each), and the
-// slot of element pair s in row r is s ^ (r & 7), so the 8 lanes of one LDS
-// read phase hit 8 distinct slots.  A DMA instruction of a wave fills 1 KiB of
+// holds eight 16-byte slots of two elements (hi word, lo word each), XOR-swizzled
+// per row (dma_swz) so that the lanes of one LDS read phase hit distinct banks.  A DMA instruction of a wave fills 1 KiB of
 // LDS (8 rows) in lane order; each lane fetches the pair that belongs in its slot.
 // Fragments: lane (r, half) of A takes k = 4 * half .. 4 * half + 3 of row r as
-// hi and lo words; B's real column 2n + p is built from complex column n as
-// (Br, -Bi) for p = 0 and (Bi, Br) for p = 1, the same operands the staged
-// kernel forms in LDS.
+// hi and lo words; B's real columns are built from complex column n as (Br, -Bi)
+// (real part of output column n) and (Bi, Br) (imaginary part), the same operands
+// the staged kernel forms in LDS, with the two parts in lanes j and j + 16.
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int DMA_STAGES = 3;
@@ -662,6 +671,10 @@ static_assert(DMA_SMEM >= 4 * 64 * (2 * 128 + 8), "epilogue staging must fit");
 
 // s_waitcnt with only the vector-memory counter constrained (gfx9 encoding:
 // vmcnt bits 3:0 and 15:14, expcnt 6:4 = 7, lgkmcnt 11:8 = 15).
+// 16-byte slot of pair s in row r is s ^ dma_swz(r): 8 consecutive rows hit 8 distinct
+// slots, and 16 consecutive rows 16 distinct (row parity, slot) bank groups
+__device__ __forceinline__ int dma_swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 0xf) | (0x7 << 4) | (0xf << 8) | ((N >> 4) << 14));
@@ -690,13 +703,13 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int r = (8 * i + w) * 8 + prow;
-    const int k = 2 * (pslot ^ (r & 7));
+    const int k = 2 * (pslot ^ dma_swz(r));
     a_pair[i] = (int32_t)(bits_offset((uint64_t)r, d->a_m, 8) + bits_offset((uint64_t)k, d->a_k, 4));
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const int c = (8 * i + w) * 8 + prow;
-    const int k = 2 * (pslot ^ (c & 7));
+    const int k = 2 * (pslot ^ dma_swz(c));
     b_pair[i] = (int32_t)(bits_offset((uint64_t)c, d->b_n, 7) + bits_offset((uint64_t)k, d->b_k, 4));
   }
 
@@ -704,6 +717,8 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
   const int64_t k_first = (int64_t)cx.split << g.k_split_bits;
   int64_t ak = a_base + bits_offset(k_first, d->a_k, d->kb);
   int64_t bk = b_base + bits_offset(k_first, d->b_k, d->kb);
+  const bool k_linear = d->k_linear != 0;
+  const int64_t a_kstep = d->a_kstep, b_kstep = d->b_kstep;
   int64_t next_it = 0;   // stage whose copy is issued next
   auto issue = [&]() {
     char* st = lds + (int)(next_it % DMA_STAGES) * DMA_STAGE_BYTES;
@@ -714,9 +729,14 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
     for (int i = 0; i < 2; ++i)
       __builtin_amdgcn_global_load_lds(B + bk + b_pair[i], st + DMA_A_BYTES + (8 * i + w) * 1024, 16, 0, 0);
     if (next_it + 1 < n_iters) {
-      const int tz = __builtin_ctzll(~(uint64_t)next_it);
-      ak += d->a_kd[tz];
-      bk += d->b_kd[tz];
+      if (k_linear) {
+        ak += a_kstep;
+        bk += b_kstep;
+      } else {
+        const int tz = __builtin_ctzll(~(uint64_t)next_it);
+        ak += d->a_kd[tz];
+        bk += d->b_kd[tz];
+      }
     }
     ++next_it;
   };
@@ -729,10 +749,11 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
-  // per-lane B expansion: real column parity p -> rotate by 16 bits (p = 1) or
-  // flip the sign of the imaginary half (p = 0)
-  const uint32_t b_rot = (lane & 1) ? 16u : 0u;
-  const uint32_t b_flip = (lane & 1) ? 0u : 0x80000000u;
+  // B fragment of block ni: lanes j < 16 form (Br, -Bi) and lanes j >= 16 (Bi, Br) of
+  // complex column ni * 16 + j % 16 (real part and imaginary part of that output
+  // column), so the lanes of one LDS read phase fetch distinct columns
+  const uint32_t b_rot = (lane & 16) ? 16u : 0u;
+  const uint32_t b_flip = (lane & 16) ? 0u : 0x80000000u;
   const int half = lane >> 5;
 
   issue();
@@ -756,15 +777,15 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi) {
         const int r = wm * 64 + mi * 32 + (lane & 31);
-        xa[mi][0] = *reinterpret_cast<const u32x4*>(st + r * 128 + ((s0 ^ (r & 7)) << 4));
-        xa[mi][1] = *reinterpret_cast<const u32x4*>(st + r * 128 + (((s0 + 1) ^ (r & 7)) << 4));
+        xa[mi][0] = *reinterpret_cast<const u32x4*>(st + r * 128 + ((s0 ^ dma_swz(r)) << 4));
+        xa[mi][1] = *reinterpret_cast<const u32x4*>(st + r * 128 + (((s0 + 1) ^ dma_swz(r)) << 4));
       }
 #pragma unroll
       for (int ni = 0; ni < 4; ++ni) {
-        const int n = (wn * 128 + ni * 32 + (lane & 31)) >> 1;
+        const int n = wn * 64 + ni * 16 + (lane & 15);
         const char* bp = st + DMA_A_BYTES + n * 128;
-        xb[ni][0] = *reinterpret_cast<const u32x4*>(bp + ((s0 ^ (n & 7)) << 4));
-        xb[ni][1] = *reinterpret_cast<const u32x4*>(bp + (((s0 + 1) ^ (n & 7)) << 4));
+        xb[ni][0] = *reinterpret_cast<const u32x4*>(bp + ((s0 ^ dma_swz(n)) << 4));
+        xb[ni][1] = *reinterpret_cast<const u32x4*>(bp + (((s0 + 1) ^ dma_swz(n)) << 4));
       }
       u32x4 ah[2], al[2], bh[4], bl[4];
 #pragma unroll
@@ -797,7 +818,7 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
     }
   }
   __syncthreads();   // the epilogue reuses the stage buffers
-  store_tile<P, 4, 2>(d, g, cx, acc, smem, red);
+  store_tile<P, 4, 2, true>(d, g, cx, acc, smem, red);
 }
 
 template <int P>

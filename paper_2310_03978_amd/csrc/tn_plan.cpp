@@ -304,6 +304,11 @@ void build_desc(tn_plan_s* p, Step& st) {
       sa += d.a_k[k0 + t];
       sb += d.b_k[k0 + t];
     }
+    d.a_kstep = k0 < d.kb ? d.a_k[k0] : 0;
+    d.b_kstep = k0 < d.kb ? d.b_k[k0] : 0;
+    d.k_linear = 1;
+    for (int t = 0; k0 + t < d.kb; ++t)
+      if (d.a_k[k0 + t] != (d.a_kstep << t) || d.b_k[k0 + t] != (d.b_kstep << t)) d.k_linear = 0;
   }
   for (size_t pos = 0; pos < C.bits.size(); ++pos) {
     const int q = C.bits[pos];
