@@ -81,6 +81,11 @@ struct GettArgs {
 // Storage formats of an intermediate.  TN_FMT_SPLIT keeps, per complex element,
 // the word (hi_re, hi_im) and the word (lo_re, lo_im) of 16-bit halves with
 // hi = rn(x), lo = rn(x - hi) of the scaled value: 8 bytes, like complex64.
+// The words are blocked by 4 elements: for the group of elements 4g .. 4g + 3 the
+// four hi words come first, then the four lo words (word 8g + j holds hi of element
+// 4g + j, word 8g + 4 + j its lo), so four consecutive k of one operand row are one
+// 16-byte hi quad and one 16-byte lo quad.  Split tensors have a multiple of 4
+// elements.
 #define TN_FMT_C64 0
 #define TN_FMT_SPLIT 1
 

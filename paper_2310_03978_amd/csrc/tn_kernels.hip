@@ -161,13 +161,19 @@ __device__ __forceinline__ void write_exp(const GettArgs& g, int sl, const Scale
   g.expC[g.c_ps ? sl : 0] = g.expA[g.a_ps ? sl : 0] + g.expB[g.b_ps ? sl : 0] - sc.sa - sc.sb - sc.t;
 }
 
+// Word index of the hi word of element `off` in the blocked split format (the lo
+// word is 4 words further).
+__device__ __forceinline__ int64_t split_hi_word(int64_t off) { return 2 * (off & ~int64_t(3)) + (off & 3); }
+
 // Store one result element in C's format; returns the bits of its max(|re|, |im|).
 __device__ __forceinline__ uint32_t store_c(float* C, int64_t off, float2 v, const GettArgs& g, float ft) {
   v.x *= ft;
   v.y *= ft;
   if (g.fc == TN_FMT_SPLIT) {
     const uint2 w = split_pair(v.x, v.y, g.split_bf16 != 0);
-    reinterpret_cast<uint2*>(C)[off] = w;
+    uint32_t* Cw = reinterpret_cast<uint32_t*>(C) + split_hi_word(off);
+    Cw[0] = w.x;
+    Cw[4] = w.y;
     return abs_bits(split_value(w, g.split_bf16 != 0));
   }
   reinterpret_cast<float2*>(C)[off] = v;
@@ -405,11 +411,31 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
   int64_t bk = b_base + bits_offset(k_first, d->b_k, d->kb);
   const bool k_linear = d->k_linear != 0;
   const int64_t a_kstep = d->a_kstep, b_kstep = d->b_kstep;
+  // split-stored operands: hi and lo words of an element sit 4 words apart
+  const bool a_split = g.fa == TN_FMT_SPLIT, b_split = g.fb == TN_FMT_SPLIT;
+  const uint32_t* Aw = reinterpret_cast<const uint32_t*>(g.A);
+  const uint32_t* Bw = reinterpret_cast<const uint32_t*>(g.B);
   auto load_stage = [&]() {
+    if (a_split) {
 #pragma unroll
-    for (int i = 0; i < IA; ++i) ra[i] = A[ak + ia_off[i]];
+      for (int i = 0; i < IA; ++i) {
+        const uint32_t* q = Aw + split_hi_word(ak + ia_off[i]);
+        ra[i] = make_uint2(q[0], q[4]);
+      }
+    } else {
 #pragma unroll
-    for (int i = 0; i < IB; ++i) rb[i] = B[bk + ib_off[i]];
+      for (int i = 0; i < IA; ++i) ra[i] = A[ak + ia_off[i]];
+    }
+    if (b_split) {
+#pragma unroll
+      for (int i = 0; i < IB; ++i) {
+        const uint32_t* q = Bw + split_hi_word(bk + ib_off[i]);
+        rb[i] = make_uint2(q[0], q[4]);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < IB; ++i) rb[i] = B[bk + ib_off[i]];
+    }
   };
   auto store_stage = [&](uint32_t* buf) {
     if constexpr (P == 0) {
@@ -692,26 +718,31 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
 
   const int64_t a_base = bits_offset(cx.bidx, d->a_b, nbb) + bits_offset(cx.tile_m << 8, d->a_m, d->mb);
   const int64_t b_base = bits_offset(cx.bidx, d->b_b, nbb) + bits_offset(cx.tile_n << 7, d->b_n, d->nb);
-  const uint2* A = reinterpret_cast<const uint2*>(g.A);
-  const uint2* B = reinterpret_cast<const uint2*>(g.B);
   char* lds = reinterpret_cast<char*>(smem);
 
-  // The pair each lane copies: DMA instruction i of wave w fills rows (8 i + w) * 8 + lane / 8
-  // (A: i < 4, 256 rows; B: i < 2, 128 columns); lane slot p = lane % 8 holds pair p ^ (row & 7).
+  // The quad each lane copies: DMA instruction i of wave w fills rows (8 i + w) * 8 + lane / 8
+  // (A: i < 4, 256 rows; B: i < 2, 128 columns).  Logical slot s of a row holds the hi
+  // (s even) or lo (s odd) quad of k = 4 (s / 2) .. 4 (s / 2) + 3; the lane in physical
+  // slot p = lane % 8 copies logical slot p ^ dma_swz(row).  a_word / b_word: word offset
+  // of that quad from the stage's element offset (doubled: two words per element).
   const int prow = lane >> 3, pslot = lane & 7;
-  int32_t a_pair[4], b_pair[2];
+  int32_t a_word[4], b_word[2];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int r = (8 * i + w) * 8 + prow;
-    const int k = 2 * (pslot ^ dma_swz(r));
-    a_pair[i] = (int32_t)(bits_offset((uint64_t)r, d->a_m, 8) + bits_offset((uint64_t)k, d->a_k, 4));
+    const int sl = pslot ^ dma_swz(r);
+    a_word[i] = (int32_t)(2 * (bits_offset((uint64_t)r, d->a_m, 8) + bits_offset((uint64_t)(4 * (sl >> 1)), d->a_k, 4)) +
+                          4 * (sl & 1));
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const int c = (8 * i + w) * 8 + prow;
-    const int k = 2 * (pslot ^ dma_swz(c));
-    b_pair[i] = (int32_t)(bits_offset((uint64_t)c, d->b_n, 7) + bits_offset((uint64_t)k, d->b_k, 4));
+    const int sl = pslot ^ dma_swz(c);
+    b_word[i] = (int32_t)(2 * (bits_offset((uint64_t)c, d->b_n, 7) + bits_offset((uint64_t)(4 * (sl >> 1)), d->b_k, 4)) +
+                          4 * (sl & 1));
   }
+  const uint32_t* Aw = reinterpret_cast<const uint32_t*>(g.A);
+  const uint32_t* Bw = reinterpret_cast<const uint32_t*>(g.B);
 
   const int64_t n_iters = (int64_t)1 << (g.k_split_bits - 4);
   const int64_t k_first = (int64_t)cx.split << g.k_split_bits;
@@ -724,10 +755,10 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
     char* st = lds + (int)(next_it % DMA_STAGES) * DMA_STAGE_BYTES;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      __builtin_amdgcn_global_load_lds(A + ak + a_pair[i], st + (8 * i + w) * 1024, 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(Aw + 2 * ak + a_word[i], st + (8 * i + w) * 1024, 16, 0, 0);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
-      __builtin_amdgcn_global_load_lds(B + bk + b_pair[i], st + DMA_A_BYTES + (8 * i + w) * 1024, 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(Bw + 2 * bk + b_word[i], st + DMA_A_BYTES + (8 * i + w) * 1024, 16, 0, 0);
     if (next_it + 1 < n_iters) {
       if (k_linear) {
         ak += a_kstep;
@@ -770,7 +801,7 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
     const char* st = lds + (int)(it % DMA_STAGES) * DMA_STAGE_BYTES;
 #pragma unroll 1
     for (int ks = 0; ks < 2; ++ks) {
-      const int s0 = ks * 4 + half * 2;      // first pair of this lane's 4 k
+      const int s0 = ks * 4 + half * 2;      // hi slot of this lane's 4 k (lo slot: s0 + 1)
       // all LDS reads of the K step first (A, then B column by column), so that the
       // products of the first columns can start while later columns are in flight
       u32x4 xa[2][2], xb[4][2];
@@ -789,25 +820,25 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
       }
       u32x4 ah[2], al[2], bh[4], bl[4];
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi) {
-        ah[mi] = u32x4{xa[mi][0].x, xa[mi][0].z, xa[mi][1].x, xa[mi][1].z};
-        al[mi] = u32x4{xa[mi][0].y, xa[mi][0].w, xa[mi][1].y, xa[mi][1].w};
+      for (int mi = 0; mi < 2; ++mi) {   // slot 2q: hi quad, slot 2q + 1: lo quad
+        ah[mi] = xa[mi][0];
+        al[mi] = xa[mi][1];
       }
-      auto expand = [&](uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3) {
-        return u32x4{__builtin_amdgcn_alignbit(w0, w0, b_rot) ^ b_flip, __builtin_amdgcn_alignbit(w1, w1, b_rot) ^ b_flip,
-                     __builtin_amdgcn_alignbit(w2, w2, b_rot) ^ b_flip, __builtin_amdgcn_alignbit(w3, w3, b_rot) ^ b_flip};
+      auto expand = [&](const u32x4& x) {
+        return u32x4{__builtin_amdgcn_alignbit(x.x, x.x, b_rot) ^ b_flip, __builtin_amdgcn_alignbit(x.y, x.y, b_rot) ^ b_flip,
+                     __builtin_amdgcn_alignbit(x.z, x.z, b_rot) ^ b_flip, __builtin_amdgcn_alignbit(x.w, x.w, b_rot) ^ b_flip};
       };
       // hi x hi, column-major over the wave tile (dependent products on one
       // accumulator stay 8 MFMAs apart)
 #pragma unroll
       for (int ni = 0; ni < 4; ++ni) {
-        bh[ni] = expand(xb[ni][0].x, xb[ni][0].z, xb[ni][1].x, xb[ni][1].z);
+        bh[ni] = expand(xb[ni][0]);
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(ah[mi], bh[ni], acc[mi][ni]);
       }
 #pragma unroll
       for (int ni = 0; ni < 4; ++ni) {
-        bl[ni] = expand(xb[ni][0].y, xb[ni][0].w, xb[ni][1].y, xb[ni][1].w);
+        bl[ni] = expand(xb[ni][1]);
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(ah[mi], bl[ni], acc[mi][ni]);
       }

@@ -339,11 +339,11 @@ void build_desc(tn_plan_s* p, Step& st) {
   fill_enum(d.ec, vc, vpass);
   st.a_contig = contig_run(d.ea);
   st.b_contig = contig_run(d.eb);
-  // the global -> LDS copy path: both operands stored split, pairs of consecutive k
-  // adjacent in memory, full 256 x 128 tiles and whole 16-k stages
+  // the global -> LDS copy path: both operands stored split, quads of consecutive k
+  // adjacent in memory (one hi quad, one lo quad), full 256 x 128 tiles and whole 16-k stages
   st.dma = (st.kernel == TN_K_MFMA_F16X3 || st.kernel == TN_K_MFMA_BF16X3) && st.tile == TN_TILE_256x128 &&
            A.fmt == TN_FMT_SPLIT && B.fmt == TN_FMT_SPLIT && d.mb >= 8 && d.nb >= 7 && d.kb >= 4 &&
-           st.k_split_bits >= 4 && d.a_k[0] == 1 && d.b_k[0] == 1;
+           st.k_split_bits >= 4 && d.a_k[0] == 1 && d.a_k[1] == 2 && d.b_k[0] == 1 && d.b_k[1] == 2;
 }
 
 // Tile shape and K split of an MFMA step.
@@ -750,6 +750,9 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
     for (int x : {st.ta, st.tb})
       if (!p->tensors[x].leaf) p->tensors[x].fmt = TN_FMT_SPLIT;
   }
+  for (const Tensor& T : p->tensors)   // the split format is blocked by 4 elements
+    if (T.fmt == TN_FMT_SPLIT && (T.elems & 3) != 0)
+      return fail(TN_E_STATE, "internal: a split-stored tensor has fewer than 4 elements");
   for (size_t s = 0; s < p->steps.size(); ++s)
     (p->steps[s].per_slice ? p->ps_order : p->inv_order).push_back((int)s);
   // memory: leaves, invariant arena, per-slice arena (S copies of each tensor)
