@@ -86,10 +86,11 @@ def run_precision(tn, torch, net, best, prec, steps, warmup, sample_slice, tunin
     by_kind = {}
     for s, ms, nl in zip(st, step_ms, launches):
         reps = steps * (n_slices if s["per_slice"] else 1)
-        d = by_kind.setdefault(kernel_name(s), {"ms": 0.0, "flops": 0.0, "launches": 0,
+        d = by_kind.setdefault(kernel_name(s), {"ms": 0.0, "flops": 0.0, "bytes": 0.0, "launches": 0,
                                                 "products": PRODUCTS[s["kernel"]]})
         d["ms"] += float(ms)
         d["flops"] += s["flops"] * reps
+        d["bytes"] += s["bytes"] * reps
         d["launches"] += int(nl)
     top = sorted(range(len(st)), key=lambda i: -step_ms[i])[:8]
     for i in top:
@@ -177,10 +178,86 @@ def run_tuning_modes(tn, torch, net, best, prec, n_slices):
     return out
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "gett_rqc30_counters.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2310_03978_amd", "csrc", "tn_kernels.hip")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
+    when there is none for it or the kernel source changed since the counters were taken
+    (the summary records the SHA-256 of tn_kernels.hip it was measured with)."""
+    import hashlib
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if f"kernel source sha256: {src}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic per launch:") and f"`{kernel}`" in line:
+            return float(line.rsplit(" ", 2)[-2])
+    return None
+
+
 def sample_slices(n_slices: int, count: int, seed: int = 137):
     """Seeded sample of distinct slice ids (sorted)."""
     rng = np.random.default_rng(seed)
     return sorted(int(x) for x in rng.choice(n_slices, size=min(count, n_slices), replace=False))
+
+
+def run_slicing_choice(tn, torch, net, prec, cap_log2, n_sliced, n_candidates, n_slices):
+    """Contraction trees with their slicings (randomised greedy paths, each sliced to the
+    cap) ranked two ways: by flops (T_cc) and by the learned model's predicted time; the
+    pick of each is then timed on the GPU over the same number of slices."""
+    from paper_2310_03978_amd import costmodel
+    from tn_inputs.paths import choose_slices, greedy_path
+    ext = net.extents()
+    cands = []
+    for t in range(n_candidates):
+        path = greedy_path(net.labels, net.open_labels, ext, seed=7000 + t,
+                           temperature=0.0 if t == 0 else 0.3)
+        sliced = choose_slices(net.labels, net.open_labels, ext, path, cap_log2,
+                               min_sliced=n_sliced, max_sliced=n_sliced)
+        if len(sliced) != n_sliced:
+            continue
+        cands.append((path, sliced))
+    with costmodel.CostModel.load() as model:
+        scored = []
+        for path, sliced in cands:
+            with tn.Plan(net.tensors, net.labels, net.open_labels, path, sliced, precision=prec,
+                         host_only=True) as h:
+                info = h.describe()
+                flops = info["flops_invariant"] + n_slices * info["flops_per_slice"]
+                scored.append((flops, costmodel.predict_plan_us(h, model, n_slices), path, sliced))
+    by_flops = min(range(len(scored)), key=lambda i: scored[i][0])
+    by_model = min(range(len(scored)), key=lambda i: scored[i][1])
+    stream = torch.cuda.current_stream()
+
+    def measure(i):
+        _, _, path, sliced = scored[i]
+        with tn.Plan(net.tensors, net.labels, net.open_labels, path, sliced, precision=prec,
+                     stream=stream, tuning=2) as p:
+            p.contract(0, min(8, n_slices))
+            torch.cuda.synchronize()
+            s = torch.cuda.Event(enable_timing=True)
+            e = torch.cuda.Event(enable_timing=True)
+            s.record(stream)
+            p.contract(0, n_slices)
+            e.record(stream)
+            torch.cuda.synchronize()
+            p.amplitudes()
+            return s.elapsed_time(e)
+
+    ms_flops = measure(by_flops)
+    ms_model = ms_flops if by_model == by_flops else measure(by_model)
+    return {"candidates": len(scored), "cap_log2": cap_log2, "sliced_labels": n_sliced,
+            "slices_timed": n_slices, "precision": prec,
+            "pick_by_flops": {"candidate": by_flops, "flops": scored[by_flops][0],
+                              "predicted_ms": round(scored[by_flops][1] / 1e3, 3), "measured_ms": round(ms_flops, 3)},
+            "pick_by_model": {"candidate": by_model, "flops": scored[by_model][0],
+                              "predicted_ms": round(scored[by_model][1] / 1e3, 3), "measured_ms": round(ms_model, 3)},
+            "model_vs_flops_speedup": round(ms_flops / ms_model, 3)}
 
 
 def cpu_baseline(net, best, ids, flops_slice):
@@ -242,6 +319,8 @@ def main():
     ap.add_argument("--tuning", type=int, default=1, help="1 = autotune tile shapes at plan creation")
     ap.add_argument("--no-tuning-modes", dest="tuning_modes", action="store_false",
                     help="skip the heuristic / learned-model / autotune comparison")
+    ap.add_argument("--slicing-candidates", type=int, default=12,
+                    help="candidate trees for the flops-vs-learned-model slicing choice (0 = skip)")
     ap.add_argument("--batching", type=int, default=64,
                     help="uneven circuits in the batching-form measurement (0 = skip it)")
     ap.add_argument("--counter-run", action="store_true",
@@ -290,9 +369,11 @@ def main():
     achieved = dk["flops"] / (dk["ms"] * 1e-3) / 1e12
     bound, peak, peak_name = PEAK[head] if dom != "k_gett_small" else ("alu", 157.3, "fp32 vector")
     roof = {"bound": bound, "kernel": dom, "achieved": round(achieved, 2),
-            "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+            "traffic": measured_traffic(dom),
             "launches": dk["launches"], "avg_launch_ms": round(dk["ms"] / max(dk["launches"], 1), 4),
             "flops_per_launch": dk["flops"] / max(dk["launches"], 1),
+            "algorithmic_bytes_per_launch": dk["bytes"] / max(dk["launches"], 1),
             "time_share": round(dk["ms"] / sum(v["ms"] for v in kinds.values()), 4),
             "peak_dtype": peak_name}
     if dk["products"] > 1:
@@ -323,6 +404,12 @@ def main():
         log("tile choice: shape heuristic vs learned model vs autotune on 32 slices")
         out["tile_choice"] = run_tuning_modes(tn, torch, net, best, head, 32)
         log(f"  {out['tile_choice']}")
+    if args.slicing_candidates > 0:
+        w_ = configs.WORKLOADS[args.workload]
+        log(f"slicing choice: {args.slicing_candidates} candidate trees, flops vs learned model")
+        out["slicing_choice"] = run_slicing_choice(tn, torch, net, head, w_.cap_log2, w_.n_sliced,
+                                                   args.slicing_candidates, 64)
+        log(f"  {out['slicing_choice']}")
     if args.batching > 0:
         log(f"batching form: {args.batching} uneven circuits + slices [0, 32) of {args.workload}")
         out["batching"] = run_batching(tn, torch, configs, net, best, head, args.batching, 32, 3)

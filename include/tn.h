@@ -79,7 +79,12 @@ typedef struct {
   int32_t tuning;          /* 0 = tile shapes from the shape heuristic; 1 = autotune: time every
                               MFMA step with each tile shape at plan creation and keep the
                               fastest (cached per step signature for the life of the process) */
-  int32_t reserved[5];
+  int32_t reserved;
+  void* workspace;         /* caller-owned device memory for every device buffer of the plan (e.g.
+                              a torch uint8 tensor), or NULL: the library allocates.  It must hold
+                              the workspace_bytes a host-only plan of the same network reports, must
+                              outlive the plan and is not freed by it.  Too small: TN_E_NOMEM. */
+  int64_t workspace_bytes; /* size of workspace */
 } tn_options;
 
 /* Plan summary.  Operation counts follow Sec. 2.4: flops = 8*B*M*N*K per step
@@ -95,7 +100,8 @@ typedef struct {
   double bytes_per_slice;
   double bytes_invariant;
   int64_t max_intermediate;    /* elements of the largest step result (per slice) */
-  int64_t workspace_bytes;     /* device bytes held by the plan */
+  int64_t workspace_bytes;     /* device bytes held by the plan; host-only plans: the bytes a
+                                  caller-owned workspace (tn_options.workspace) must hold */
   int32_t slice_batch;         /* slices per chunk actually used */
   int32_t precision;
 } tn_plan_info;

@@ -125,6 +125,20 @@ class CostModel:
         return m
 
 
+def predict_plan_us(plan, model: CostModel, n_slices: int | None = None) -> float:
+    """Predicted microseconds of contracting n_slices slices (default: all) with the plan's
+    tiles chosen by the model: slice-independent steps once, slice-dependent steps once per
+    chunk of slice_batch slices.  Works on host-only plans."""
+    pred = plan.tune_with_model(model)
+    info = plan.describe()
+    n = info["n_slices"] if n_slices is None else n_slices
+    chunks = -(-n // max(info["slice_batch"], 1))
+    total = 0.0
+    for us, st in zip(pred, plan.steps()):
+        total += float(us) * (chunks if st["per_slice"] else 1)
+    return total
+
+
 # ---------------------------------------------------------------------------
 # Harvesting
 # ---------------------------------------------------------------------------

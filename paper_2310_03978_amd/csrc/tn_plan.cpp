@@ -184,6 +184,11 @@ struct tn_plan_s {
   int32_t* d_flag = nullptr;
   float* d_scratch = nullptr;      // split-K partials, shared by all steps (one stream)
   int64_t scratch_elems = 0;
+  // caller-owned workspace (options.workspace): every device buffer is carved from it
+  bool own_memory = true;
+  char* ws = nullptr;
+  size_t ws_size = 0, ws_used = 0;
+  int64_t ws_need = 0;             // bytes a workspace must hold (computed for every plan)
   int64_t slices_acc = 0;
   size_t device_bytes = 0;
 
@@ -202,8 +207,9 @@ struct tn_plan_s {
     else if (!host_only) hipDeviceSynchronize();
     void* ptrs[] = {d_leaves, d_inv, d_ps, d_desc, d_max_inv, d_max_ps, d_exp_inv, d_exp_ps, d_acc, d_part, d_flag,
                     d_scratch};
-    for (void* p : ptrs)
-      if (p) hipFree(p);
+    if (own_memory)
+      for (void* p : ptrs)
+        if (p) hipFree(p);
     for (auto& t : pending) event_pool.push_back({t.start, t.stop});
     for (auto& e : event_pool) {
       hipEventDestroy(e.first);
@@ -792,11 +798,48 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
   p->S = (int)S;
   for (auto& st : p->steps) p->scratch_elems = std::max(p->scratch_elems, st.scratch_elems);
   if (tn_status vb = validate_bounds(p)) return vb;
+  // a caller-owned workspace reserves split-K scratch for any tile a step may be given later
+  int64_t scratch_any = p->scratch_elems;
+  for (const Step& st0 : p->steps) {
+    if (st0.kernel == TN_K_SMALL) continue;
+    for (int tile = 0; tile < TN_N_TILES; ++tile) {
+      Step c = st0;
+      set_tile(p, c, tile);
+      scratch_any = std::max(scratch_any, c.scratch_elems);
+    }
+  }
+  const size_t nt = p->tensors.size();
+  int64_t max_leaf = 1;
+  for (int t = 0; t < p->n_leaves; ++t) max_leaf = std::max(max_leaf, p->tensors[t].elems << p->tensors[t].sbits.size());
+  const size_t dev_bytes[] = {(size_t)p->leaf_elems * 8, (size_t)p->inv_elems * 8, (size_t)p->ps_elems * 8,
+                              sizeof(GettDesc) * std::max<size_t>(p->steps.size(), 1) + sizeof(PermDesc),
+                              nt * 4, nt * S * 4, nt * 4, nt * S * 4, (size_t)p->n_amp * 16,
+                              (size_t)p->n_amp * 16 * S, 64, (size_t)scratch_any * 8, (size_t)max_leaf * 8};
+  p->ws_need = 0;
+  for (size_t b : dev_bytes) p->ws_need += (int64_t)((b + 255) & ~size_t(255));
   if (p->host_only) return TN_OK;
 
   // ---- device setup ----
   hipStream_t s = p->stream;
+  if (p->opts.workspace) {
+    if (p->opts.workspace_bytes < p->ws_need)
+      return fail(TN_E_NOMEM, "workspace of " + std::to_string(p->opts.workspace_bytes) + " bytes is too small: the plan needs " +
+                                  std::to_string(p->ws_need));
+    p->own_memory = false;
+    p->ws = reinterpret_cast<char*>(p->opts.workspace);
+    p->ws_size = (size_t)p->opts.workspace_bytes;
+    if ((reinterpret_cast<uintptr_t>(p->ws) & 255) != 0) return fail(TN_E_ARG, "workspace must be 256-byte aligned");
+    p->scratch_elems = scratch_any;
+  }
   auto dmalloc = [&](void** ptr, size_t bytes) -> tn_status {
+    if (!p->own_memory) {
+      const size_t b = (bytes + 255) & ~size_t(255);
+      if (p->ws_used + b > p->ws_size) return fail(TN_E_NOMEM, "workspace too small");
+      *ptr = p->ws + p->ws_used;
+      p->ws_used += b;
+      p->device_bytes += b;
+      return TN_OK;
+    }
     if (hipMalloc(ptr, bytes) != hipSuccess) {
       hipGetLastError();
       return fail(TN_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
@@ -804,8 +847,10 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
     p->device_bytes += bytes;
     return TN_OK;
   };
+  auto dfree = [&](void* ptr) {
+    if (p->own_memory) hipFree(ptr);
+  };
   tn_status st;
-  const size_t nt = p->tensors.size();
   if ((st = dmalloc((void**)&p->d_leaves, p->leaf_elems * 8))) return st;
   if ((st = dmalloc((void**)&p->d_inv, p->inv_elems * 8))) return st;
   if ((st = dmalloc((void**)&p->d_ps, p->ps_elems * 8))) return st;
@@ -832,8 +877,6 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
   PermDesc* d_perm = reinterpret_cast<PermDesc*>(p->d_desc + std::max<size_t>(p->steps.size(), 1));
   // leaves: upload complex128 -> complex64 staging, then permute on the device
   float* d_stage = nullptr;
-  int64_t max_leaf = 1;
-  for (int t = 0; t < p->n_leaves; ++t) max_leaf = std::max(max_leaf, p->tensors[t].elems << p->tensors[t].sbits.size());
   if ((st = dmalloc((void**)&d_stage, max_leaf * 8))) return st;
   std::vector<float> host;
   for (int t = 0; t < p->n_leaves; ++t) {
@@ -842,7 +885,7 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
     host.assign(2 * n, 0.f);
     if (t < n_tensors) {
       if (!data[t]) {
-        hipFree(d_stage);
+        dfree(d_stage);
         return fail(TN_E_ARG, "null data for a tensor");
       }
       for (int64_t i = 0; i < 2 * n; ++i) host[i] = (float)data[t][i];
@@ -852,14 +895,14 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
     st = check(hipMemcpyAsync(d_stage, host.data(), n * 8, hipMemcpyHostToDevice, s), "leaf upload");
     if (!st) st = check(hipStreamSynchronize(s), "leaf upload sync");
     if (st) {
-      hipFree(d_stage);
+      dfree(d_stage);
       return st;
     }
     // user layout -> planned layout (bits then sliced bits)
     std::vector<int> full = T.bits;
     full.insert(full.end(), T.sbits.begin(), T.sbits.end());
     if (full.size() != T.user_layout.size()) {
-      hipFree(d_stage);
+      dfree(d_stage);
       return fail(TN_E_STATE, "internal: leaf layout size mismatch");
     }
     std::vector<int> in_pos(full.size()), out_pos(full.size());
@@ -874,20 +917,20 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
       st = permute_bits(in_pos, out_pos, d_stage, dst, s, d_perm);
     }
     if (st) {
-      hipFree(d_stage);
+      dfree(d_stage);
       return st;
     }
     if (scaled(p)) {
       st = check(tn_launch_absmax(dst, n, p->d_max_inv + t, s), "leaf max");
       if (st) {
-        hipFree(d_stage);
+        dfree(d_stage);
         return st;
       }
     }
   }
   st = check(hipStreamSynchronize(s), "setup sync");
-  hipFree(d_stage);
-  p->device_bytes -= max_leaf * 8;
+  dfree(d_stage);
+  if (p->own_memory) p->device_bytes -= max_leaf * 8;
   if (st) return st;
   if (p->opts.tuning == 1) {
     // timing runs read the (zeroed) arenas before any real data is there
@@ -1144,6 +1187,7 @@ std::string step_signature(const tn_plan_s* p, const Step& st) {
 
 tn_status ensure_scratch(tn_plan_s* p, int64_t elems) {
   if (elems <= p->scratch_elems) return TN_OK;
+  if (!p->own_memory) return fail(TN_E_NOMEM, "split-K scratch beyond the workspace reservation");
   tn_status st = check(hipStreamSynchronize(p->stream), "scratch sync");
   if (st) return st;
   if (p->d_scratch) {
@@ -1355,7 +1399,7 @@ tn_status tn_plan_describe(tn_plan p, tn_plan_info* out) {
   out->bytes_per_slice = p->bytes_ps;
   out->bytes_invariant = p->bytes_inv;
   out->max_intermediate = p->max_intermediate;
-  out->workspace_bytes = p->host_only ? (p->leaf_elems + p->inv_elems + p->ps_elems) * 8 : (int64_t)p->device_bytes;
+  out->workspace_bytes = p->host_only ? p->ws_need : (int64_t)p->device_bytes;
   out->slice_batch = p->S;
   out->precision = p->precision;
   return TN_OK;

@@ -62,7 +62,8 @@ class tn_options(ctypes.Structure):
                 ("mem_cap_elems", ctypes.c_int64), ("stream", ctypes.c_void_p),
                 ("slice_batch", ctypes.c_int32), ("host_only", ctypes.c_int32),
                 ("split_policy", ctypes.c_int32), ("record_steps", ctypes.c_int32),
-                ("tuning", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("tuning", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64)]
 
 
 class tn_plan_info(ctypes.Structure):
@@ -185,7 +186,7 @@ def _stream_handle(stream):
 def tn_plan_create(tensors, labels, open_labels, path, sliced_labels=(), precision="c64",
                    mem_cap_elems: int = 0, stream=None, slice_batch: int = 0,
                    host_only: bool = False, split_policy: int = 0, record_steps: bool = False,
-                   tuning: int = 0):
+                   tuning: int = 0, workspace=None):
     """Create a plan; returns an opaque handle (int).  Leaves are copied."""
     n = len(labels)
     ranks = (ctypes.c_int32 * n)(*[len(l) for l in labels])
@@ -225,6 +226,9 @@ def tn_plan_create(tensors, labels, open_labels, path, sliced_labels=(), precisi
     opts.split_policy = int(split_policy)
     opts.record_steps = 1 if record_steps else 0
     opts.tuning = int(tuning)
+    if workspace is not None:   # a device tensor: its memory, caller-owned
+        opts.workspace = int(workspace.data_ptr())
+        opts.workspace_bytes = int(workspace.numel() * workspace.element_size())
     handle = ctypes.c_void_p()
     status = _lib.tn_plan_create(ctypes.byref(handle), n, ranks, lab_pp, ext_pp, data_pp,
                                  len(open_labels), op, len(path), pa, len(sliced_labels), sl,
@@ -482,6 +486,7 @@ class Plan:
         learned = kw.get("tuning", 0) == 2
         if learned:
             kw["tuning"] = 0
+        self.workspace = kw.get("workspace")   # kept alive for the plan's lifetime
         self.handle = tn_plan_create(tensors, labels, open_labels, path, sliced_labels, **kw)
         if learned:
             from .costmodel import CostModel

@@ -176,3 +176,16 @@ def test_set_tile_on_host_plan():
         _expect("TN_E_ARG", lambda: tn.tn_plan_step_features(h, i, 7))
     finally:
         tn.tn_plan_destroy(h)
+
+
+def test_host_plan_reports_workspace_size():
+    """A host-only plan reports the device bytes a caller-owned workspace must hold: at least
+    the leaves and both arenas, 256-byte aligned pieces."""
+    circ, net, best = configs.build("rqc30")
+    h = _host_plan(net, best["path"], best["sliced"], precision="f16x3")
+    try:
+        info = tn.tn_plan_describe(h)
+    finally:
+        tn.tn_plan_destroy(h)
+    assert info["workspace_bytes"] % 256 == 0
+    assert info["workspace_bytes"] >= 8 * info["max_intermediate"] * info["slice_batch"]

@@ -380,3 +380,34 @@ def test_group_graph_launch_matches_individual_plans(prec):
     finally:
         for p in plans + alone:
             p.close()
+
+
+@pytest.mark.parametrize("prec", ["c64", "f16x3"])
+def test_caller_owned_workspace(prec):
+    """A plan built in a torch-owned workspace gives the same amplitudes, bit for bit, as a
+    plan that allocates its own memory; a workspace that is too small is refused."""
+    print(f"workspace {prec}", flush=True)
+    circ, net, best = configs.build("rqc12")
+    sliced = choose_slices(net.labels, net.open_labels, net.extents(), best["path"], cap_log2=6,
+                           min_sliced=3)
+    args = (net.tensors, net.labels, net.open_labels, best["path"], sliced)
+    with tn.Plan(*args, precision=prec, host_only=True) as h:
+        need = h.describe()["workspace_bytes"]
+    with tn.Plan(*args, precision=prec) as p:
+        p.contract()
+        ref, _ = p.amplitudes()
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    with tn.Plan(*args, precision=prec, workspace=ws) as q:
+        assert q.describe()["workspace_bytes"] <= need
+        q.contract()
+        got, _ = q.amplitudes()
+    assert np.array_equal(got, ref)
+    # autotuning inside the workspace (split-K scratch is reserved for every tile)
+    with tn.Plan(*args, precision=prec, workspace=ws, tuning=1) as q:
+        q.contract()
+        tuned, _ = q.amplitudes()
+    assert metrics.rel_l2(tuned, ref) <= TOL[prec]
+    small = torch.empty(need // 2, dtype=torch.uint8, device="cuda")
+    with pytest.raises(tn.TnError) as e:
+        tn.Plan(*args, precision=prec, workspace=small)
+    assert e.value.name == "TN_E_NOMEM"
