@@ -330,9 +330,9 @@ __device__ __forceinline__ TileCtx tile_ctx(const GettDesc* __restrict__ d, cons
   return c;
 }
 
-// PAIRED: the accumulator's 32 columns of block ni hold, in lanes 0-15, the real parts
-// and, in lanes 16-31, the imaginary parts of 16 complex columns (else real columns
-// 2n, 2n + 1 sit in adjacent lanes).
+// PAIRED: accumulator blocks 0, 1 hold the real parts and blocks 2, 3 the imaginary
+// parts of the wave's complex columns 0-31 and 32-63 (else real columns 2n, 2n + 1 sit
+// in adjacent lanes of one block).
 template <int P, int WM, int WN, bool PAIRED = false>
 __device__ __forceinline__ void store_tile(const GettDesc* __restrict__ d, const GettArgs& g, const TileCtx& cx,
                            floatx16 (&acc)[2][4], uint32_t* smem, uint32_t* red);
@@ -635,7 +635,7 @@ __device__ __forceinline__ void store_tile(const GettDesc* __restrict__ d, const
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const int row = mi * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-            const int col = wn * 128 + ni * 32 + (PAIRED ? 2 * (lane & 15) + ((lane >> 4) & 1) : (lane & 31));
+            const int col = wn * 128 + (PAIRED ? 2 * ((ni & 1) * 32 + (lane & 31)) + (ni >> 1) : ni * 32 + (lane & 31));
             Cs[row * T::LDC + col] = acc[mi][ni][v];
           }
     }
@@ -684,9 +684,10 @@ __device__ __forceinline__ void store_tile(const GettDesc* __restrict__ d, const
 // per row (dma_swz) so that the lanes of one LDS read phase hit distinct banks.  A DMA instruction of a wave fills 1 KiB of
 // LDS (8 rows) in lane order; each lane fetches the pair that belongs in its slot.
 // Fragments: lane (r, half) of A takes k = 4 * half .. 4 * half + 3 of row r as
-// hi and lo words; B's real columns are built from complex column n as (Br, -Bi)
-// (real part of output column n) and (Bi, Br) (imaginary part), the same operands
-// the staged kernel forms in LDS, with the two parts in lanes j and j + 16.
+// hi and lo words; lane (n, half) of B the same k of complex column n, as (Br, -Bi)
+// for the blocks of real parts of the output and as (Bi, Br) for the blocks of
+// imaginary parts (one VALU operation per word either way), the products the staged
+// kernel forms in LDS.
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int DMA_STAGES = 3;
@@ -780,11 +781,8 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
-  // B fragment of block ni: lanes j < 16 form (Br, -Bi) and lanes j >= 16 (Bi, Br) of
-  // complex column ni * 16 + j % 16 (real part and imaginary part of that output
-  // column), so the lanes of one LDS read phase fetch distinct columns
-  const uint32_t b_rot = (lane & 16) ? 16u : 0u;
-  const uint32_t b_flip = (lane & 16) ? 0u : 0x80000000u;
+  // accumulator blocks 0, 1: real parts of complex columns wn * 64 + [0, 32) and
+  // [32, 64); blocks 2, 3: their imaginary parts
   const int half = lane >> 5;
 
   issue();
@@ -804,7 +802,7 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
       const int s0 = ks * 4 + half * 2;      // hi slot of this lane's 4 k (lo slot: s0 + 1)
       // all LDS reads of the K step first (A, then B column by column), so that the
       // products of the first columns can start while later columns are in flight
-      u32x4 xa[2][2], xb[4][2];
+      u32x4 xa[2][2], xb[2][2];
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi) {
         const int r = wm * 64 + mi * 32 + (lane & 31);
@@ -812,11 +810,11 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
         xa[mi][1] = *reinterpret_cast<const u32x4*>(st + r * 128 + (((s0 + 1) ^ dma_swz(r)) << 4));
       }
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) {
-        const int n = wn * 64 + ni * 16 + (lane & 15);
+      for (int nb = 0; nb < 2; ++nb) {
+        const int n = wn * 64 + nb * 32 + (lane & 31);
         const char* bp = st + DMA_A_BYTES + n * 128;
-        xb[ni][0] = *reinterpret_cast<const u32x4*>(bp + ((s0 ^ dma_swz(n)) << 4));
-        xb[ni][1] = *reinterpret_cast<const u32x4*>(bp + (((s0 + 1) ^ dma_swz(n)) << 4));
+        xb[nb][0] = *reinterpret_cast<const u32x4*>(bp + ((s0 ^ dma_swz(n)) << 4));
+        xb[nb][1] = *reinterpret_cast<const u32x4*>(bp + (((s0 + 1) ^ dma_swz(n)) << 4));
       }
       u32x4 ah[2], al[2], bh[4], bl[4];
 #pragma unroll
@@ -824,21 +822,24 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
         ah[mi] = xa[mi][0];
         al[mi] = xa[mi][1];
       }
-      auto expand = [&](const u32x4& x) {
-        return u32x4{__builtin_amdgcn_alignbit(x.x, x.x, b_rot) ^ b_flip, __builtin_amdgcn_alignbit(x.y, x.y, b_rot) ^ b_flip,
-                     __builtin_amdgcn_alignbit(x.z, x.z, b_rot) ^ b_flip, __builtin_amdgcn_alignbit(x.w, x.w, b_rot) ^ b_flip};
+      // block ni < 2: (Br, -Bi) of column block ni; ni >= 2: (Bi, Br) of block ni - 2
+      auto expand = [&](const u32x4 (&x)[2][2], int ni, int hl) {
+        const u32x4& v = x[ni & 1][hl];
+        if (ni < 2) return u32x4{v.x ^ 0x80000000u, v.y ^ 0x80000000u, v.z ^ 0x80000000u, v.w ^ 0x80000000u};
+        return u32x4{__builtin_amdgcn_alignbit(v.x, v.x, 16), __builtin_amdgcn_alignbit(v.y, v.y, 16),
+                     __builtin_amdgcn_alignbit(v.z, v.z, 16), __builtin_amdgcn_alignbit(v.w, v.w, 16)};
       };
       // hi x hi, column-major over the wave tile (dependent products on one
       // accumulator stay 8 MFMAs apart)
 #pragma unroll
       for (int ni = 0; ni < 4; ++ni) {
-        bh[ni] = expand(xb[ni][0]);
+        bh[ni] = expand(xb, ni, 0);
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(ah[mi], bh[ni], acc[mi][ni]);
       }
 #pragma unroll
       for (int ni = 0; ni < 4; ++ni) {
-        bl[ni] = expand(xb[ni][1]);
+        bl[ni] = expand(xb, ni, 1);
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(ah[mi], bl[ni], acc[mi][ni]);
       }
