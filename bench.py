@@ -106,15 +106,20 @@ def run_precision(tn, torch, net, best, prec, steps, warmup, sample_slice, tunin
             "by_kind": by_kind, "amps": amps, "partial": part}
 
 
-def run_batching(tn, torch, configs, net, best, prec, n_small, n_slices, steps):
-    """Batching form: a slice range of the workload plus n_small uneven 16-28-qubit circuits,
-    contracted plan by plan (tn_contract_slices each) and as one graph replay (tn_group_*)."""
-    items = [(net, best, n_slices)] + [(n, b, 1) for n, b in
-                                        configs.uneven_circuits(n_small, seed=1040, cap_log2=22)]
+def run_batching(tn, torch, configs, workload, prec, n_small, n_slices, steps):
+    """Batching form: a slice range of a large network plus n_small uneven 16-28-qubit
+    circuits, contracted plan by plan (tn_contract_slices each) and as one graph replay
+    (tn_group_*)."""
+    _, net, best = configs.build(workload)
+    first = sample_slices(1 << len(best["sliced"]), 1, 404)[0] & ~(n_slices - 1)
+    items = [(net, best, first, n_slices)] + [(n, b, 0, 1) for n, b in
+                                               configs.uneven_circuits(n_small, seed=1040, cap_log2=22)]
     stream = torch.cuda.current_stream()
     plans = [tn.Plan(n.tensors, n.labels, n.open_labels, b["path"], b.get("sliced", ()),
-                     precision=prec, stream=stream) for n, b, _ in items]
-    counts = [c for _, _, c in items]
+                     precision=prec, stream=stream, slice_batch=4 if i == 0 else 0)
+             for i, (n, b, _, _) in enumerate(items)]
+    firsts = [f for _, _, f, _ in items]
+    counts = [c for _, _, _, c in items]
     flops = sum(p.describe()["flops_invariant"] + c * p.describe()["flops_per_slice"]
                 for p, c in zip(plans, counts))
     start = torch.cuda.Event(enable_timing=True)
@@ -131,23 +136,24 @@ def run_batching(tn, torch, configs, net, best, prec, n_small, n_slices, steps):
         return start.elapsed_time(end) / steps
 
     def sequential():
-        for p, c in zip(plans, counts):
-            p.contract(0, c)
+        for p, f, c in zip(plans, firsts, counts):
+            p.contract(f, c)
 
     seq_ms = timed(sequential)
     seq_amps = [p.amplitudes()[0] for p in plans]
     for p in plans:
         p.reset()
     with tn.Group(plans, stream=stream) as g:
-        grp_ms = timed(lambda: g.contract([0] * len(plans), counts))
+        grp_ms = timed(lambda: g.contract(firsts, counts))
         info = g.describe()
         grp_amps = [p.amplitudes()[0] for p in plans]
     same = all(np.array_equal(a, b) for a, b in zip(seq_amps, grp_amps))
     for p in plans:
         p.close()
-    return {"plans": len(plans), "workload_slices": n_slices, "small_circuits": n_small,
-            "flops": flops, "sequential_ms": round(seq_ms, 3), "graph_ms": round(grp_ms, 3),
-            "speedup": round(seq_ms / grp_ms, 3), "graph_tflops": round(flops / (grp_ms * 1e-3) / 1e12, 3),
+    return {"workload": workload, "plans": len(plans), "workload_slices": [first, first + n_slices],
+            "small_circuits": n_small, "flops": flops, "sequential_ms": round(seq_ms, 3),
+            "graph_ms": round(grp_ms, 3), "speedup": round(seq_ms / grp_ms, 3),
+            "graph_tflops": round(flops / (grp_ms * 1e-3) / 1e12, 3),
             "graph_kernels": info["n_kernels"], "graph_branches": info["n_branches"],
             "amplitudes_identical": bool(same), "precision": prec}
 
@@ -206,58 +212,73 @@ def sample_slices(n_slices: int, count: int, seed: int = 137):
     return sorted(int(x) for x in rng.choice(n_slices, size=min(count, n_slices), replace=False))
 
 
-def run_slicing_choice(tn, torch, net, prec, cap_log2, n_sliced, n_candidates, n_slices):
+def run_slicing_choice(tn, torch, configs, workload, prec, n_candidates, n_timed):
     """Contraction trees with their slicings (randomised greedy paths, each sliced to the
-    cap) ranked two ways: by flops (T_cc) and by the learned model's predicted time; the
-    pick of each is then timed on the GPU over the same number of slices."""
+    workload's cap) ranked three ways for the whole job (all slices): by flops (T_cc), by
+    the analytic flop/byte roofline model and by the learned model's predicted time (tiles
+    chosen by the model).  Each pick is then timed on the GPU over n_timed slices with the
+    model's tiles and its time extrapolated to all slices (slices cost the same)."""
     from paper_2310_03978_amd import costmodel
     from tn_inputs.paths import choose_slices, greedy_path
+    _, net, _ = configs.build(workload)
+    w = configs.WORKLOADS[workload]
     ext = net.extents()
     cands = []
     for t in range(n_candidates):
         path = greedy_path(net.labels, net.open_labels, ext, seed=7000 + t,
                            temperature=0.0 if t == 0 else 0.3)
-        sliced = choose_slices(net.labels, net.open_labels, ext, path, cap_log2,
-                               min_sliced=n_sliced, max_sliced=n_sliced)
-        if len(sliced) != n_sliced:
-            continue
+        sliced = choose_slices(net.labels, net.open_labels, ext, path, w.cap_log2)
         cands.append((path, sliced))
     with costmodel.CostModel.load() as model:
         scored = []
         for path, sliced in cands:
             with tn.Plan(net.tensors, net.labels, net.open_labels, path, sliced, precision=prec,
-                         host_only=True) as h:
+                         host_only=True, slice_batch=1) as h:
                 info = h.describe()
-                flops = info["flops_invariant"] + n_slices * info["flops_per_slice"]
-                scored.append((flops, costmodel.predict_plan_us(h, model, n_slices), path, sliced))
-    by_flops = min(range(len(scored)), key=lambda i: scored[i][0])
-    by_model = min(range(len(scored)), key=lambda i: scored[i][1])
+                if info["max_intermediate"] > (1 << w.cap_log2):
+                    continue
+                flops = info["flops_invariant"] + info["n_slices"] * info["flops_per_slice"]
+                scored.append({"flops": flops, "analytic_us": costmodel.analytic_plan_us(h),
+                               "model_us": costmodel.predict_plan_us(h, model),
+                               "n_slices": info["n_slices"], "path": path, "sliced": sliced})
+    picks = {"flops": min(range(len(scored)), key=lambda i: scored[i]["flops"]),
+             "analytic": min(range(len(scored)), key=lambda i: scored[i]["analytic_us"]),
+             "learned_model": min(range(len(scored)), key=lambda i: scored[i]["model_us"])}
     stream = torch.cuda.current_stream()
+    measured = {}
 
     def measure(i):
-        _, _, path, sliced = scored[i]
-        with tn.Plan(net.tensors, net.labels, net.open_labels, path, sliced, precision=prec,
-                     stream=stream, tuning=2) as p:
-            p.contract(0, min(8, n_slices))
+        c = scored[i]
+        with tn.Plan(net.tensors, net.labels, net.open_labels, c["path"], c["sliced"], precision=prec,
+                     stream=stream, tuning=2, slice_batch=1) as p:
+            ids = sample_slices(c["n_slices"], n_timed + 1, 505)
+            p.contract(ids[0], 1)
             torch.cuda.synchronize()
             s = torch.cuda.Event(enable_timing=True)
             e = torch.cuda.Event(enable_timing=True)
             s.record(stream)
-            p.contract(0, n_slices)
+            for sid in ids[1:]:
+                p.contract(sid, 1)
             e.record(stream)
             torch.cuda.synchronize()
             p.amplitudes()
-            return s.elapsed_time(e)
+            return s.elapsed_time(e) / n_timed
 
-    ms_flops = measure(by_flops)
-    ms_model = ms_flops if by_model == by_flops else measure(by_model)
-    return {"candidates": len(scored), "cap_log2": cap_log2, "sliced_labels": n_sliced,
-            "slices_timed": n_slices, "precision": prec,
-            "pick_by_flops": {"candidate": by_flops, "flops": scored[by_flops][0],
-                              "predicted_ms": round(scored[by_flops][1] / 1e3, 3), "measured_ms": round(ms_flops, 3)},
-            "pick_by_model": {"candidate": by_model, "flops": scored[by_model][0],
-                              "predicted_ms": round(scored[by_model][1] / 1e3, 3), "measured_ms": round(ms_model, 3)},
-            "model_vs_flops_speedup": round(ms_flops / ms_model, 3)}
+    out = {"workload": f"{workload}: {w.description}", "candidates": len(scored), "cap_log2": w.cap_log2,
+           "slices_timed_per_pick": n_timed, "precision": prec}
+    for name, i in picks.items():
+        if i not in measured:
+            measured[i] = measure(i)
+        c = scored[i]
+        out[f"pick_by_{name}"] = {
+            "candidate": i, "sliced_labels": len(c["sliced"]), "flops": c["flops"],
+            "analytic_s": round(c["analytic_us"] / 1e6, 2), "predicted_s": round(c["model_us"] / 1e6, 2),
+            "measured_ms_per_slice": round(measured[i], 3),
+            "measured_job_s": round(measured[i] * c["n_slices"] / 1e3, 1)}
+    job = {k: out[f"pick_by_{k}"]["measured_job_s"] for k in picks}
+    out["learned_vs_flops_speedup"] = round(job["flops"] / job["learned_model"], 3)
+    out["learned_vs_analytic_speedup"] = round(job["analytic"] / job["learned_model"], 3)
+    return out
 
 
 def cpu_baseline(net, best, ids, flops_slice):
@@ -319,10 +340,13 @@ def main():
     ap.add_argument("--tuning", type=int, default=1, help="1 = autotune tile shapes at plan creation")
     ap.add_argument("--no-tuning-modes", dest="tuning_modes", action="store_false",
                     help="skip the heuristic / learned-model / autotune comparison")
-    ap.add_argument("--slicing-candidates", type=int, default=12,
-                    help="candidate trees for the flops-vs-learned-model slicing choice (0 = skip)")
-    ap.add_argument("--batching", type=int, default=64,
+    ap.add_argument("--slicing-candidates", type=int, default=8,
+                    help="candidate trees for the slicing choice: flops vs analytic vs learned model (0 = skip)")
+    ap.add_argument("--slicing-workload", default="rqc53d14")
+    ap.add_argument("--batching", type=int, default=256,
                     help="uneven circuits in the batching-form measurement (0 = skip it)")
+    ap.add_argument("--batching-workload", default="rqc40")
+    ap.add_argument("--batching-slices", type=int, default=32)
     ap.add_argument("--counter-run", action="store_true",
                     help="one chunk per precision and a calibration copy, for rocprofv3 --pmc")
     args = ap.parse_args()
@@ -405,14 +429,16 @@ def main():
         out["tile_choice"] = run_tuning_modes(tn, torch, net, best, head, 32)
         log(f"  {out['tile_choice']}")
     if args.slicing_candidates > 0:
-        w_ = configs.WORKLOADS[args.workload]
-        log(f"slicing choice: {args.slicing_candidates} candidate trees, flops vs learned model")
-        out["slicing_choice"] = run_slicing_choice(tn, torch, net, head, w_.cap_log2, w_.n_sliced,
-                                                   args.slicing_candidates, 64)
+        log(f"slicing choice on {args.slicing_workload}: {args.slicing_candidates} candidate trees, "
+            f"flops vs analytic model vs learned model")
+        out["slicing_choice"] = run_slicing_choice(tn, torch, configs, args.slicing_workload, head,
+                                                   args.slicing_candidates, 2)
         log(f"  {out['slicing_choice']}")
     if args.batching > 0:
-        log(f"batching form: {args.batching} uneven circuits + slices [0, 32) of {args.workload}")
-        out["batching"] = run_batching(tn, torch, configs, net, best, head, args.batching, 32, 3)
+        log(f"batching form: {args.batching} uneven circuits + {args.batching_slices} slices of "
+            f"{args.batching_workload}")
+        out["batching"] = run_batching(tn, torch, configs, args.batching_workload, head, args.batching,
+                                       args.batching_slices, 2)
         log(f"  {out['batching']}")
     if not args.no_cpu_baseline:
         from oracle import metrics

@@ -139,6 +139,29 @@ def predict_plan_us(plan, model: CostModel, n_slices: int | None = None) -> floa
     return total
 
 
+# MI355X roofline of the analytic model: dense MFMA peaks (FP32 for the complex64 GEMM,
+# FP16 / BF16 for the split form, whose three products each run the step's flops), FP32
+# vector for the small kernel, HBM3E bandwidth.
+PEAK_FP32 = 157.3e12
+PEAK_SPLIT = 2.5e15 / 3
+HBM_BW = 8.0e12
+
+
+def analytic_step_us(step: dict) -> float:
+    """Roofline time of one step for one slice (or once, if slice-independent):
+    max(flops / peak, bytes / bandwidth), with the peak of the step's kernel."""
+    rate = PEAK_SPLIT if step["kernel"] in (2, 3) else PEAK_FP32
+    return max(step["flops"] / rate, step["bytes"] / HBM_BW) * 1e6
+
+
+def analytic_plan_us(plan, n_slices: int | None = None) -> float:
+    """Analytic flop/byte estimate of contracting n_slices slices (default: all): the
+    fallback the learned model is compared with.  Works on host-only plans."""
+    info = plan.describe()
+    n = info["n_slices"] if n_slices is None else n_slices
+    return sum(analytic_step_us(st) * (n if st["per_slice"] else 1) for st in plan.steps())
+
+
 # ---------------------------------------------------------------------------
 # Harvesting
 # ---------------------------------------------------------------------------

@@ -258,6 +258,31 @@ def test_rqc30_sampled_slices_match_oracle(prec):
     assert metrics.rel_l2(acc, parts.sum(axis=0)) <= 1e-6
 
 
+@pytest.mark.parametrize("prec", ["c64", "f16x3", "bf16x3"])
+def test_rqc30d12_precision_subcase_matches_oracle(prec):
+    """The precision form's 30-qubit sub-case (5x6 lattice, 12 cycles, 512 correlated
+    amplitudes, largest intermediate 2^26): every amplitude against the oracle's, stored
+    by tests/golden/make_rqc30d12_amplitudes.py."""
+    import importlib.util
+    import os
+    print(f"rqc30d12 {prec}", flush=True)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_rqc30d12_amplitudes.py")
+    spec = importlib.util.spec_from_file_location("make_rqc30d12_amplitudes", path)
+    fx = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(fx)
+    digest, ref = fx.read_fixture()
+    _, net, best = configs.build("rqc30d12")
+    assert digest == fx.network_digest(net, best)
+    with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], precision=prec) as p:
+        p.contract()
+        got, c = p.amplitudes()
+    assert c == 1
+    rep = metrics.report(got, ref)
+    print(f"rqc30d12 {prec}: {rep}", flush=True)
+    assert rep["rel_l2"] <= TOL[prec]
+    assert rep["fidelity"] >= 1 - 2 * TOL[prec]
+
+
 _ORACLE_CACHE = {}
 
 
@@ -411,3 +436,80 @@ def test_caller_owned_workspace(prec):
     with pytest.raises(tn.TnError) as e:
         tn.Plan(*args, precision=prec, workspace=small)
     assert e.value.name == "TN_E_NOMEM"
+
+
+def _sample_slices(n_slices, k, seed):
+    rng = np.random.default_rng(seed)
+    return sorted(int(x) for x in rng.choice(n_slices, size=min(k, n_slices), replace=False))
+
+
+def test_rqc53d12_full_size_properties():
+    """The precision form at its full size (53 qubits, 12 cycles, 512 correlated amplitudes,
+    largest intermediate 2^30 elements, 2^16 slices), where no oracle slice finishes in
+    seconds: properties that hold at any size, on slices of the seeded sample (seed 303).
+    (1) The split-FP16 and split-BF16 partial amplitudes of a slice agree with the
+    complex64 ones within the precision form's bound.  (2) Slicing invariance (Sec. 3.2):
+    the two slices that differ only in the last sliced bond sum to the slice of the plan
+    that leaves that bond unsliced (largest intermediate 2^31)."""
+    print("rqc53d12 full size", flush=True)
+    _, net, best = configs.build("rqc53d12")
+    sliced = list(best["sliced"])
+    n = 1 << len(sliced)
+    s = _sample_slices(n, 4096, 303)[0] & ~1
+    args = (net.tensors, net.labels, net.open_labels, best["path"])
+    with tn.Plan(*args, sliced, precision="c64", slice_batch=1) as q:
+        pc = q.partials([s, s | 1])
+    for prec in ("f16x3", "bf16x3"):
+        with tn.Plan(*args, sliced, precision=prec, slice_batch=1) as p:
+            pf = p.partials([s, s | 1])
+        for j in range(2):
+            err = metrics.rel_l2(pf[j], pc[j])
+            print(f"rqc53d12 slice {s | j} {prec} vs c64: rel_l2 {err:.2e}", flush=True)
+            assert err <= TOL[prec]
+    with tn.Plan(*args, sliced[:-1], precision="c64", slice_batch=1) as r:
+        pr = r.partials([s >> 1])[0]
+    err = metrics.rel_l2(pc.sum(axis=0), pr)
+    print(f"rqc53d12 slicing invariance: rel_l2 {err:.2e}", flush=True)
+    assert err <= 2 * TOL["c64"]
+
+
+def test_rqc40_batching_form_full_size():
+    """The batching form's shape: slices of the 40-qubit, 16-cycle network (largest
+    intermediate 2^28) and 64 uneven 16-28-qubit circuits in one captured graph.  Every
+    plan's amplitudes equal, bit for bit, the same plan's run on its own; the four
+    cheapest uneven circuits also match the oracle, and the graph's 40-qubit sum agrees
+    with the complex64 path's."""
+    print("rqc40 batching form", flush=True)
+    _, net, best = configs.build("rqc40")
+    args = (net.tensors, net.labels, net.open_labels, best["path"], best["sliced"])
+    small = configs.uneven_circuits(64)
+    first = _sample_slices(1 << len(best["sliced"]), 1, 404)[0] & ~7
+
+    def make():
+        return ([tn.Plan(*args, precision="f16x3", slice_batch=4)] +
+                [tn.Plan(n_.tensors, n_.labels, n_.open_labels, b["path"], precision="f16x3") for n_, b in small])
+
+    alone, plans = make(), make()
+    try:
+        alone[0].contract(first, 8)
+        for p in alone[1:]:
+            p.contract()
+        singles = [p.amplitudes()[0] for p in alone]
+        with tn.Group(plans, branches=8) as g:
+            g.contract([first] + [0] * len(small), [8] + [1] * len(small))
+            for p, one in zip(plans, singles):
+                assert np.array_equal(p.amplitudes()[0], one)
+        cheap = sorted(range(len(small)), key=lambda i: small[i][1]["cost"]["flops_total"])[:4]
+        for i in cheap:
+            n_, b = small[i]
+            ref = contract.amplitudes(n_.tensors, n_.labels, n_.open_labels, b["path"])
+            assert metrics.rel_l2(singles[1 + i], ref) <= TOL["f16x3"]
+        with tn.Plan(*args, precision="c64", slice_batch=4) as q:
+            q.contract(first, 8)
+            ref40, _ = q.amplitudes()
+        err = metrics.rel_l2(singles[0], ref40)
+        print(f"rqc40 slices [{first}, {first + 8}) f16x3 vs c64: rel_l2 {err:.2e}", flush=True)
+        assert err <= TOL["f16x3"]
+    finally:
+        for p in plans + alone:
+            p.close()

@@ -40,6 +40,17 @@ WORKLOADS = {
                                   "8 sliced bonds (256 slices), cap 2^28"),
     "rqc30d12": Workload("rqc30d12", 5, 6, 12, 9, 130, 230, 28, 0,
                          description="30-qubit 5x6 lattice, 12 cycles, 9 open qubits, cap 2^28"),
+    # the precision form at full size: 53 qubits, largest intermediate 2^30
+    "rqc53d12": Workload("rqc53d12", 6, 9, 12, 9, 103, 203, 30, 0, removed=((5, 8),), trials=4,
+                         description="53-qubit 6x9 lattice minus one site, 12 cycles, 9 open qubits, "
+                                     "sliced to cap 2^30"),
+    # the batching form's large network
+    "rqc40": Workload("rqc40", 5, 8, 16, 6, 104, 204, 28, 0, trials=4,
+                      description="40-qubit 5x8 lattice, 16 cycles, 6 open qubits, sliced to cap 2^28"),
+    # the slicing-choice workload of the learned cost model
+    "rqc53d14": Workload("rqc53d14", 6, 9, 14, 6, 105, 205, 30, 0, removed=((5, 8),), trials=4,
+                         description="53-qubit 6x9 lattice minus one site, 14 cycles, 6 open qubits, "
+                                     "sliced to cap 2^30"),
 }
 
 
