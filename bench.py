@@ -208,6 +208,37 @@ def measured_traffic(kernel: str):
     return None
 
 
+def run_mixed_precision(tn, torch, net, best, prec, sample_ids, n_slices):
+    """Per-step precision (Sec. 4.3, Table 3): single products on the k split steps with the
+    most flops, three products elsewhere.  For each k: time of n_slices slices and the
+    partial amplitudes of the sampled slices (compared with the oracle afterwards)."""
+    stream = torch.cuda.current_stream()
+    out = []
+    with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best["sliced"],
+                 precision=prec, stream=stream, tuning=2) as p:
+        n_split = sum(1 for s in p.steps() if s["kernel"] in (2, 3))
+        ks = sorted({0, 1, 2, 4, 8, 16, n_split} & set(range(n_split + 1)))
+        st = p.steps()
+        total = sum(s["flops"] * (p.describe()["n_slices"] if s["per_slice"] else 1)
+                    for s in st if s["kernel"] in (2, 3))
+        for k in ks:
+            top = p.single_product_top(k)
+            share = sum(st[i]["flops"] * (p.describe()["n_slices"] if st[i]["per_slice"] else 1)
+                        for i in top) / max(total, 1.0)
+            p.contract(0, min(8, n_slices))
+            torch.cuda.synchronize()
+            s0 = torch.cuda.Event(enable_timing=True)
+            e0 = torch.cuda.Event(enable_timing=True)
+            s0.record(stream)
+            p.contract(0, n_slices)
+            e0.record(stream)
+            torch.cuda.synchronize()
+            p.reset()
+            out.append({"k": k, "split_flops_share": round(share, 4), "ms": round(s0.elapsed_time(e0), 3),
+                        "partial": p.partials(sample_ids)})
+    return out
+
+
 def sample_slices(n_slices: int, count: int, seed: int = 137):
     """Seeded sample of distinct slice ids (sorted)."""
     rng = np.random.default_rng(seed)
@@ -351,6 +382,8 @@ def main():
                     help="uneven circuits in the batching-form measurement (0 = skip it)")
     ap.add_argument("--batching-workload", default="rqc40")
     ap.add_argument("--batching-slices", type=int, default=32)
+    ap.add_argument("--no-mixed-precision", dest="mixed_precision", action="store_false",
+                    help="skip the per-step precision (single products on the costliest steps) sweep")
     ap.add_argument("--counter-run", action="store_true",
                     help="one pass per precision and a calibration copy, for rocprofv3 --pmc")
     args = ap.parse_args()
@@ -438,6 +471,10 @@ def main():
         out["slicing_choice"] = run_slicing_choice(tn, torch, configs, args.slicing_workload, head,
                                                    args.slicing_candidates, 2)
         log(f"  {out['slicing_choice']}")
+    mixed = None
+    if args.mixed_precision and head != "c64":
+        log(f"per-step precision: single products on the top-k split steps, {head}")
+        mixed = run_mixed_precision(tn, torch, net, best, head, sample_ids, 32)
     if args.batching > 0:
         log(f"batching form: {args.batching} uneven circuits + {args.batching_slices} slices of "
             f"{args.batching_workload}")
@@ -449,6 +486,13 @@ def main():
         ref, cb = cpu_baseline(net, best, sample_ids,
                                info["flops_per_slice"] + info["flops_invariant"])
         out["cpu_baseline"] = cb
+        if mixed:
+            # Table 3's trend: time and error against the oracle as single products spread
+            out["mixed_precision"] = {"precision": head, "slices_timed": 32, "sampled_slices": len(ref), "top_k": [
+                {"k": r["k"], "split_flops_share": r["split_flops_share"], "ms": r["ms"],
+                 "eps_l2sq": metrics.eps_l2sq(r["partial"], ref), "rel_l2": metrics.rel_l2(r["partial"], ref)}
+                for r in mixed]}
+            log(f"  {out['mixed_precision']}")
         for prec, r in runs.items():
             # a11: errors of the sampled slices' amplitudes against the complex128 oracle
             per = [metrics.rel_l2(a, b) for a, b in zip(r["partial"], ref)]

@@ -119,6 +119,8 @@ typedef struct {
   int32_t tile;                /* tile id (0..3, see TN_N_TILE_SHAPES) of an MFMA step; -1 for the small kernel */
   int32_t lds_copy;            /* 1 = split operands copied global -> LDS without registers (three-stage
                                   pipeline; both operands stored split, k pairs contiguous, 256 x 128 tiles) */
+  int32_t terms;               /* split steps: 3 = hi*hi + hi*lo + lo*hi (default), 1 = hi*hi only
+                                  (tn_plan_set_step_terms); 0 for the other kernels */
 } tn_step_info;
 
 /* Build a plan.
@@ -162,6 +164,14 @@ tn_status tn_plan_steps(tn_plan plan, tn_step_info* steps, int32_t cap);
  * is timed from its main launch to the end of its reduction launch.  TN_E_STATE if
  * recording is off. */
 tn_status tn_plan_step_times(tn_plan plan, double* ms_total, int64_t* launches, int32_t cap);
+
+/* Per-step precision (Sec. 4.3, Table 3: the extended-precision product replaced by a
+ * single low-precision one on the steps that cost most).  terms = 3 runs split step
+ * `step` as hi*hi + hi*lo + lo*hi (the default), terms = 1 as hi*hi only: a third of the
+ * MFMA work, with the operands' rounding to 16-bit (relative 2^-11 for fp16, 2^-8 for
+ * bf16) no longer compensated.  Takes effect from the next contraction.  TN_E_ARG for a
+ * step that does not run a split kernel or terms other than 1 and 3. */
+tn_status tn_plan_set_step_terms(tn_plan plan, int32_t step, int32_t terms);
 
 /* Contract slices [first_slice, first_slice + n_slices) and ADD their amplitudes into the
  * plan's FP64 accumulator, summing in increasing slice id (Sec. 3.2, Sec. 5: sub-task

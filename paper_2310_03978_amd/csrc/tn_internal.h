@@ -76,6 +76,7 @@ struct GettArgs {
   int32_t fa, fb, fc;           // storage format of A, B, C: TN_FMT_C64 or TN_FMT_SPLIT
   int32_t split_bf16;           // split storage uses bf16 halves (else fp16)
   int32_t dma;                  // split kernels: operands copied global -> LDS directly (k_gett_dma)
+  int32_t terms;                // split kernels: 3 = hi.hi + hi.lo + lo.hi, 1 = hi.hi only
 };
 
 // Storage formats of an intermediate.  TN_FMT_SPLIT keeps, per complex element,

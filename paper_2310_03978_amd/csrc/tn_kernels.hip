@@ -527,6 +527,7 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
       for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma16<P>(ah[mi], bh[ni], acc[mi][ni]);
+    if (g.terms == 1) return;   // hi x hi only
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -837,6 +838,7 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(ah[mi], bh[ni], acc[mi][ni]);
       }
+      if (g.terms == 1) continue;   // hi x hi only
 #pragma unroll
       for (int ni = 0; ni < 4; ++ni) {
         bl[ni] = expand(xb, ni, 1);

@@ -94,6 +94,7 @@ struct Step {
   int tiles_m_bits = 0, tiles_n_bits = 0;
   int a_contig = 0, b_contig = 0;
   bool dma = false;                  // split tile 256x128 fed by global -> LDS copies
+  int terms = 3;                     // split steps: products per complex multiply-add term (3 or 1)
   double flops = 0, bytes = 0;
   int64_t scratch_elems = 0;         // split-K partials (elements)
   GettDesc desc;
@@ -149,6 +150,7 @@ struct Arena {
 struct tn_plan_s {
   tn_options opts{};
   bool host_only = false;
+  int64_t epoch = 0;         // bumped whenever a step is re-tiled (graphs captured before are stale)
   hipStream_t stream = nullptr;
   int precision = TN_PREC_C64;
 
@@ -1045,6 +1047,7 @@ void step_launches(const tn_plan_s* p, const Step& st, const GettDesc* d, int s,
   g.fc = C.fmt;
   g.split_bf16 = p->precision == TN_PREC_BF16X3 ? 1 : 0;
   g.dma = st.dma ? 1 : 0;
+  g.terms = st.terms;
   L.desc = d;
   L.step = s;
   L.kind = st.kernel;
@@ -1207,6 +1210,7 @@ tn_status ensure_scratch(tn_plan_s* p, int64_t elems) {
 
 tn_status apply_tile(tn_plan_s* p, int s, int tile) {
   Step& st = p->steps[s];
+  ++p->epoch;
   set_tile(p, st, tile);
   build_desc(p, st);
   tn_status r = ensure_scratch(p, st.scratch_elems);
@@ -1322,6 +1326,7 @@ void step_features(const tn_plan_s* p, const Step& st0, int tile, float* f) {
 tn_status retile_step(tn_plan_s* p, int s, int tile) {
   if (!p->host_only) return apply_tile(p, s, tile);
   Step& st = p->steps[s];
+  ++p->epoch;
   set_tile(p, st, tile);
   build_desc(p, st);
   return TN_OK;
@@ -1428,6 +1433,7 @@ tn_status tn_plan_steps(tn_plan p, tn_step_info* steps, int32_t cap) {
     o.a_contig = st.a_contig;
     o.b_contig = st.b_contig;
     o.flops = st.flops;
+    o.terms = (st.kernel == TN_K_MFMA_F16X3 || st.kernel == TN_K_MFMA_BF16X3) ? st.terms : 0;
     o.bytes = st.bytes;
     o.tile = st.kernel == TN_K_SMALL ? -1 : st.tile;
     o.lds_copy = st.dma ? 1 : 0;
@@ -1477,6 +1483,18 @@ tn_status tn_plan_set_tile(tn_plan p, int32_t step, int32_t tile) {
   tn_status st = retile_step(p, step, tile);
   if (!st) st = validate_steps(p, p->steps);
   return st;
+}
+
+tn_status tn_plan_set_step_terms(tn_plan p, int32_t step, int32_t terms) {
+  if (!p) return fail(TN_E_ARG, "null plan");
+  if (step < 0 || step >= (int32_t)p->steps.size()) return fail(TN_E_ARG, "step out of range");
+  Step& st = p->steps[step];
+  if (st.kernel != TN_K_MFMA_F16X3 && st.kernel != TN_K_MFMA_BF16X3)
+    return fail(TN_E_ARG, "step does not run a split-precision kernel");
+  if (terms != 1 && terms != 3) return fail(TN_E_ARG, "terms must be 1 or 3");
+  if (st.terms != terms) ++p->epoch;
+  st.terms = terms;
+  return TN_OK;
 }
 
 tn_status tn_plan_tune_with_model(tn_plan p, tn_costmodel model, float* predicted_us, int32_t cap) {
@@ -1647,7 +1665,7 @@ tn_status group_build(tn_group_s* G, const std::vector<int64_t>& key, tn_group_s
   std::vector<std::pair<double, int>> work;
   for (int i = 0; i < P; ++i) {
     tn_plan_s* p = G->plans[i];
-    const int64_t first = key[2 * i], n = key[2 * i + 1];
+    const int64_t first = key[3 * i], n = key[3 * i + 1];
     if (n == 0) continue;
     invariant_launches(p, p->steps, p->d_desc, chains[i]);
     for (auto& c : chunks_of(p, first, n)) chunk_launches(p, p->steps, p->d_desc, c.first, c.second, nullptr, chains[i]);
@@ -1740,17 +1758,38 @@ tn_status tn_group_create(tn_group* out, const tn_plan* plans, int32_t n, const 
 tn_status tn_group_contract(tn_group G, const int64_t* first, const int64_t* count) {
   if (!G || !first || !count) return fail(TN_E_ARG, "bad arguments");
   const int P = (int)G->plans.size();
-  std::vector<int64_t> key(2 * P);
+  // graphs are cached per set of ranges and per plan configuration: a plan re-tiled since
+  // a capture has new descriptors in device memory that its old kernels must not read
+  std::vector<int64_t> key(3 * P);
   for (int i = 0; i < P; ++i) {
     if (first[i] < 0 || count[i] < 0 || first[i] + count[i] > G->plans[i]->n_slices)
       return fail(TN_E_SLICE, "slice range out of bounds for plan " + std::to_string(i));
-    key[2 * i] = first[i];
-    key[2 * i + 1] = count[i];
+    key[3 * i] = first[i];
+    key[3 * i + 1] = count[i];
+    key[3 * i + 2] = G->plans[i]->epoch;
   }
   tn_group_s::Cached* C = nullptr;
   for (auto& c : G->cache)
     if (c.key == key) C = &c;
   if (!C) {
+    // drop graphs of earlier plan configurations (after their last replay has finished)
+    bool synced = false;
+    for (size_t j = 0; j < G->cache.size();) {
+      bool stale = false;
+      for (int i = 0; i < P; ++i) stale = stale || G->cache[j].key[3 * i + 2] != key[3 * i + 2];
+      if (stale) {
+        if (!synced) {
+          tn_status st = check(hipStreamSynchronize(G->stream), "group sync");
+          if (st) return st;
+          synced = true;
+        }
+        if (G->cache[j].exec) hipGraphExecDestroy(G->cache[j].exec);
+        if (G->cache[j].graph) hipGraphDestroy(G->cache[j].graph);
+        G->cache.erase(G->cache.begin() + j);
+      } else {
+        ++j;
+      }
+    }
     G->cache.emplace_back();
     C = &G->cache.back();
     tn_status st = group_build(G, key, *C);

@@ -39,7 +39,7 @@ STATUS = {0: "TN_OK", -1: "TN_E_ARG", -2: "TN_E_LABEL", -3: "TN_E_PATH", -4: "TN
 EXPORTED = ["tn_plan_create", "tn_plan_destroy", "tn_plan_describe", "tn_plan_steps",
             "tn_plan_step_times", "tn_contract_slices", "tn_slice_partials", "tn_amplitudes", "tn_accumulator_set",
             "tn_reset", "tn_group_create", "tn_group_contract", "tn_group_describe",
-            "tn_group_destroy", "tn_plan_step_features", "tn_plan_set_tile",
+            "tn_group_destroy", "tn_plan_step_features", "tn_plan_set_tile", "tn_plan_set_step_terms",
             "tn_plan_tune_with_model", "tn_costmodel_create", "tn_costmodel_destroy",
             "tn_costmodel_describe", "tn_costmodel_set_normalization", "tn_costmodel_get_params",
             "tn_costmodel_set_params", "tn_costmodel_predict", "tn_costmodel_gradient",
@@ -82,7 +82,8 @@ class tn_step_info(ctypes.Structure):
                 ("k", ctypes.c_int64), ("split_k", ctypes.c_int32), ("tile_m", ctypes.c_int32),
                 ("tile_n", ctypes.c_int32), ("a_contig", ctypes.c_int32),
                 ("b_contig", ctypes.c_int32), ("flops", ctypes.c_double),
-                ("bytes", ctypes.c_double), ("tile", ctypes.c_int32), ("lds_copy", ctypes.c_int32)]
+                ("bytes", ctypes.c_double), ("tile", ctypes.c_int32), ("lds_copy", ctypes.c_int32),
+                ("terms", ctypes.c_int32)]
 
 
 _P = ctypes.POINTER
@@ -129,6 +130,8 @@ _lib.tn_plan_step_features.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c
 _lib.tn_plan_step_features.restype = ctypes.c_int
 _lib.tn_plan_set_tile.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
 _lib.tn_plan_set_tile.restype = ctypes.c_int
+_lib.tn_plan_set_step_terms.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
+_lib.tn_plan_set_step_terms.restype = ctypes.c_int
 _lib.tn_plan_tune_with_model.argtypes = [ctypes.c_void_p, ctypes.c_void_p, _F32P, ctypes.c_int32]
 _lib.tn_plan_tune_with_model.restype = ctypes.c_int
 _lib.tn_costmodel_create.argtypes = [_P(ctypes.c_void_p), ctypes.c_int32, ctypes.c_uint64]
@@ -380,6 +383,10 @@ def tn_plan_set_tile(plan, step: int, tile: int):
     _check(_lib.tn_plan_set_tile(plan, int(step), int(tile)))
 
 
+def tn_plan_set_step_terms(plan, step: int, terms: int):
+    _check(_lib.tn_plan_set_step_terms(plan, int(step), int(terms)))
+
+
 def tn_plan_tune_with_model(plan, model) -> np.ndarray:
     n = tn_plan_describe(plan)["n_steps"]
     out = np.zeros(max(n, 1), dtype=np.float32)
@@ -538,6 +545,20 @@ class Plan:
 
     def set_tile(self, step, tile):
         tn_plan_set_tile(self.handle, step, tile)
+
+    def set_step_terms(self, step, terms):
+        tn_plan_set_step_terms(self.handle, step, terms)
+
+    def single_product_top(self, k):
+        """Run the k split steps with the most flops per contraction (per-slice steps count
+        once per slice) as hi*hi only, the others as three products; returns their indices."""
+        st = self.steps()
+        n = self.describe()["n_slices"]
+        split = [i for i, s in enumerate(st) if s["kernel"] in (2, 3)]
+        top = sorted(split, key=lambda i: -st[i]["flops"] * (n if st[i]["per_slice"] else 1))[:k]
+        for i in split:
+            tn_plan_set_step_terms(self.handle, i, 1 if i in top else 3)
+        return top
 
     def tune_with_model(self, model):
         """Tile every MFMA step by the model's predicted time; returns predicted us per step."""

@@ -189,3 +189,33 @@ def test_host_plan_reports_workspace_size():
         tn.tn_plan_destroy(h)
     assert info["workspace_bytes"] % 256 == 0
     assert info["workspace_bytes"] >= 8 * info["max_intermediate"] * info["slice_batch"]
+
+
+def test_step_terms_setting_and_errors():
+    """Per-step product count: split steps default to 3 and accept 1 or 3; other steps and
+    other counts are refused; single_product_top marks the costliest split steps."""
+    _, net, best = configs.build("rqc30d12")
+    with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], precision="f16x3",
+                 split_policy=1, host_only=True) as p:
+        st = p.steps()
+        split = [i for i, s in enumerate(st) if s["kernel"] in (2, 3)]
+        other = [i for i, s in enumerate(st) if s["kernel"] not in (2, 3)]
+        assert split and other
+        assert all(st[i]["terms"] == 3 for i in split) and all(st[i]["terms"] == 0 for i in other)
+        p.set_step_terms(split[0], 1)
+        assert p.steps()[split[0]]["terms"] == 1
+        with pytest.raises(tn.TnError):
+            p.set_step_terms(split[0], 2)
+        with pytest.raises(tn.TnError):
+            p.set_step_terms(other[0], 1)
+        with pytest.raises(tn.TnError):
+            p.set_step_terms(len(st), 1)
+        top = p.single_product_top(2)
+        costs = sorted((st[i]["flops"] for i in split), reverse=True)
+        assert sorted((st[i]["flops"] for i in top), reverse=True) == costs[:2]
+        after = p.steps()
+        assert [i for i in split if after[i]["terms"] == 1] == sorted(top)
+    with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], precision="c64",
+                 host_only=True) as q:
+        with pytest.raises(tn.TnError):
+            q.set_step_terms(0, 1)

@@ -513,3 +513,120 @@ def test_rqc40_batching_form_full_size():
     finally:
         for p in plans + alone:
             p.close()
+
+
+def test_group_recaptures_after_retile():
+    """A plan re-tiled after its group captured a graph: the next group contraction uses the
+    new tiles (bitwise equal to the re-tiled plan alone), not the stale graph."""
+    print("group retile", flush=True)
+    items = _small_circuits(3)
+    kw = dict(precision="f16x3", split_policy=1)
+    plans = [tn.Plan(n.tensors, n.labels, n.open_labels, b["path"], **kw) for n, b in items]
+    alone = tn.Plan(items[0][0].tensors, items[0][0].labels, items[0][0].open_labels, items[0][1]["path"], **kw)
+    try:
+        mfma = [i for i, s in enumerate(plans[0].steps()) if s["kernel"] != 0]
+        assert mfma
+        with tn.Group(plans, branches=2) as g:
+            g.contract()
+            first, _ = plans[0].amplitudes()
+            s = mfma[0]
+            new_tile = (plans[0].steps()[s]["tile"] + 1) % 4
+            plans[0].set_tile(s, new_tile)
+            alone.set_tile(s, new_tile)
+            for p in plans:
+                p.reset()
+            g.contract()
+            got, c = plans[0].amplitudes()
+        assert c == 1
+        alone.contract()
+        ref, _ = alone.amplitudes()
+        assert np.array_equal(got, ref)
+        assert metrics.rel_l2(got, first) <= 2 * TOL["f16x3"]
+    finally:
+        for p in plans + [alone]:
+            p.close()
+
+
+def _round16(x, bf):
+    """float32 array rounded to fp16 (or bf16), round to nearest even, as float64."""
+    x = np.asarray(x, dtype=np.float32)
+    if not bf:
+        return x.astype(np.float16).astype(np.float64)
+    bits = x.view(np.uint32).astype(np.uint64)
+    r = ((bits + 0x7FFF + ((bits >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+def _split_hi(z, bf):
+    """The hi part the split kernels form for a complex64 leaf: scaled by the power of two
+    that brings max(|re|, |im|) to [2^14, 2^15), rounded to 16 bits, scaled back."""
+    z = z.astype(np.complex64)
+    mx = np.float32(max(np.abs(z.real).max(), np.abs(z.imag).max()))
+    e = 14 - (int(np.frexp(mx)[1]) - 1)
+    s = np.float32(2.0 ** e)
+    return (_round16(z.real * s, bf) + 1j * _round16(z.imag * s, bf)) / float(s)
+
+
+@pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
+def test_single_product_step_is_the_rounded_operands_product(prec):
+    """A split step run with one product (hi x hi) computes exactly the product of the 16-bit
+    rounded, power-of-two scaled operands, up to FP32 accumulation; with three products it is
+    within the extended-precision bound of the exact product."""
+    print(f"single product {prec}", flush=True)
+    bf = prec == "bf16x3"
+    rng = np.random.default_rng(17)
+    m, k, n = 256, 512, 128
+    A, B = _crandn(rng, (m, k)).astype(np.complex128), _crandn(rng, (k, n)).astype(np.complex128)
+    net = Network(tensors=[A, B], labels=[(0, 1), (1, 2)], open_labels=(0, 2))
+    exact = (A.astype(np.complex64).astype(np.complex128) @ B.astype(np.complex64).astype(np.complex128)).reshape(-1)
+    rounded = (_split_hi(A, bf) @ _split_hi(B, bf)).reshape(-1)
+    with tn.Plan(net.tensors, net.labels, net.open_labels, [(0, 1)], precision=prec, split_policy=1) as p:
+        st = p.steps()
+        assert st[0]["kernel"] in (2, 3) and st[0]["terms"] == 3
+        p.contract()
+        three, _ = p.amplitudes()
+        p.set_step_terms(0, 1)
+        assert p.steps()[0]["terms"] == 1
+        p.reset()
+        p.contract()
+        one, _ = p.amplitudes()
+    e1 = metrics.rel_l2(one, rounded)
+    e3 = metrics.rel_l2(three, exact)
+    e1x = metrics.rel_l2(one, exact)
+    print(f"{prec}: one product vs rounded {e1:.2e}, vs exact {e1x:.2e}; three products vs exact {e3:.2e}", flush=True)
+    assert e1 <= 1e-5
+    assert e3 <= GEMM_TOL[prec]
+    assert e1x > 10 * e3          # the single product really drops the correction terms
+
+
+def test_single_product_on_top_steps_trend():
+    """Per-step precision on the 30-qubit 12-cycle sub-case (512 amplitudes, stored oracle
+    amplitudes): single products on the k costliest split steps; k = 0 is the default plan
+    bit for bit, and the error grows with k while staying near the 16-bit rounding level."""
+    import importlib.util
+    import os
+    print("single product top-k", flush=True)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_rqc30d12_amplitudes.py")
+    spec = importlib.util.spec_from_file_location("make_rqc30d12_amplitudes", path)
+    fx = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(fx)
+    digest, ref = fx.read_fixture()
+    _, net, best = configs.build("rqc30d12")
+    assert digest == fx.network_digest(net, best)
+    errs = []
+    with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], precision="f16x3") as p:
+        p.contract()
+        base, _ = p.amplitudes()
+        n_split = sum(1 for s in p.steps() if s["kernel"] in (2, 3))
+        for k in (0, 1, 4, n_split):
+            p.single_product_top(k)
+            p.reset()
+            p.contract()
+            got, _ = p.amplitudes()
+            if k == 0:
+                assert np.array_equal(got, base)
+            errs.append(metrics.eps_l2sq(got, ref))
+            print(f"top-{k} of {n_split} split steps single: eps_l2^2 {errs[-1]:.3e} rel_l2 {metrics.rel_l2(got, ref):.3e}",
+                  flush=True)
+    assert errs[-1] > errs[0]
+    assert metrics.rel_l2(got, ref) <= 2e-2
