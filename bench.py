@@ -246,71 +246,83 @@ def sample_slices(n_slices: int, count: int, seed: int = 137):
 
 
 def run_slicing_choice(tn, torch, configs, workload, prec, n_candidates, n_timed):
-    """Contraction trees with their slicings (randomised greedy paths, each sliced to the
-    workload's cap) ranked three ways for the whole job (all slices): by flops (T_cc), by
-    the analytic flop/byte roofline model and by the learned model's predicted time (tiles
-    chosen by the model).  Each pick is then timed on the GPU over n_timed slices with the
-    model's tiles and its time extrapolated to all slices (slices cost the same)."""
+    """Slicings of the workload's contraction tree (the greedy slicer, and the slicer with
+    noisy costs for further candidates, each cutting bonds until the cap holds) ranked for
+    the whole job (all slices) three ways: by flops (T_cc), by the analytic flop/byte
+    roofline and by the learned model's predicted time with its own tiles.  Every
+    candidate is then timed on the GPU (n_timed seeded slices at full size, the model's
+    tiles) and its time extrapolated to all its slices (slices cost the same), so each
+    ranking's pick and its rank agreement with the measurement can be compared."""
     from paper_2310_03978_amd import costmodel
-    from tn_inputs.paths import choose_slices, greedy_path
-    _, net, _ = configs.build(workload)
+    from tn_inputs.paths import choose_slices
+    _, net, best = configs.build(workload)
     w = configs.WORKLOADS[workload]
     ext = net.extents()
-    cands = []
+    cands, seen = [], set()
     for t in range(n_candidates):
-        path = greedy_path(net.labels, net.open_labels, ext, seed=7000 + t,
-                           temperature=0.0 if t == 0 else 0.3)
-        sliced = choose_slices(net.labels, net.open_labels, ext, path, w.cap_log2)
-        cands.append((path, sliced))
-    with costmodel.CostModel.load() as model:
-        scored = []
-        for path, sliced in cands:
-            with tn.Plan(net.tensors, net.labels, net.open_labels, path, sliced, precision=prec,
-                         host_only=True, slice_batch=1) as h:
-                info = h.describe()
-                if info["max_intermediate"] > (1 << w.cap_log2):
-                    continue
-                flops = info["flops_invariant"] + info["n_slices"] * info["flops_per_slice"]
-                scored.append({"flops": flops, "analytic_us": costmodel.analytic_plan_us(h),
-                               "model_us": costmodel.predict_plan_us(h, model),
-                               "n_slices": info["n_slices"], "path": path, "sliced": sliced})
-    picks = {"flops": min(range(len(scored)), key=lambda i: scored[i]["flops"]),
-             "analytic": min(range(len(scored)), key=lambda i: scored[i]["analytic_us"]),
-             "learned_model": min(range(len(scored)), key=lambda i: scored[i]["model_us"])}
+        sliced = list(best["sliced"]) if t == 0 else choose_slices(
+            net.labels, net.open_labels, ext, best["path"], w.cap_log2, seed=t, temperature=0.5)
+        if tuple(sorted(sliced)) not in seen:
+            seen.add(tuple(sorted(sliced)))
+            cands.append(sliced)
     stream = torch.cuda.current_stream()
-    measured = {}
+    rows = []
+    with costmodel.CostModel.load() as model:
+        for sliced in cands:
+            args = (net.tensors, net.labels, net.open_labels, best["path"], sliced)
+            with tn.Plan(*args, precision=prec, host_only=True, slice_batch=1) as h:
+                info = h.describe()
+                r = {"sliced_labels": len(sliced), "n_slices": info["n_slices"],
+                     "flops": info["flops_invariant"] + info["n_slices"] * info["flops_per_slice"],
+                     "analytic_s": costmodel.analytic_plan_us(h) / 1e6,
+                     "predicted_s": costmodel.predict_plan_us(h, model) / 1e6}
+            with tn.Plan(*args, precision=prec, stream=stream, tuning=2, slice_batch=1) as p:
+                ids = sample_slices(info["n_slices"], n_timed + 1, 505)
+                p.contract(ids[0], 1)
+                torch.cuda.synchronize()
+                s0 = torch.cuda.Event(enable_timing=True)
+                e0 = torch.cuda.Event(enable_timing=True)
+                s0.record(stream)
+                for sid in ids[1:]:
+                    p.contract(sid, 1)
+                e0.record(stream)
+                torch.cuda.synchronize()
+                p.amplitudes()
+                r["measured_ms_per_slice"] = s0.elapsed_time(e0) / n_timed
+            r["measured_s"] = r["measured_ms_per_slice"] * r["n_slices"] / 1e3
+            rows.append(r)
 
-    def measure(i):
-        c = scored[i]
-        with tn.Plan(net.tensors, net.labels, net.open_labels, c["path"], c["sliced"], precision=prec,
-                     stream=stream, tuning=2, slice_batch=1) as p:
-            ids = sample_slices(c["n_slices"], n_timed + 1, 505)
-            p.contract(ids[0], 1)
-            torch.cuda.synchronize()
-            s = torch.cuda.Event(enable_timing=True)
-            e = torch.cuda.Event(enable_timing=True)
-            s.record(stream)
-            for sid in ids[1:]:
-                p.contract(sid, 1)
-            e.record(stream)
-            torch.cuda.synchronize()
-            p.amplitudes()
-            return s.elapsed_time(e) / n_timed
+    def ranks(v):
+        order = sorted(range(len(v)), key=lambda i: v[i])
+        out = [0] * len(v)
+        for k, i in enumerate(order):
+            out[i] = k
+        return out
 
-    out = {"workload": f"{workload}: {w.description}", "candidates": len(scored), "cap_log2": w.cap_log2,
-           "slices_timed_per_pick": n_timed, "precision": prec}
-    for name, i in picks.items():
-        if i not in measured:
-            measured[i] = measure(i)
-        c = scored[i]
-        out[f"pick_by_{name}"] = {
-            "candidate": i, "sliced_labels": len(c["sliced"]), "flops": c["flops"],
-            "analytic_s": round(c["analytic_us"] / 1e6, 2), "predicted_s": round(c["model_us"] / 1e6, 2),
-            "measured_ms_per_slice": round(measured[i], 3),
-            "measured_job_s": round(measured[i] * c["n_slices"] / 1e3, 1)}
-    job = {k: out[f"pick_by_{k}"]["measured_job_s"] for k in picks}
-    out["learned_vs_flops_speedup"] = round(job["flops"] / job["learned_model"], 3)
-    out["learned_vs_analytic_speedup"] = round(job["analytic"] / job["learned_model"], 3)
+    def spearman(x, y):
+        rx, ry = ranks(x), ranks(y)
+        n = len(x)
+        return 1.0 - 6.0 * sum((a - b) ** 2 for a, b in zip(rx, ry)) / (n * (n * n - 1)) if n > 1 else 1.0
+
+    meas = [r["measured_s"] for r in rows]
+    out = {"workload": f"{workload}: {w.description}", "cap_log2": w.cap_log2, "candidates": len(rows),
+           "slices_timed_per_candidate": n_timed, "precision": prec,
+           "fastest_measured_s": round(min(meas), 1)}
+    for name, key in (("flops", "flops"), ("analytic", "analytic_s"), ("learned_model", "predicted_s")):
+        vals = [r[key] for r in rows]
+        i = min(range(len(rows)), key=lambda j: vals[j])
+        out[f"pick_by_{name}"] = {"candidate": i, "sliced_labels": rows[i]["sliced_labels"],
+                                  "measured_s": round(rows[i]["measured_s"], 1),
+                                  "rank_correlation_with_measured": round(spearman(vals, meas), 3)}
+    for name, key in (("analytic", "analytic_s"), ("learned_model", "predicted_s")):
+        errs = sorted(abs(r[key] / r["measured_s"] - 1.0) for r in rows)
+        out[f"pick_by_{name}"]["median_abs_rel_error_of_job_time"] = round(errs[len(errs) // 2], 3)
+    out["learned_vs_flops_speedup"] = round(out["pick_by_flops"]["measured_s"] /
+                                            out["pick_by_learned_model"]["measured_s"], 3)
+    out["learned_vs_analytic_speedup"] = round(out["pick_by_analytic"]["measured_s"] /
+                                               out["pick_by_learned_model"]["measured_s"], 3)
+    out["rows"] = [{k: (round(v, 3) if isinstance(v, float) and k != "flops" else v) for k, v in r.items()}
+                   for r in rows]
     return out
 
 

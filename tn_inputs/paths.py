@@ -164,13 +164,16 @@ def _masked_log(mask, lg_items):
 
 
 def choose_slices(labels, open_labels, extents, path, cap_log2: int, min_sliced: int = 0,
-                  max_sliced: int = 64) -> list:
+                  max_sliced: int = 64, seed=None, temperature: float = 0.0) -> list:
     """Greedy slicing: cut bonds until the largest intermediate is <= 2^cap_log2.
 
     Slicing a label removes it from every tensor without changing how the other
     labels are classified, so each step's sliced sizes are its unsliced label
-    sets minus the sliced labels.
+    sets minus the sliced labels.  With a seed and temperature > 0 the candidates'
+    total costs are multiplied by log-normal noise, giving other slicings of the
+    same tree for comparison.
     """
+    rng = np.random.default_rng(seed) if (seed is not None and temperature > 0) else None
     lg = _log2ext(extents)
     unit = all(w == 1 for w in lg.values())
     lg_items = None if unit else sorted(lg.items())
@@ -202,6 +205,8 @@ def choose_slices(labels, open_labels, extents, path, cap_log2: int, min_sliced:
         best = None
         for l in cands:
             t2, m2 = cost(smask | (1 << l))
+            if rng is not None:
+                t2 *= float(np.exp(temperature * rng.standard_normal()))
             key = (m2 if mx > cap_log2 else 0, t2)
             if best is None or key < best[0]:
                 best = (key, l)
