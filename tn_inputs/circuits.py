@@ -129,3 +129,14 @@ def open_and_closed(n_qubits: int, k_open: int, seed: int):
     closed = {q: int(b) for q, b in zip(range(n_qubits - k_open),
                                          rng.integers(0, 2, size=n_qubits - k_open))}
     return open_q, closed
+
+
+def sample_bitstrings(n_qubits: int, count: int, seed: int, duplicates: int = 0):
+    """count uniformly random bitstrings (uint8 [count, n_qubits], qubit order), seeded;
+    the last `duplicates` rows repeat earlier ones.  Stand-ins for measured samples."""
+    rng = np.random.default_rng(seed)
+    x = rng.integers(0, 2, size=(count, n_qubits), dtype=np.uint8)
+    if duplicates:
+        src = rng.integers(0, max(count - duplicates, 1), size=duplicates)
+        x[count - duplicates:] = x[src]
+    return x
