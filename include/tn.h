@@ -121,6 +121,8 @@ typedef struct {
                                   pipeline; both operands stored split, k pairs contiguous, 256 x 128 tiles) */
   int32_t terms;               /* split steps: 3 = hi*hi + hi*lo + lo*hi (default), 1 = hi*hi only
                                   (tn_plan_set_step_terms); 0 for the other kernels */
+  int32_t merged_bits;         /* sparse-state plans: bits of the merged open bond of a sparse einsum
+                                  (its lowest batch bits, indexed through tables); -1 otherwise */
 } tn_step_info;
 
 /* Build a plan.
@@ -148,6 +150,30 @@ tn_status tn_plan_create(tn_plan* out, int32_t n_tensors, const int32_t* ranks,
                          const double* const* data, int32_t n_open, const int32_t* open_labels,
                          int32_t n_steps, const int32_t* path, int32_t n_sliced,
                          const int32_t* sliced_labels, const tn_options* opts);
+
+/* Build a sparse-state plan (Sec. 3.3): the amplitudes of n_bitstrings sampled
+ * bitstrings from one contraction.  Arguments as tn_plan_create, plus
+ *  bitstrings       host uint8 [n_bitstrings][n_open], row-major, values 0 or 1: bitstring
+ *                   i gives open label j the value bitstrings[i * n_open + j].  COPIED.
+ * Every open label must have extent 2 and sit on exactly one leaf; n_open <= 64.
+ * When two tensors that both hold open labels meet, their open bonds merge into one
+ * bond whose values are the distinct restrictions of the bitstrings to the qubits they
+ * hold (the sparse einsum), computed as one batched product whose operand offsets come
+ * from per-step tables.  The plan's amplitude vector (tn_plan_info.n_amplitudes,
+ * tn_amplitudes, tn_slice_partials) then holds one entry per value of the root's merged
+ * bond; tn_plan_sparse_index gives each bitstring's entry.  TN_E_UNSUPPORTED for open
+ * labels that break these rules, TN_E_ARG for bad bitstrings. */
+tn_status tn_plan_create_sparse(tn_plan* out, int32_t n_tensors, const int32_t* ranks,
+                                const int32_t* const* labels, const int64_t* const* extents,
+                                const double* const* data, int32_t n_open, const int32_t* open_labels,
+                                int32_t n_steps, const int32_t* path, int32_t n_sliced,
+                                const int32_t* sliced_labels, int64_t n_bitstrings,
+                                const uint8_t* bitstrings, const tn_options* opts);
+
+/* For a sparse-state plan: index[i] = the entry of the plan's amplitude vector that holds
+ * bitstring i's amplitude (host array of n_bitstrings, which must match the plan).
+ * TN_E_STATE for a plan built without bitstrings. */
+tn_status tn_plan_sparse_index(tn_plan plan, int64_t* index, int64_t n_bitstrings);
 
 /* Free a plan; legal on NULL and on partly built plans.  Synchronises the plan's stream. */
 void tn_plan_destroy(tn_plan plan);

@@ -77,6 +77,11 @@ struct GettArgs {
   int32_t split_bf16;           // split storage uses bf16 halves (else fp16)
   int32_t dma;                  // split kernels: operands copied global -> LDS directly (k_gett_dma)
   int32_t terms;                // split kernels: 3 = hi.hi + hi.lo + lo.hi, 1 = hi.hi only
+  // sparse einsum: the lowest tab_bits batch bits index per-step tables of element
+  // offsets added to A's and B's batch offsets (null when the step has none)
+  const int64_t* tab_a;
+  const int64_t* tab_b;
+  int32_t tab_bits;
 };
 
 // Storage formats of an intermediate.  TN_FMT_SPLIT keeps, per complex element,

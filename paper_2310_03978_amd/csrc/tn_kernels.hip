@@ -239,8 +239,13 @@ __device__ void gett_small_block(const GettDesc* __restrict__ d, const GettArgs&
     }
     sl = (int)(bidx >> d->own_bb);
     const Scales sc = step_scales(d, g, sl);
-    const int64_t oa = bits_offset(bidx, d->a_b, nbb) + bits_offset(m, d->a_m, d->mb);
-    const int64_t ob = bits_offset(bidx, d->b_b, nbb) + bits_offset(n, d->b_n, d->nb);
+    int64_t oa = bits_offset(bidx, d->a_b, nbb) + bits_offset(m, d->a_m, d->mb);
+    int64_t ob = bits_offset(bidx, d->b_b, nbb) + bits_offset(n, d->b_n, d->nb);
+    if (g.tab_bits) {   // sparse einsum: the merged bond's value selects the operands' slices
+      const uint64_t f = bidx & ((1ull << g.tab_bits) - 1);
+      oa += g.tab_a[f];
+      ob += g.tab_b[f];
+    }
     const float2* A = reinterpret_cast<const float2*>(g.A);
     const float2* B = reinterpret_cast<const float2*>(g.B);
     float cr = 0.f, ci = 0.f;
@@ -305,6 +310,7 @@ struct Tile {
 struct TileCtx {
   uint64_t tile_m, tile_n, bidx;
   int split, nbb, lm, ln, lk, sl;
+  int64_t a_tab, b_tab;   // sparse-einsum table offsets of the tile's batch (0 without tables)
   Scales sc;
 };
 
@@ -327,6 +333,12 @@ __device__ __forceinline__ TileCtx tile_ctx(const GettDesc* __restrict__ d, cons
   c.lk = d->kb < 4 ? d->kb : 4;
   c.sl = (int)(c.bidx >> d->own_bb);
   c.sc = step_scales(d, g, c.sl);
+  c.a_tab = c.b_tab = 0;
+  if (g.tab_bits) {
+    const uint64_t f = c.bidx & ((1ull << g.tab_bits) - 1);
+    c.a_tab = g.tab_a[f];
+    c.b_tab = g.tab_b[f];
+  }
   return c;
 }
 
@@ -352,8 +364,8 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
   const Scales& sc = cx.sc;
   constexpr bool bf = P == 2;
 
-  const int64_t a_base = bits_offset(bidx, d->a_b, nbb) + bits_offset(tile_m << lm, d->a_m, d->mb);
-  const int64_t b_base = bits_offset(bidx, d->b_b, nbb) + bits_offset(tile_n << ln, d->b_n, d->nb);
+  const int64_t a_base = bits_offset(bidx, d->a_b, nbb) + bits_offset(tile_m << lm, d->a_m, d->mb) + cx.a_tab;
+  const int64_t b_base = bits_offset(bidx, d->b_b, nbb) + bits_offset(tile_n << ln, d->b_n, d->nb) + cx.b_tab;
   const uint2* A = reinterpret_cast<const uint2*>(g.A);
   const uint2* B = reinterpret_cast<const uint2*>(g.B);
 
@@ -718,8 +730,8 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
   const TileCtx cx = tile_ctx<4, 2>(d, g, bid);
   const int nbb = cx.nbb;
 
-  const int64_t a_base = bits_offset(cx.bidx, d->a_b, nbb) + bits_offset(cx.tile_m << 8, d->a_m, d->mb);
-  const int64_t b_base = bits_offset(cx.bidx, d->b_b, nbb) + bits_offset(cx.tile_n << 7, d->b_n, d->nb);
+  const int64_t a_base = bits_offset(cx.bidx, d->a_b, nbb) + bits_offset(cx.tile_m << 8, d->a_m, d->mb) + cx.a_tab;
+  const int64_t b_base = bits_offset(cx.bidx, d->b_b, nbb) + bits_offset(cx.tile_n << 7, d->b_n, d->nb) + cx.b_tab;
   char* lds = reinterpret_cast<char*>(smem);
 
   // The quad each lane copies: DMA instruction i of wave w fills rows (8 i + w) * 8 + lane / 8

@@ -65,6 +65,8 @@ struct Label {
   bool open = false;
   int slice_pos = -1;
   int user = 0;
+  int qubit = -1;   // sparse-state plans: column of the bitstrings this open label measures
+  bool merged = false;  // sparse-state plans: a merged open bond (made by the planner)
 };
 
 struct Tensor {
@@ -79,6 +81,12 @@ struct Tensor {
   int arena = 0;             // 0 leaves, 1 invariant, 2 per-slice
   int64_t offset = 0;        // elements
   std::vector<int> user_layout;  // leaves: bits of the caller's row-major data, LSB first
+  // sparse-state plans (Sec. 3.3): measured qubits whose open bonds this tensor holds
+  // (bit i = bitstring column i), either as their own labels (raw) or as one merged bond
+  // `merged` whose value v stands for keys[v], a distinct restriction of the bitstrings
+  uint64_t sq = 0;
+  int merged = -1;
+  std::vector<uint64_t> keys;
 };
 
 struct Step {
@@ -97,6 +105,14 @@ struct Step {
   int terms = 3;                     // split steps: products per complex multiply-add term (3 or 1)
   double flops = 0, bytes = 0;
   int64_t scratch_elems = 0;         // split-K partials (elements)
+  // sparse einsum (Sec. 3.3): the result's merged bond `tab_label` is the step's lowest
+  // batch bits; operand offsets for its value f come from tables (element offsets)
+  int tab_label = -1;
+  std::vector<int> ia_labels, ib_labels;   // open-bond labels of A and B the tables index
+  std::vector<int64_t> tab_a, tab_b;
+  int64_t tab_a_max = 0, tab_b_max = 0;
+  int64_t* d_tab_a = nullptr;
+  int64_t* d_tab_b = nullptr;
   GettDesc desc;
 };
 
@@ -161,6 +177,11 @@ struct tn_plan_s {
   int64_t n_slices = 1;
   int64_t n_amp = 1;
   int n_leaves = 0;
+  // sparse-state plans: bitstring keys (bit i = column i) and, per bitstring, the index of
+  // its amplitude in the root's merged open bond
+  bool sparse = false;
+  std::vector<uint64_t> bkeys;
+  std::vector<int64_t> amp_index;
 
   std::vector<Tensor> tensors;
   std::vector<Step> steps;
@@ -185,6 +206,8 @@ struct tn_plan_s {
   double* d_part = nullptr;        // [S][n_amp] complex128 partials
   int32_t* d_flag = nullptr;
   float* d_scratch = nullptr;      // split-K partials, shared by all steps (one stream)
+  int64_t* d_tabs = nullptr;       // sparse-einsum tables of every step (element offsets)
+  int64_t tab_elems = 0;
   int64_t scratch_elems = 0;
   // caller-owned workspace (options.workspace): every device buffer is carved from it
   bool own_memory = true;
@@ -208,7 +231,7 @@ struct tn_plan_s {
     if (stream) hipStreamSynchronize(stream);
     else if (!host_only) hipDeviceSynchronize();
     void* ptrs[] = {d_leaves, d_inv, d_ps, d_desc, d_max_inv, d_max_ps, d_exp_inv, d_exp_ps, d_acc, d_part, d_flag,
-                    d_scratch};
+                    d_scratch, d_tabs};
     if (own_memory)
       for (void* p : ptrs)
         if (p) hipFree(p);
@@ -397,6 +420,48 @@ void choose_kernel(tn_plan_s* p, Step& st) {
   set_tile(p, st, tile);
 }
 
+// Offset (elements) in tensor T of the open bonds' values for bitstring key `key`:
+// raw open labels contribute their bit's stride when the key's bit is set; a merged
+// bond contributes the strides of the bits of its value, the index of the key's
+// restriction to T's measured qubits among T's keys.
+int64_t open_offset(const tn_plan_s* p, const Tensor& T, uint64_t key) {
+  int64_t off = 0;
+  if (T.merged >= 0) {
+    const uint64_t r = key & T.sq;
+    const int64_t v = std::lower_bound(T.keys.begin(), T.keys.end(), r) - T.keys.begin();
+    const Label& L = p->labels[T.merged];
+    for (int b = 0; b < L.nb; ++b)
+      if ((v >> b) & 1) off += bit_stride(T, L.bit0 + b);
+    return off;
+  }
+  for (int l : T.labels) {
+    const Label& L = p->labels[l];
+    if (L.qubit >= 0 && ((key >> L.qubit) & 1)) off += bit_stride(T, L.bit0);
+  }
+  return off;
+}
+
+// Tables of a sparse-einsum step: for each value f of the result's merged bond (padding
+// values repeat f = 0), the offsets in A and B of the restrictions of keys[f].
+void build_tables(tn_plan_s* p, Step& st) {
+  const Tensor& A = p->tensors[st.ta];
+  const Tensor& B = p->tensors[st.tb];
+  const Tensor& C = p->tensors[st.tc];
+  const int64_t ext = p->labels[st.tab_label].ext;
+  st.tab_a.assign(ext, 0);
+  st.tab_b.assign(ext, 0);
+  for (size_t f = 0; f < C.keys.size(); ++f) {
+    st.tab_a[f] = open_offset(p, A, C.keys[f]);
+    st.tab_b[f] = open_offset(p, B, C.keys[f]);
+  }
+  for (int64_t f = (int64_t)C.keys.size(); f < ext; ++f) {
+    st.tab_a[f] = st.tab_a[0];
+    st.tab_b[f] = st.tab_b[0];
+  }
+  st.tab_a_max = *std::max_element(st.tab_a.begin(), st.tab_a.end());
+  st.tab_b_max = *std::max_element(st.tab_b.begin(), st.tab_b.end());
+}
+
 // Every address a kernel forms is a sum of per-bit strides.  Check, for every
 // step and operand, that the largest reachable offset stays inside its buffer
 // and that no two bits share a non-zero stride.
@@ -422,7 +487,7 @@ tn_status validate_steps(const tn_plan_s* p, const std::vector<Step>& steps) {
       for (int j = 0; j < ops[o].nr; ++j) strides.push_back(ops[o].r[j]);
       for (int j = 0; j < ops[o].nk; ++j) strides.push_back(ops[o].k[j]);
       int64_t cap = T.leaf ? (T.elems << T.sbits.size()) : (T.per_slice ? T.elems * S : T.elems);
-      int64_t mx = 0;
+      int64_t mx = o == 0 ? st.tab_a_max : o == 1 ? st.tab_b_max : 0;   // sparse-einsum table offsets
       if (T.leaf && T.per_slice)  // slice bits above the chunk are a base offset
         for (int j = (st.per_slice ? p->s_bits : 0); j < p->n_slice_bits; ++j) mx += bit_stride(T, p->slice_bits[j]);
       std::set<int64_t> seen;
@@ -549,6 +614,18 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
     p->labels[it->second].open = true;
     open_d.push_back(it->second);
   }
+  if (p->sparse) {
+    if (n_open > 64) return fail(TN_E_UNSUPPORTED, "a sparse state measures at most 64 open labels");
+    for (int i = 0; i < n_open; ++i) {
+      Label& L = p->labels[open_d[i]];
+      if (L.ext != 2) return fail(TN_E_UNSUPPORTED, "open labels of a sparse state must have extent 2");
+      L.qubit = i;
+      int on = 0;
+      for (int t = 0; t < n_tensors; ++t)
+        for (int r = 0; r < ranks[t]; ++r) on += labels[t][r] == open_labels[i] ? 1 : 0;
+      if (on != 1) return fail(TN_E_UNSUPPORTED, "an open label of a sparse state must be on exactly one tensor");
+    }
+  }
   std::vector<int> sliced_d;
   for (int i = 0; i < n_sliced; ++i) {
     auto it = dense.find(sliced_labels[i]);
@@ -575,8 +652,8 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
   p->n_slices = int64_t(1) << p->n_slice_bits;
   int amp_bits = 0;
   for (int l : open_d) amp_bits += p->labels[l].nb;
-  if (amp_bits > 30) return fail(TN_E_UNSUPPORTED, "too many output bits");
-  p->n_amp = int64_t(1) << amp_bits;
+  if (!p->sparse && amp_bits > 30) return fail(TN_E_UNSUPPORTED, "too many output bits");
+  if (!p->sparse) p->n_amp = int64_t(1) << amp_bits;
 
   // leaves (plus a unit scalar when the network is a single tensor)
   const bool single = n_tensors == 1;
@@ -600,6 +677,7 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
       } else {
         T.labels.push_back(l);
       }
+      if (p->labels[l].qubit >= 0) T.sq |= uint64_t(1) << p->labels[l].qubit;
     }
     p->tensors.push_back(T);
   }
@@ -635,13 +713,55 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
     std::set<int> all = sa;
     all.insert(sbs.begin(), sbs.end());
     Tensor C;
+    // sparse einsum (Sec. 3.3): both operands hold open bonds of measured qubits; those
+    // bonds are not classified but indexed through the step's tables
+    const bool merge = p->sparse && A.sq != 0 && B.sq != 0;
+    std::set<int> indexed;
+    if (merge) {
+      for (int l : A.labels)
+        if (p->labels[l].open) st.ia_labels.push_back(l);
+      for (int l : B.labels)
+        if (p->labels[l].open) st.ib_labels.push_back(l);
+      indexed.insert(st.ia_labels.begin(), st.ia_labels.end());
+      indexed.insert(st.ib_labels.begin(), st.ib_labels.end());
+    }
     for (int l : all) {
+      if (indexed.count(l)) continue;
       const bool keep = p->labels[l].open || count[l] > 0;
       const bool ina = sa.count(l), inb = sbs.count(l);
       if (ina && inb) (keep ? st.lb : st.lk).push_back(l);
       else if (ina) (keep ? st.lm : st.lk).push_back(l);
       else (keep ? st.ln : st.lk).push_back(l);
       if (keep) C.labels.push_back(l);
+    }
+    if (merge) {
+      // the merged bond: one value per distinct restriction of the bitstrings to the
+      // union of the operands' measured qubits, in increasing order, padded to a power of two
+      const uint64_t q = A.sq | B.sq;
+      for (uint64_t k : p->bkeys) C.keys.push_back(k & q);
+      std::sort(C.keys.begin(), C.keys.end());
+      C.keys.erase(std::unique(C.keys.begin(), C.keys.end()), C.keys.end());
+      Label L;
+      while ((int64_t(1) << L.nb) < (int64_t)C.keys.size()) ++L.nb;
+      L.ext = int64_t(1) << L.nb;
+      L.open = true;
+      L.merged = true;
+      L.user = -1;
+      L.bit0 = p->n_bits;
+      p->n_bits += L.nb;
+      const int ml = (int)p->labels.size();
+      p->labels.push_back(L);
+      count.push_back(0);
+      st.lb.push_back(ml);
+      C.labels.push_back(ml);
+      st.tab_label = ml;
+      C.sq = q;
+      C.merged = ml;
+    } else {
+      const Tensor& O = A.sq != 0 ? A : B;
+      C.sq = A.sq | B.sq;
+      C.merged = O.merged;
+      C.keys = O.keys;
     }
     for (int l : C.labels) count[l]++;
     C.per_slice = A.per_slice || B.per_slice;
@@ -666,6 +786,10 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
     if (nb > 36) return fail(TN_E_UNSUPPORTED, "tensor with more than 2^36 elements");
     T.elems = int64_t(1) << nb;
   }
+  if (p->sparse) {
+    if (p->tensors[p->root].elems > (int64_t(1) << 30)) return fail(TN_E_UNSUPPORTED, "too many output bits");
+    p->n_amp = p->tensors[p->root].elems;
+  }
   for (auto& st : p->steps) {
     p->max_intermediate = std::max(p->max_intermediate, p->tensors[st.tc].elems);
     if (p->opts.mem_cap_elems > 0 && p->tensors[st.tc].elems > p->opts.mem_cap_elems)
@@ -676,9 +800,16 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
   {
     Tensor& R = p->tensors[p->root];
     R.bits.clear();
-    for (int i = (int)open_d.size() - 1; i >= 0; --i) {
-      const Label& L = p->labels[open_d[i]];
+    if (p->sparse && R.merged >= 0) {
+      const Label& L = p->labels[R.merged];
       for (int b = 0; b < L.nb; ++b) R.bits.push_back(L.bit0 + b);
+    } else {
+      const std::set<int> rl(R.labels.begin(), R.labels.end());
+      for (int i = (int)open_d.size() - 1; i >= 0; --i) {
+        if (p->sparse && !rl.count(open_d[i])) continue;
+        const Label& L = p->labels[open_d[i]];
+        for (int b = 0; b < L.nb; ++b) R.bits.push_back(L.bit0 + b);
+      }
     }
     R.layout_set = true;
   }
@@ -698,6 +829,13 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
       return v;
     };
     st.bb = by_cpos(bits_of(st.lb));
+    if (st.tab_label >= 0) {   // the merged bond's bits are the lowest batch bits (table index)
+      std::vector<int> tb = bits_of({st.tab_label}), rest;
+      for (int q : st.bb)
+        if (std::find(tb.begin(), tb.end(), q) == tb.end()) rest.push_back(q);
+      st.bb = tb;
+      st.bb.insert(st.bb.end(), rest.begin(), rest.end());
+    }
     st.mb = by_cpos(bits_of(st.lm));
     st.nb = by_cpos(bits_of(st.ln));
     st.kb = bits_of(st.lk);
@@ -714,12 +852,16 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
     for (int q : st.kb)
       if (abits.count(q)) A.bits.push_back(q);
     for (int q : st.mb) A.bits.push_back(q);
-    for (int q : st.bb) A.bits.push_back(q);
+    for (int q : st.bb)
+      if (abits.count(q)) A.bits.push_back(q);
+    for (int q : bits_of(st.ia_labels)) A.bits.push_back(q);   // open bonds the tables index
     B.bits.clear();
     for (int q : st.kb)
       if (bbits.count(q)) B.bits.push_back(q);
     for (int q : st.nb) B.bits.push_back(q);
-    for (int q : st.bb) B.bits.push_back(q);
+    for (int q : st.bb)
+      if (bbits.count(q)) B.bits.push_back(q);
+    for (int q : bits_of(st.ib_labels)) B.bits.push_back(q);
     A.layout_set = B.layout_set = true;
   }
   // leaves: sliced bits on top, in slice-id order
@@ -796,6 +938,15 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
   }
   p->inv_elems = std::max<int64_t>(inv.peak, 64);
   p->ps_elems = std::max<int64_t>(ps.peak, 64);
+  if (p->sparse) {
+    for (auto& st : p->steps)
+      if (st.tab_label >= 0) {
+        build_tables(p, st);
+        p->tab_elems += 2 * p->labels[st.tab_label].ext;
+      }
+    const Tensor& R = p->tensors[p->root];
+    for (uint64_t k : p->bkeys) p->amp_index.push_back(open_offset(p, R, k));
+  }
   for (auto& st : p->steps) build_desc(p, st);
   p->S = (int)S;
   for (auto& st : p->steps) p->scratch_elems = std::max(p->scratch_elems, st.scratch_elems);
@@ -816,7 +967,8 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
   const size_t dev_bytes[] = {(size_t)p->leaf_elems * 8, (size_t)p->inv_elems * 8, (size_t)p->ps_elems * 8,
                               sizeof(GettDesc) * std::max<size_t>(p->steps.size(), 1) + sizeof(PermDesc),
                               nt * 4, nt * S * 4, nt * 4, nt * S * 4, (size_t)p->n_amp * 16,
-                              (size_t)p->n_amp * 16 * S, 64, (size_t)scratch_any * 8, (size_t)max_leaf * 8};
+                              (size_t)p->n_amp * 16 * S, 64, (size_t)scratch_any * 8, (size_t)max_leaf * 8,
+                              (size_t)p->tab_elems * 8};
   p->ws_need = 0;
   for (size_t b : dev_bytes) p->ws_need += (int64_t)((b + 255) & ~size_t(255));
   if (p->host_only) return TN_OK;
@@ -865,6 +1017,20 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
   if ((st = dmalloc((void**)&p->d_part, p->n_amp * 16 * S))) return st;
   if ((st = dmalloc((void**)&p->d_flag, 64))) return st;
   if (p->scratch_elems > 0 && (st = dmalloc((void**)&p->d_scratch, p->scratch_elems * 8))) return st;
+  if (p->tab_elems > 0) {
+    if ((st = dmalloc((void**)&p->d_tabs, p->tab_elems * 8))) return st;
+    std::vector<int64_t> all;
+    for (auto& stp : p->steps)
+      if (stp.tab_label >= 0) {
+        stp.d_tab_a = p->d_tabs + all.size();
+        all.insert(all.end(), stp.tab_a.begin(), stp.tab_a.end());
+        stp.d_tab_b = p->d_tabs + all.size();
+        all.insert(all.end(), stp.tab_b.begin(), stp.tab_b.end());
+      }
+    if ((st = check(hipMemcpyAsync(p->d_tabs, all.data(), all.size() * 8, hipMemcpyHostToDevice, s), "table upload")))
+      return st;
+    if ((st = check(hipStreamSynchronize(s), "table upload sync"))) return st;
+  }
   if ((st = check(hipMemsetAsync(p->d_acc, 0, p->n_amp * 16, s), "memset acc"))) return st;
   if ((st = check(hipMemsetAsync(p->d_flag, 0, 64, s), "memset flag"))) return st;
   if ((st = check(hipMemsetAsync(p->d_max_inv, 0, nt * 4, s), "memset max"))) return st;
@@ -1048,6 +1214,11 @@ void step_launches(const tn_plan_s* p, const Step& st, const GettDesc* d, int s,
   g.split_bf16 = p->precision == TN_PREC_BF16X3 ? 1 : 0;
   g.dma = st.dma ? 1 : 0;
   g.terms = st.terms;
+  if (st.tab_label >= 0) {
+    g.tab_a = st.d_tab_a;
+    g.tab_b = st.d_tab_b;
+    g.tab_bits = p->labels[st.tab_label].nb;
+  }
   L.desc = d;
   L.step = s;
   L.kind = st.kernel;
@@ -1355,14 +1526,38 @@ const char* tn_status_string(tn_status s) {
 
 const char* tn_last_error_message(void) { return g_err.c_str(); }
 
-tn_status tn_plan_create(tn_plan* out, int32_t n_tensors, const int32_t* ranks, const int32_t* const* labels,
-                         const int64_t* const* extents, const double* const* data, int32_t n_open,
-                         const int32_t* open_labels, int32_t n_steps, const int32_t* path, int32_t n_sliced,
-                         const int32_t* sliced_labels, const tn_options* opts) {
+}  // extern "C"
+
+namespace {
+tn_status create_plan(tn_plan* out, int32_t n_tensors, const int32_t* ranks, const int32_t* const* labels,
+                      const int64_t* const* extents, const double* const* data, int32_t n_open,
+                      const int32_t* open_labels, int32_t n_steps, const int32_t* path, int32_t n_sliced,
+                      const int32_t* sliced_labels, int64_t n_bitstrings, const uint8_t* bitstrings,
+                      const tn_options* opts) {
   if (!out) return fail(TN_E_ARG, "null output pointer");
   *out = nullptr;
   tn_plan_s* p = new (std::nothrow) tn_plan_s();
   if (!p) return fail(TN_E_NOMEM, "host allocation failed");
+  if (bitstrings) {
+    if (n_bitstrings < 1 || n_open < 1) {
+      delete p;
+      return fail(TN_E_ARG, "a sparse state needs at least one bitstring and one open label");
+    }
+    p->sparse = true;
+    p->bkeys.resize(n_bitstrings);
+    for (int64_t i = 0; i < n_bitstrings; ++i) {
+      uint64_t k = 0;
+      for (int32_t c = 0; c < n_open && c < 64; ++c) {
+        const uint8_t v = bitstrings[i * n_open + c];
+        if (v > 1) {
+          delete p;
+          return fail(TN_E_ARG, "bitstring values must be 0 or 1");
+        }
+        k |= uint64_t(v) << c;
+      }
+      p->bkeys[i] = k;
+    }
+  }
   if (opts) {
     if (opts->struct_size < (int32_t)offsetof(tn_options, reserved)) {
       delete p;
@@ -1387,6 +1582,35 @@ tn_status tn_plan_create(tn_plan* out, int32_t n_tensors, const int32_t* ranks, 
     return st;
   }
   *out = p;
+  return TN_OK;
+}
+}  // namespace
+
+extern "C" {
+
+tn_status tn_plan_create(tn_plan* out, int32_t n_tensors, const int32_t* ranks, const int32_t* const* labels,
+                         const int64_t* const* extents, const double* const* data, int32_t n_open,
+                         const int32_t* open_labels, int32_t n_steps, const int32_t* path, int32_t n_sliced,
+                         const int32_t* sliced_labels, const tn_options* opts) {
+  return create_plan(out, n_tensors, ranks, labels, extents, data, n_open, open_labels, n_steps, path, n_sliced,
+                     sliced_labels, 0, nullptr, opts);
+}
+
+tn_status tn_plan_create_sparse(tn_plan* out, int32_t n_tensors, const int32_t* ranks, const int32_t* const* labels,
+                                const int64_t* const* extents, const double* const* data, int32_t n_open,
+                                const int32_t* open_labels, int32_t n_steps, const int32_t* path, int32_t n_sliced,
+                                const int32_t* sliced_labels, int64_t n_bitstrings, const uint8_t* bitstrings,
+                                const tn_options* opts) {
+  if (!bitstrings) return fail(TN_E_ARG, "null bitstrings");
+  return create_plan(out, n_tensors, ranks, labels, extents, data, n_open, open_labels, n_steps, path, n_sliced,
+                     sliced_labels, n_bitstrings, bitstrings, opts);
+}
+
+tn_status tn_plan_sparse_index(tn_plan p, int64_t* index, int64_t n_bitstrings) {
+  if (!p || !index) return fail(TN_E_ARG, "null argument");
+  if (!p->sparse) return fail(TN_E_STATE, "the plan has no sparse state");
+  if (n_bitstrings != (int64_t)p->amp_index.size()) return fail(TN_E_ARG, "n_bitstrings does not match the plan");
+  std::copy(p->amp_index.begin(), p->amp_index.end(), index);
   return TN_OK;
 }
 
@@ -1434,6 +1658,7 @@ tn_status tn_plan_steps(tn_plan p, tn_step_info* steps, int32_t cap) {
     o.b_contig = st.b_contig;
     o.flops = st.flops;
     o.terms = (st.kernel == TN_K_MFMA_F16X3 || st.kernel == TN_K_MFMA_BF16X3) ? st.terms : 0;
+    o.merged_bits = st.tab_label >= 0 ? p->labels[st.tab_label].nb : -1;
     o.bytes = st.bytes;
     o.tile = st.kernel == TN_K_SMALL ? -1 : st.tile;
     o.lds_copy = st.dma ? 1 : 0;

@@ -36,7 +36,7 @@ STATUS = {0: "TN_OK", -1: "TN_E_ARG", -2: "TN_E_LABEL", -3: "TN_E_PATH", -4: "TN
           -5: "TN_E_CAP", -6: "TN_E_NOMEM", -7: "TN_E_DEVICE", -8: "TN_E_STATE",
           -9: "TN_E_UNSUPPORTED", -10: "TN_E_NUMERIC"}
 
-EXPORTED = ["tn_plan_create", "tn_plan_destroy", "tn_plan_describe", "tn_plan_steps",
+EXPORTED = ["tn_plan_create", "tn_plan_create_sparse", "tn_plan_sparse_index", "tn_plan_destroy", "tn_plan_describe", "tn_plan_steps",
             "tn_plan_step_times", "tn_contract_slices", "tn_slice_partials", "tn_amplitudes", "tn_accumulator_set",
             "tn_reset", "tn_group_create", "tn_group_contract", "tn_group_describe",
             "tn_group_destroy", "tn_plan_step_features", "tn_plan_set_tile", "tn_plan_set_step_terms",
@@ -83,7 +83,7 @@ class tn_step_info(ctypes.Structure):
                 ("tile_n", ctypes.c_int32), ("a_contig", ctypes.c_int32),
                 ("b_contig", ctypes.c_int32), ("flops", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("tile", ctypes.c_int32), ("lds_copy", ctypes.c_int32),
-                ("terms", ctypes.c_int32)]
+                ("terms", ctypes.c_int32), ("merged_bits", ctypes.c_int32)]
 
 
 _P = ctypes.POINTER
@@ -93,6 +93,14 @@ _lib.tn_plan_create.argtypes = [_P(ctypes.c_void_p), ctypes.c_int32, _P(ctypes.c
                                 ctypes.c_int32, _P(ctypes.c_int32), ctypes.c_int32,
                                 _P(ctypes.c_int32), _P(tn_options)]
 _lib.tn_plan_create.restype = ctypes.c_int
+_lib.tn_plan_create_sparse.argtypes = [_P(ctypes.c_void_p), ctypes.c_int32, _P(ctypes.c_int32),
+                                       _P(_P(ctypes.c_int32)), _P(_P(ctypes.c_int64)),
+                                       _P(_P(ctypes.c_double)), ctypes.c_int32, _P(ctypes.c_int32),
+                                       ctypes.c_int32, _P(ctypes.c_int32), ctypes.c_int32,
+                                       _P(ctypes.c_int32), ctypes.c_int64, _P(ctypes.c_uint8), _P(tn_options)]
+_lib.tn_plan_create_sparse.restype = ctypes.c_int
+_lib.tn_plan_sparse_index.argtypes = [ctypes.c_void_p, _P(ctypes.c_int64), ctypes.c_int64]
+_lib.tn_plan_sparse_index.restype = ctypes.c_int
 _lib.tn_plan_destroy.argtypes = [ctypes.c_void_p]
 _lib.tn_plan_destroy.restype = None
 _lib.tn_plan_describe.argtypes = [ctypes.c_void_p, _P(tn_plan_info)]
@@ -189,8 +197,9 @@ def _stream_handle(stream):
 def tn_plan_create(tensors, labels, open_labels, path, sliced_labels=(), precision="c64",
                    mem_cap_elems: int = 0, stream=None, slice_batch: int = 0,
                    host_only: bool = False, split_policy: int = 0, record_steps: bool = False,
-                   tuning: int = 0, workspace=None):
-    """Create a plan; returns an opaque handle (int).  Leaves are copied."""
+                   tuning: int = 0, workspace=None, bitstrings=None):
+    """Create a plan; returns an opaque handle (int).  Leaves are copied.  With bitstrings
+    (uint8 [count, n_open]) a sparse-state plan (tn_plan_create_sparse)."""
     n = len(labels)
     ranks = (ctypes.c_int32 * n)(*[len(l) for l in labels])
     lab_arrays = [(ctypes.c_int32 * max(len(l), 1))(*l) for l in labels]
@@ -233,9 +242,19 @@ def tn_plan_create(tensors, labels, open_labels, path, sliced_labels=(), precisi
         opts.workspace = int(workspace.data_ptr())
         opts.workspace_bytes = int(workspace.numel() * workspace.element_size())
     handle = ctypes.c_void_p()
-    status = _lib.tn_plan_create(ctypes.byref(handle), n, ranks, lab_pp, ext_pp, data_pp,
-                                 len(open_labels), op, len(path), pa, len(sliced_labels), sl,
-                                 ctypes.byref(opts))
+    if bitstrings is None:
+        status = _lib.tn_plan_create(ctypes.byref(handle), n, ranks, lab_pp, ext_pp, data_pp,
+                                     len(open_labels), op, len(path), pa, len(sliced_labels), sl,
+                                     ctypes.byref(opts))
+    else:
+        bits = np.ascontiguousarray(np.asarray(bitstrings, dtype=np.uint8))
+        if bits.ndim != 2 or bits.shape[1] != len(open_labels):
+            raise ValueError("bitstrings must be (count, n_open)")
+        keep.append(bits)
+        status = _lib.tn_plan_create_sparse(ctypes.byref(handle), n, ranks, lab_pp, ext_pp, data_pp,
+                                            len(open_labels), op, len(path), pa, len(sliced_labels), sl,
+                                            bits.shape[0], bits.ctypes.data_as(_P(ctypes.c_uint8)),
+                                            ctypes.byref(opts))
     del keep
     _check(status)
     return handle.value
@@ -243,6 +262,12 @@ def tn_plan_create(tensors, labels, open_labels, path, sliced_labels=(), precisi
 
 def tn_plan_destroy(plan):
     _lib.tn_plan_destroy(plan)
+
+
+def tn_plan_sparse_index(plan, n_bitstrings: int) -> np.ndarray:
+    idx = np.zeros(max(int(n_bitstrings), 1), dtype=np.int64)
+    _check(_lib.tn_plan_sparse_index(plan, idx.ctypes.data_as(_P(ctypes.c_int64)), int(n_bitstrings)))
+    return idx[:n_bitstrings]
 
 
 def tn_plan_describe(plan) -> dict:
@@ -488,6 +513,7 @@ class Plan:
     package (loaded here and applied with tn_plan_tune_with_model)."""
 
     handle = None
+    sparse_index = None
 
     def __init__(self, tensors, labels, open_labels, path, sliced_labels=(), **kw):
         learned = kw.get("tuning", 0) == 2
@@ -495,6 +521,8 @@ class Plan:
             kw["tuning"] = 0
         self.workspace = kw.get("workspace")   # kept alive for the plan's lifetime
         self.handle = tn_plan_create(tensors, labels, open_labels, path, sliced_labels, **kw)
+        bits = kw.get("bitstrings")
+        self.sparse_index = None if bits is None else tn_plan_sparse_index(self.handle, len(bits))
         if learned:
             from .costmodel import CostModel
             with CostModel.load() as model:
@@ -526,13 +554,21 @@ class Plan:
         tn_contract_slices(self.handle, first, n)
 
     def amplitudes(self):
-        return tn_amplitudes(self.handle)
+        """(amplitudes, slices accumulated); for a sparse-state plan one amplitude per
+        bitstring, in the order given."""
+        amps, count = tn_amplitudes(self.handle)
+        if self.sparse_index is not None:
+            amps = amps[self.sparse_index]
+        return amps, count
 
     def step_times(self):
         return tn_plan_step_times(self.handle)
 
     def partials(self, ids):
-        return tn_slice_partials(self.handle, ids)
+        out = tn_slice_partials(self.handle, ids)
+        if self.sparse_index is not None:
+            out = out[:, self.sparse_index]
+        return out
 
     def reset(self):
         tn_reset(self.handle)

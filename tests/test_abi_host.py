@@ -219,3 +219,45 @@ def test_step_terms_setting_and_errors():
                  host_only=True) as q:
         with pytest.raises(tn.TnError):
             q.set_step_terms(0, 1)
+
+
+def _all_open_circuit(rows, cols, cycles, seed):
+    from tn_inputs.circuits import open_and_closed, random_circuit
+    from tn_inputs.network import circuit_network
+    circ = random_circuit(rows, cols, cycles, seed)
+    oq, _ = open_and_closed(circ.n_qubits, circ.n_qubits, seed)
+    net = circuit_network(circ, oq, {})
+    return circ, net, greedy_path(net.labels, net.open_labels, net.extents(), seed=seed)
+
+
+def test_sparse_plan_host_side():
+    """Sparse-state plans: one amplitude entry per distinct bitstring (padded to a power of
+    two), duplicates share their entry, merged bonds appear as table-indexed batch bits,
+    and malformed inputs are refused."""
+    from tn_inputs.circuits import sample_bitstrings
+    circ, net, path = _all_open_circuit(3, 4, 8, 31)
+    bits = sample_bitstrings(circ.n_qubits, 64, 5, duplicates=4)
+    distinct = len({tuple(r) for r in bits})
+    with tn.Plan(net.tensors, net.labels, net.open_labels, path, host_only=True, bitstrings=bits) as p:
+        n_amp = p.describe()["n_amplitudes"]
+        assert n_amp == 1 << (distinct - 1).bit_length()
+        idx = p.sparse_index
+        assert len(idx) == len(bits) and len(set(idx.tolist())) == distinct and idx.max() < n_amp
+        for i in range(len(bits)):
+            for j in range(i):
+                assert (idx[i] == idx[j]) == bool(np.array_equal(bits[i], bits[j]))
+        assert any(s["merged_bits"] >= 0 for s in p.steps())
+    bad = bits.copy()
+    bad[3, 2] = 2
+    with pytest.raises(tn.TnError):
+        tn.Plan(net.tensors, net.labels, net.open_labels, path, host_only=True, bitstrings=bad)
+    with pytest.raises(ValueError):
+        tn.Plan(net.tensors, net.labels, net.open_labels, path, host_only=True, bitstrings=bits[:, 1:])
+    with tn.Plan(net.tensors, net.labels, net.open_labels, path, host_only=True) as q:
+        with pytest.raises(tn.TnError):
+            tn.tn_plan_sparse_index(q.handle, len(bits))
+    # an open label of extent 4 is not a qubit bond
+    x = np.ones((4, 2), dtype=np.complex128)
+    y = np.ones((2,), dtype=np.complex128)
+    with pytest.raises(tn.TnError):
+        tn.Plan([x, y], [(0, 1), (1,)], (0,), [(0, 1)], host_only=True, bitstrings=np.zeros((2, 1), np.uint8))
