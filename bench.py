@@ -239,6 +239,49 @@ def run_mixed_precision(tn, torch, net, best, prec, sample_ids, n_slices):
     return out
 
 
+def run_sparse_state(tn, torch, configs, reps):
+    """Sparse-state contraction (Sec. 3.3): amplitudes of 4096 sampled bitstrings of the
+    30-qubit 12-cycle circuit with every qubit measured, in one contraction; split FP16
+    timed, complex64 for the speed ratio and the amplitude agreement."""
+    net, path, bits = configs.sparse_state_workload()
+    stream = torch.cuda.current_stream()
+    out = {"workload": "rqc30d12 circuit, all 30 qubits measured, 4096 uniform bitstrings, unsliced",
+           "bitstrings": int(len(bits))}
+    amps = {}
+    for prec in ("f16x3", "c64"):
+        with tn.Plan(net.tensors, net.labels, net.open_labels, path, precision=prec, stream=stream,
+                     bitstrings=bits, record_steps=True, tuning=2) as p:
+            info = p.describe()
+            st = p.steps()
+            flops = info["flops_invariant"] + info["flops_per_slice"]
+            p.contract()
+            torch.cuda.synchronize()
+            p.step_times()
+            p.reset()
+            n = reps if prec == "f16x3" else 1
+            s0 = torch.cuda.Event(enable_timing=True)
+            e0 = torch.cuda.Event(enable_timing=True)
+            s0.record(stream)
+            for _ in range(n):
+                p.contract()
+            e0.record(stream)
+            torch.cuda.synchronize()
+            ms = s0.elapsed_time(e0) / n
+            step_ms, _ = p.step_times()
+            a, c = p.amplitudes()
+            amps[prec] = a / c
+            merged_ms = sum(float(m) for m, s in zip(step_ms, st) if s["merged_bits"] >= 0)
+            out[prec] = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+                         "bitstrings_per_s": round(len(bits) / (ms * 1e-3), 1),
+                         "sparse_einsum_time_share": round(merged_ms / max(float(step_ms.sum()), 1e-9), 4)}
+            out["flops"] = flops
+            out["sparse_einsum_flops_share"] = round(sum(s["flops"] for s in st if s["merged_bits"] >= 0) / flops, 4)
+            out["max_intermediate"] = info["max_intermediate"]
+    out["speedup_vs_c64"] = round(out["c64"]["ms"] / out["f16x3"]["ms"], 3)
+    out["rel_l2_f16x3_vs_c64"] = float(np.linalg.norm(amps["f16x3"] - amps["c64"]) / np.linalg.norm(amps["c64"]))
+    return out
+
+
 def sample_slices(n_slices: int, count: int, seed: int = 137):
     """Seeded sample of distinct slice ids (sorted)."""
     rng = np.random.default_rng(seed)
@@ -394,6 +437,8 @@ def main():
                     help="uneven circuits in the batching-form measurement (0 = skip it)")
     ap.add_argument("--batching-workload", default="rqc40")
     ap.add_argument("--batching-slices", type=int, default=32)
+    ap.add_argument("--no-sparse-state", dest="sparse_state", action="store_false",
+                    help="skip the sparse-state (sampled bitstrings) measurement")
     ap.add_argument("--no-mixed-precision", dest="mixed_precision", action="store_false",
                     help="skip the per-step precision (single products on the costliest steps) sweep")
     ap.add_argument("--counter-run", action="store_true",
@@ -483,6 +528,10 @@ def main():
         out["slicing_choice"] = run_slicing_choice(tn, torch, configs, args.slicing_workload, head,
                                                    args.slicing_candidates, 2)
         log(f"  {out['slicing_choice']}")
+    if args.sparse_state:
+        log("sparse-state contraction: 4096 bitstrings of the 30-qubit 12-cycle circuit")
+        out["sparse_state"] = run_sparse_state(tn, torch, configs, 2)
+        log(f"  {out['sparse_state']}")
     mixed = None
     if args.mixed_precision and head != "c64":
         log(f"per-step precision: single products on the top-k split steps, {head}")

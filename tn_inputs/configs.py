@@ -87,3 +87,23 @@ def uneven_circuits(n: int, seed: int = 1040, open_k: int = 4, cap_log2: int = 2
         best = find_path(net, cap_log2=cap_log2, trials=trials, seed=seed + i)
         out.append((net, best))
     return out
+
+
+@lru_cache(maxsize=None)
+def sparse_state_workload(count: int = 4096, seed: int = 7):
+    """The sparse-state workload (Sec. 3.3): the 30-qubit 5x6 lattice circuit of rqc30d12
+    (12 cycles, seed 130) with every qubit measured, `count` uniformly random bitstrings
+    (seed `seed`; stand-ins for experimental samples), and a randomised greedy path whose
+    sizes count merged open bonds by their distinct bitstring restrictions (seed 1302,
+    unsliced; largest intermediate 2^32 elements for the default bitstrings).
+
+    Returns (network, path, bitstrings)."""
+    from .circuits import sample_bitstrings
+    from .paths import greedy_path
+    w = WORKLOADS["rqc30d12"]
+    circ = random_circuit(w.rows, w.cols, w.cycles, w.circuit_seed)
+    oq, _ = open_and_closed(circ.n_qubits, circ.n_qubits, w.closed_seed)
+    net = circuit_network(circ, oq, {})
+    bits = sample_bitstrings(circ.n_qubits, count, seed)
+    path = greedy_path(net.labels, net.open_labels, net.extents(), seed=1302, temperature=0.3, bitstrings=bits)
+    return net, path, bits

@@ -79,8 +79,12 @@ def path_cost(labels, open_labels, extents, path, sliced=()) -> dict:
 
 
 def greedy_path(labels, open_labels, extents, seed: int = 0, temperature: float = 0.0,
-                sliced=()) -> list:
-    """Randomised greedy pairwise path (memory-reduction score, Gumbel noise)."""
+                sliced=(), bitstrings=None) -> list:
+    """Randomised greedy pairwise path (memory-reduction score, Gumbel noise).
+
+    With bitstrings (a sparse state, one column per open label), a tensor's open labels
+    count as one merged bond over the distinct restrictions of the bitstrings to them
+    (Sec. 3.3) instead of 2 per label."""
     rng = np.random.default_rng(seed)
     lg = _log2ext(extents)
     sliced = set(sliced)
@@ -90,9 +94,28 @@ def greedy_path(labels, open_labels, extents, seed: int = 0, temperature: float 
     for i, s in live.items():
         for l in s:
             where[l].add(i)
+    col = {l: c for c, l in enumerate(open_labels)}
+    bkeys = None
+    if bitstrings is not None:
+        X = np.asarray(bitstrings, dtype=np.uint64)
+        bkeys = (X << np.arange(X.shape[1], dtype=np.uint64)).sum(axis=1, dtype=np.uint64)
+    distinct = {}
 
     def size(s):
-        return sum(lg[l] for l in s)
+        if bkeys is None:
+            return sum(lg[l] for l in s)
+        mask = 0
+        closed = 0
+        for l in s:
+            if l in col:
+                mask |= 1 << col[l]
+            else:
+                closed += lg[l]
+        if mask == 0:
+            return closed
+        if mask not in distinct:
+            distinct[mask] = math.log2(len(np.unique(bkeys & np.uint64(mask))))
+        return closed + distinct[mask]
 
     def result(i, j):
         a, b = live[i], live[j]
