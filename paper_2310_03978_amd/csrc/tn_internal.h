@@ -82,6 +82,7 @@ struct GettArgs {
   const int64_t* tab_a;
   const int64_t* tab_b;
   int32_t tab_bits;
+  int32_t dot;                  // small steps: one block per output element, K split over the block
 };
 
 // Storage formats of an intermediate.  TN_FMT_SPLIT keeps, per complex element,

@@ -278,6 +278,84 @@ __global__ __launch_bounds__(256) void k_gett_small(const GettDesc* __restrict__
   gett_small_block(d, g, blockIdx.x, red);
 }
 
+// Steps with (almost) no free output extent and a long K (batched dot products, such as
+// the last sparse einsum of a sparse state): one block per output element, the block's
+// threads split K (k = 256 j + t) and add their partial sums in a fixed tree.
+__global__ __launch_bounds__(256) void k_gett_dot(const GettDesc* __restrict__ d, GettArgs g) {
+  __shared__ float2 part[256];
+  __shared__ int64_t hd_a[TN_MAXK], hd_b[TN_MAXK];
+  const int t = threadIdx.x;
+  const int nbb = d->own_bb + g.chunk_bits;
+  const int cbits = d->c_nbits + g.chunk_bits;
+  const int64_t e = blockIdx.x;
+  uint64_t bidx = 0, m = 0, n = 0;
+  for (int p = 0; p < cbits; ++p) {
+    if ((e >> p) & 1) {
+      const int code = d->c_pos[p];
+      const int role = code >> 8, idx = code & 255;
+      if (role == 0) bidx |= 1ull << idx;
+      else if (role == 1) m |= 1ull << idx;
+      else n |= 1ull << idx;
+    }
+  }
+  const int sl = (int)(bidx >> d->own_bb);
+  const Scales sc = step_scales(d, g, sl);
+  int64_t oa = bits_offset(bidx, d->a_b, nbb) + bits_offset(m, d->a_m, d->mb);
+  int64_t ob = bits_offset(bidx, d->b_b, nbb) + bits_offset(n, d->b_n, d->nb);
+  if (g.tab_bits) {
+    const uint64_t f = bidx & ((1ull << g.tab_bits) - 1);
+    oa += g.tab_a[f];
+    ob += g.tab_b[f];
+  }
+  // k bits 0..7 from the thread, bits 8.. from the iteration j (offsets advanced with
+  // per-bit deltas: going from j to j + 1 sets bit ctz(~j) and clears the bits below it)
+  const int lob = d->kb < 8 ? d->kb : 8, hib = d->kb - lob;
+  if (t < hib) {
+    int64_t sa = 0, sb = 0;
+    for (int i = 0; i < t; ++i) {
+      sa += d->a_k[lob + i];
+      sb += d->b_k[lob + i];
+    }
+    hd_a[t] = d->a_k[lob + t] - sa;
+    hd_b[t] = d->b_k[lob + t] - sb;
+  }
+  __syncthreads();
+  float cr = 0.f, ci = 0.f;
+  if (t < (1 << lob)) {
+    const float2* A = reinterpret_cast<const float2*>(g.A);
+    const float2* B = reinterpret_cast<const float2*>(g.B);
+    int64_t ka = oa + bits_offset((uint64_t)t, d->a_k, lob);
+    int64_t kb = ob + bits_offset((uint64_t)t, d->b_k, lob);
+    const int64_t nj = (int64_t)1 << hib;
+    for (int64_t j = 0; j < nj; ++j) {
+      const float2 a = A[ka];
+      const float2 b = B[kb];
+      const float ar = a.x * sc.fa, ai = a.y * sc.fa, br = b.x * sc.fb, bi = b.y * sc.fb;
+      cr = fmaf(ar, br, cr);
+      cr = fmaf(-ai, bi, cr);
+      ci = fmaf(ar, bi, ci);
+      ci = fmaf(ai, br, ci);
+      if (j + 1 < nj) {
+        const int tz = __builtin_ctzll(~(uint64_t)j);
+        ka += hd_a[tz];
+        kb += hd_b[tz];
+      }
+    }
+  }
+  part[t] = make_float2(cr, ci);
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) part[t] = make_float2(part[t].x + part[t + w].x, part[t].y + part[t + w].y);
+    __syncthreads();
+  }
+  if (t == 0) {
+    const uint32_t mx = store_c(g.C, e, part[0], g, sc.ft);
+    const uint64_t own_mask = (1ull << d->own_bb) - 1;
+    if (g.scale_mode && m == 0 && n == 0 && (bidx & own_mask) == 0) write_exp(g, sl, sc);
+    if (g.maxC) atomicMax(g.maxC + (g.c_ps ? sl : 0), mx);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Tiled MFMA kernel.
 // ---------------------------------------------------------------------------
@@ -1074,7 +1152,10 @@ hipError_t tn_launch_gett(int kind, int tile, const GettDesc* d, const GettArgs&
   if (blocks <= 0) return hipSuccess;
   switch (kind) {
     case TN_K_SMALL:
-      hipLaunchKernelGGL(k_gett_small, dim3((unsigned)blocks), dim3(256), 0, s, d, g);
+      if (g.dot)
+        hipLaunchKernelGGL(k_gett_dot, dim3((unsigned)blocks), dim3(256), 0, s, d, g);
+      else
+        hipLaunchKernelGGL(k_gett_small, dim3((unsigned)blocks), dim3(256), 0, s, d, g);
       return hipGetLastError();
     case TN_K_MFMA_F32: return launch_mfma_tile<0>(tile, d, g, blocks, s);
     case TN_K_MFMA_F16X3: return launch_mfma_tile<1>(tile, d, g, blocks, s);

@@ -103,6 +103,7 @@ struct Step {
   int a_contig = 0, b_contig = 0;
   bool dma = false;                  // split tile 256x128 fed by global -> LDS copies
   int terms = 3;                     // split steps: products per complex multiply-add term (3 or 1)
+  bool dot = false;                  // small steps with <= 4 outputs per batch and long K: block per output
   double flops = 0, bytes = 0;
   int64_t scratch_elems = 0;         // split-K partials (elements)
   // sparse einsum (Sec. 3.3): the result's merged bond `tab_label` is the step's lowest
@@ -400,8 +401,12 @@ void choose_kernel(tn_plan_s* p, Step& st) {
   const int bbits = (int)st.bb.size() + (st.per_slice ? p->s_bits : 0);
   const int mb = (int)st.mb.size(), nb = (int)st.nb.size(), kb = (int)st.kb.size();
   const bool small = (kb <= 6 && bbits + mb + nb <= 14) || (bbits + mb + nb + kb <= 16);
-  if (small) {
+  // batched dot products (at most 4 output elements per batch, K >= 2^10): an MFMA tile
+  // would be almost empty; one block per output element splits K instead
+  const bool dot = mb + nb <= 2 && kb >= 10;
+  if (small || dot) {
     st.kernel = TN_K_SMALL;
+    st.dot = dot;
     st.splits = 1;
     return;
   }
@@ -1165,6 +1170,7 @@ struct Launch {
   int64_t elems = 0;       // element-wise kinds: elements covered
   int64_t blocks = 0;      // MFMA kinds: tile blocks
   int64_t nblocks(int threads) const {
+    if (kind == TN_K_SMALL && g.dot) return elems;   // one block per output element
     return (kind == TN_K_MFMA_F32 || kind == TN_K_MFMA_F16X3 || kind == TN_K_MFMA_BF16X3)
                ? blocks
                : (elems + threads - 1) / threads;
@@ -1225,6 +1231,7 @@ void step_launches(const tn_plan_s* p, const Step& st, const GettDesc* d, int s,
   L.tile = st.tile;
   const int64_t c_total = int64_t(1) << (C.bits.size() + g.chunk_bits);
   if (st.kernel == TN_K_SMALL) {
+    g.dot = st.dot ? 1 : 0;
     L.elems = c_total;
     out.push_back(L);
     return;
@@ -2131,7 +2138,9 @@ tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_
   const GettDesc* d = dd;
   if (!r) {
     if (st.kernel == TN_K_SMALL) {
-      r = check(tn_launch_gett(TN_K_SMALL, 0, d, g, ((int64_t(1) << (bb + mb + nb)) + 255) / 256, s), "gemm");
+      g.dot = st.dot ? 1 : 0;
+      const int64_t outs = int64_t(1) << (bb + mb + nb);
+      r = check(tn_launch_gett(TN_K_SMALL, 0, d, g, st.dot ? outs : (outs + 255) / 256, s), "gemm");
     } else {
       g.splits = st.splits;
       g.k_split_bits = st.k_split_bits;

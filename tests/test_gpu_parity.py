@@ -38,7 +38,8 @@ def _dev(x):
 @pytest.mark.parametrize("prec", ["c64", "f16x3", "bf16x3"])
 @pytest.mark.parametrize("b,m,n,k", [(1, 128, 64, 16), (2, 256, 128, 64), (1, 8, 4, 2),
                                      (1, 1, 1, 1), (4, 32, 16, 512),
-                                     (1, 64, 32, 8192), (1, 512, 256, 256), (2, 16, 128, 32)])
+                                     (1, 64, 32, 8192), (1, 512, 256, 256), (2, 16, 128, 32),
+                                     (256, 1, 1, 4096), (4, 2, 2, 65536), (1, 1, 2, 1024)])
 def test_gemm_matches_numpy(prec, b, m, n, k):
     print(f"gemm {prec} b={b} m={m} n={n} k={k}", flush=True)
     rng = np.random.default_rng(b * 7 + m + n + k)
