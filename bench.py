@@ -282,6 +282,45 @@ def run_sparse_state(tn, torch, configs, reps):
     return out
 
 
+def run_permute(tn, torch, reps):
+    """HBM bandwidth of the LDS-staged permutation kernel (Sec. 2.4 transposes) on 2^28
+    complex64 elements (2 GiB read, 2 GiB written): a plain copy, a 2-D transpose, a rank-5
+    transpose and a random permutation of 28 bits; bytes = 16 per element.  Each call is
+    timed with HIP events on the stream it runs on (descriptor upload + kernel), median of
+    reps calls; torch's own device copy of the same bytes is timed the same way."""
+    n_bits = 28
+    x = torch.randn(1 << n_bits, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    rng = np.random.default_rng(11)
+    cases = {"copy": ([1 << 14, 1 << 14], [0, 1]), "transpose_2d": ([1 << 14, 1 << 14], [1, 0]),
+             "transpose_rank5": ([64, 64, 64, 32, 32], [3, 0, 4, 2, 1]),
+             "random_bit_permutation": ([2] * n_bits, [int(v) for v in rng.permutation(n_bits)])}
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()                                   # warm-up
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+
+    out = {}
+    for name, (shape, perm) in cases.items():
+        xs = x.view(*shape)
+        ms = timed(lambda: tn.tn_permute(xs, perm, y, stream))
+        gbs = 16.0 * (1 << n_bits) / (ms * 1e-3) / 1e9
+        out[name] = {"ms": round(ms, 3), "GB/s": round(gbs, 1), "frac_of_8TB/s": round(gbs / 8000.0, 3)}
+    ms = timed(lambda: y.copy_(x))
+    out["torch_copy_reference"] = {"ms": round(ms, 3), "GB/s": round(16.0 * (1 << n_bits) / (ms * 1e-3) / 1e9, 1)}
+    del x, y
+    return out
+
+
 def sample_slices(n_slices: int, count: int, seed: int = 137):
     """Seeded sample of distinct slice ids (sorted)."""
     rng = np.random.default_rng(seed)
@@ -437,6 +476,10 @@ def main():
                     help="uneven circuits in the batching-form measurement (0 = skip it)")
     ap.add_argument("--batching-workload", default="rqc40")
     ap.add_argument("--batching-slices", type=int, default=32)
+    ap.add_argument("--no-permute", dest="permute", action="store_false",
+                    help="skip the permutation-kernel bandwidth measurement")
+    ap.add_argument("--permute-only", action="store_true",
+                    help="only the permutation-kernel bandwidth measurement (one JSON line)")
     ap.add_argument("--no-sparse-state", dest="sparse_state", action="store_false",
                     help="skip the sparse-state (sampled bitstrings) measurement")
     ap.add_argument("--no-mixed-precision", dest="mixed_precision", action="store_false",
@@ -455,6 +498,9 @@ def main():
     torch.cuda.set_device(0)
     from paper_2310_03978_amd import tn
     from tn_inputs import configs
+    if args.permute_only:
+        print(json.dumps({"permute": run_permute(tn, torch, max(args.steps, 5))}), flush=True)
+        return
 
     t0 = time.perf_counter()
     circ, net, best = configs.build(args.workload)
@@ -528,6 +574,10 @@ def main():
         out["slicing_choice"] = run_slicing_choice(tn, torch, configs, args.slicing_workload, head,
                                                    args.slicing_candidates, 2)
         log(f"  {out['slicing_choice']}")
+    if args.permute:
+        log("permutation kernel bandwidth: 2^28 complex64")
+        out["permute"] = run_permute(tn, torch, 5)
+        log(f"  {out['permute']}")
     if args.sparse_state:
         log("sparse-state contraction: 4096 bitstrings of the 30-qubit 12-cycle circuit")
         out["sparse_state"] = run_sparse_state(tn, torch, configs, 2)

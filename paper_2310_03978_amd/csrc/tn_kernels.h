@@ -29,17 +29,27 @@ enum {
 
 // Permutation of one bit-indexed tensor: the block owns the local bits
 // (enumerated by ein in input-stride order and by eout in output-stride order,
-// row = LDS position increment); block index bits select the high bits.
+// row = LDS position increment, combined by XOR); block index bits select the
+// high bits.  pairs = 1: 16-byte accesses of two elements along the lowest input
+// and output bits (needs 16-byte aligned buffers, the local bit of input stride 1
+// at LDS position 1, and every other row even).
 struct PermDesc {
   int32_t nh;
   int32_t pad_;
   int64_t h_in[64];
   int64_t h_out[64];
   TileEnum ein, eout;
+  // per iteration of a thread (the enumeration bits above the pair bit, if any, and
+  // the 8 thread bits): offsets and LDS rows in input and output order
+  int32_t iters;
+  int32_t pad2_;
+  int64_t it_in_off[1 << (PERM_LOCAL_MAX - 8)], it_out_off[1 << (PERM_LOCAL_MAX - 8)];
+  int32_t it_in_row[1 << (PERM_LOCAL_MAX - 8)], it_out_row[1 << (PERM_LOCAL_MAX - 8)];
 };
 
 hipError_t tn_launch_gett(int kind, int tile, const GettDesc* d, const GettArgs& g, int64_t blocks, hipStream_t s);
-hipError_t tn_launch_permute(const PermDesc* p, int64_t blocks, const void* in, void* out, hipStream_t s);
+hipError_t tn_launch_permute(const PermDesc* p, int pairs, int64_t blocks, const void* in, void* out,
+                             hipStream_t s);
 hipError_t tn_launch_slice_reduce(const ReduceArgs& r, hipStream_t s);
 hipError_t tn_launch_absmax(const void* x, int64_t n, uint32_t* dst, hipStream_t s);
 hipError_t tn_launch_fill_u32(void* p, uint32_t v, int64_t n, hipStream_t s);

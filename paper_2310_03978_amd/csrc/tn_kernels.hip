@@ -34,6 +34,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
+#include <type_traits>
 
 #include "tn_internal.h"
 #include "tn_kernels.h"
@@ -1019,10 +1020,35 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const GettDesc* __restric
 // ---------------------------------------------------------------------------
 // Permutation: the block owns the local bits (low input bits U low output bits);
 // loads follow input order, stores follow output order, staged through LDS.
+// The row field of a local bit is its LDS position increment, combined by XOR
+// (the planner folds a bank swizzle into them).  With V = 2 every access moves
+// two elements along the lowest input (load) or output (store) bit: 16 bytes.
 // ---------------------------------------------------------------------------
+struct PermPart {
+  int64_t off;
+  int row;
+};
+
+// bits first .. first + count - 1 of an enumeration, selected by the bits of v
+__device__ __forceinline__ PermPart perm_part(const TileEnum& en, int first, int count, int v) {
+  PermPart r{0, 0};
+  const int last = en.n < first + count ? en.n : first + count;
+  for (int j = first; j < last; ++j)
+    if ((v >> (j - first)) & 1) {
+      r.off += en.stride[j];
+      r.row ^= en.row[j];
+    }
+  return r;
+}
+
+template <int V>
 __global__ __launch_bounds__(256) void k_permute(const PermDesc* __restrict__ p, const float2* __restrict__ in,
                                                  float2* __restrict__ out) {
-  __shared__ float2 tile[1 << PERM_LOCAL_MAX];
+  using vec = typename std::conditional<V == 2, float4, float2>::type;
+  constexpr int VB = V == 2 ? 1 : 0;                              // enumeration bits inside one access
+  constexpr int MAXIT = (1 << (PERM_LOCAL_MAX - VB)) >> 8;
+  __shared__ float4 tile4[1 << (PERM_LOCAL_MAX - 1)];
+  float2* tile = reinterpret_cast<float2*>(tile4);
   const int t = threadIdx.x;
   const uint64_t bid = blockIdx.x;
   int64_t ib = 0, ob = 0;
@@ -1031,23 +1057,47 @@ __global__ __launch_bounds__(256) void k_permute(const PermDesc* __restrict__ p,
       ib += p->h_in[j];
       ob += p->h_out[j];
     }
-  const int n = p->ein.n;
-  const int elems = 1 << n;
-  const ThreadEnum ti = thread_part<8>(p->ein, t);
-  const ThreadEnum to = thread_part<8>(p->eout, t);
-  const int iters = elems > 256 ? elems >> 8 : 1;
-  for (int it = 0; it < iters; ++it) {
-    if (t < elems) {
-      const ThreadEnum ip = iter_part<8>(p->ein, it);
-      tile[ti.row + ip.row] = in[ib + ti.off + ip.off];
+  const PermPart ti = perm_part(p->ein, VB, 8, t);
+  const PermPart to = perm_part(p->eout, VB, 8, t);
+  const float2* src = in + ib + ti.off;
+  float2* dst = out + ob + to.off;
+  const int pair = p->eout.row[0];   // LDS offset of the second element of an output pair
+  auto gather = [&](int r) -> vec {
+    if constexpr (V == 2) {
+      if (pair == 1) return tile4[r >> 1];
+      const float2 x0 = tile[r], x1 = tile[r ^ pair];
+      return make_float4(x0.x, x0.y, x1.x, x1.y);
+    } else {
+      return tile[r];
     }
-  }
-  __syncthreads();
-  for (int it = 0; it < iters; ++it) {
-    if (t < elems) {
-      const ThreadEnum ip = iter_part<8>(p->eout, it);
-      out[ob + to.off + ip.off] = tile[to.row + ip.row];
+  };
+  if (p->iters == MAXIT) {
+    // full tile, every thread busy: all loads of the thread in flight together
+    vec v[MAXIT];
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) v[it] = *reinterpret_cast<const vec*>(src + p->it_in_off[it]);
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) *reinterpret_cast<vec*>(tile + (ti.row ^ p->it_in_row[it])) = v[it];
+    __syncthreads();
+    if (V == 1 || pair == 1) {
+#pragma unroll
+      for (int it = 0; it < MAXIT; ++it)
+        *reinterpret_cast<vec*>(dst + p->it_out_off[it]) =
+            *reinterpret_cast<const vec*>(tile + (to.row ^ p->it_out_row[it]));
+    } else {
+#pragma unroll
+      for (int it = 0; it < MAXIT; ++it) v[it] = gather(to.row ^ p->it_out_row[it]);
+#pragma unroll
+      for (int it = 0; it < MAXIT; ++it) *reinterpret_cast<vec*>(dst + p->it_out_off[it]) = v[it];
     }
+  } else {
+    const bool active = t < (1 << (p->ein.n - VB));
+    for (int it = 0; it < p->iters; ++it)
+      if (active) *reinterpret_cast<vec*>(tile + (ti.row ^ p->it_in_row[it])) =
+                      *reinterpret_cast<const vec*>(src + p->it_in_off[it]);
+    __syncthreads();
+    for (int it = 0; it < p->iters; ++it)
+      if (active) *reinterpret_cast<vec*>(dst + p->it_out_off[it]) = gather(to.row ^ p->it_out_row[it]);
   }
 }
 
@@ -1167,9 +1217,14 @@ hipError_t tn_launch_gett(int kind, int tile, const GettDesc* d, const GettArgs&
   }
 }
 
-hipError_t tn_launch_permute(const PermDesc* p, int64_t blocks, const void* in, void* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)blocks), dim3(256), 0, s, p, reinterpret_cast<const float2*>(in),
-                     reinterpret_cast<float2*>(out));
+hipError_t tn_launch_permute(const PermDesc* p, int pairs, int64_t blocks, const void* in, void* out,
+                             hipStream_t s) {
+  if (pairs)
+    hipLaunchKernelGGL(k_permute<2>, dim3((unsigned)blocks), dim3(256), 0, s, p, reinterpret_cast<const float2*>(in),
+                       reinterpret_cast<float2*>(out));
+  else
+    hipLaunchKernelGGL(k_permute<1>, dim3((unsigned)blocks), dim3(256), 0, s, p, reinterpret_cast<const float2*>(in),
+                       reinterpret_cast<float2*>(out));
   return hipGetLastError();
 }
 

@@ -551,10 +551,19 @@ tn_status permute_bits(const std::vector<int>& in_pos, const std::vector<int>& o
     if (best < 0) break;
     local.push_back(best);
   }
+  // LDS position r holds the local bit of the r-th lowest input position, so a load
+  // of two elements along input stride 1 fills two adjacent positions.  Positions
+  // 5 and up also flip some of bits 1..4 (an XOR swizzle that keeps position pairs
+  // together): output-order reads of a transpose then spread over the LDS banks
+  // (at most 2-way conflicts for 2-D transposes and random bit permutations of
+  // 28 bits, by enumeration of the access pattern, against 32-way unswizzled).
+  std::sort(local.begin(), local.end(), [&](int a, int b) { return in_pos[a] < in_pos[b]; });
+  static const int kSwizzle[PERM_LOCAL_MAX - 5] = {28, 30, 4, 26, 24, 18, 14};
   std::vector<std::pair<int64_t, std::pair<int, int>>> vi, vo;
   for (size_t r = 0; r < local.size(); ++r) {
-    vi.push_back({int64_t(1) << in_pos[local[r]], {1 << r, 0}});
-    vo.push_back({int64_t(1) << out_pos[local[r]], {1 << r, 0}});
+    const int row = (1 << r) ^ (r >= 5 ? kSwizzle[r - 5] : 0);
+    vi.push_back({int64_t(1) << in_pos[local[r]], {row, 0}});
+    vo.push_back({int64_t(1) << out_pos[local[r]], {row, 0}});
   }
   fill_enum(pd.ein, vi);
   fill_enum(pd.eout, vo);
@@ -566,9 +575,22 @@ tn_status permute_bits(const std::vector<int>& in_pos, const std::vector<int>& o
     ++h;
   }
   pd.nh = h;
+  // 16-byte accesses need aligned buffers (the lowest input and output bits are local)
+  const int pairs = n >= 1 && ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+  const int first = 8 + pairs;   // enumeration bits below: the pair bit and the thread bits
+  const int nl = pd.ein.n;
+  pd.iters = nl > first ? 1 << (nl - first) : 1;
+  for (int it = 0; it < pd.iters; ++it)
+    for (int j = first; j < nl; ++j)
+      if ((it >> (j - first)) & 1) {
+        pd.it_in_off[it] += pd.ein.stride[j];
+        pd.it_in_row[it] ^= pd.ein.row[j];
+        pd.it_out_off[it] += pd.eout.stride[j];
+        pd.it_out_row[it] ^= pd.eout.row[j];
+      }
   tn_status st = check(hipMemcpyAsync(d_desc_scratch, &pd, sizeof(pd), hipMemcpyHostToDevice, s), "permute desc");
   if (st) return st;
-  st = check(tn_launch_permute(d_desc_scratch, int64_t(1) << h, in, out, s), "permute launch");
+  st = check(tn_launch_permute(d_desc_scratch, pairs, int64_t(1) << h, in, out, s), "permute launch");
   if (st) return st;
   return check(hipStreamSynchronize(s), "permute sync");
 }

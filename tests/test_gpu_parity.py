@@ -54,7 +54,10 @@ def test_gemm_matches_numpy(prec, b, m, n, k):
 
 @pytest.mark.parametrize("shape,perm", [((2, 4, 8), (2, 0, 1)), ((64, 32), (1, 0)),
                                         ((2,) * 14, tuple(np.random.default_rng(1).permutation(14))),
-                                        ((4, 1, 256, 8, 2), (3, 1, 4, 0, 2)), ((), ())])
+                                        ((4, 1, 256, 8, 2), (3, 1, 4, 0, 2)), ((), ()), ((2,), (0,)),
+                                        ((1024, 2048), (1, 0)), ((1 << 20,), (0,)),
+                                        ((2,) * 22, tuple(np.random.default_rng(2).permutation(22))),
+                                        ((2, 512, 4, 256), (2, 0, 3, 1)), ((8, 8, 8, 8, 8, 8, 8), (6, 5, 4, 3, 2, 1, 0))])
 def test_permute_bit_exact(shape, perm):
     print(f"permute {shape} {perm}", flush=True)
     rng = np.random.default_rng(len(shape))
@@ -64,6 +67,24 @@ def test_permute_bit_exact(shape, perm):
     tn.tn_permute(xd, list(perm), out)
     ref = np.transpose(x, perm).reshape(-1) if shape else x.reshape(-1)
     assert np.array_equal(out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("shift_in,shift_out", [(1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("shape,perm", [((64, 32), (1, 0)), ((2,) * 18, tuple(np.random.default_rng(5).permutation(18)))])
+def test_permute_unaligned_buffers(shape, perm, shift_in, shift_out):
+    # buffers 8-byte but not 16-byte aligned: element-wide accesses instead of pairs
+    print(f"permute unaligned {shape} {perm} {shift_in} {shift_out}", flush=True)
+    rng = np.random.default_rng(9)
+    x = _crandn(rng, shape)
+    n = x.size
+    xin = torch.zeros(n + 1, dtype=torch.complex64, device="cuda")
+    xin[shift_in:shift_in + n] = _dev(x.reshape(-1))
+    out = torch.zeros(n + 1, dtype=torch.complex64, device="cuda")
+    tn.tn_permute(xin[shift_in:shift_in + n].view(shape), list(perm), out[shift_out:shift_out + n])
+    ref = np.transpose(x, perm).reshape(-1)
+    got = out.cpu().numpy()
+    assert np.array_equal(got[shift_out:shift_out + n], ref)
+    assert got[0 if shift_out else n] == 0   # nothing written outside the output
 
 
 def _gpu_amplitudes(net, path, sliced=(), prec="c64", **kw):
