@@ -877,70 +877,81 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
   // [32, 64); blocks 2, 3: their imaginary parts
   const int half = lane >> 5;
 
+  // Software pipeline over half-stages (8 complex k): the fragments of the next
+  // half-stage are read from LDS while the products of the current one run, so
+  // the MFMA pipe does not wait for LDS latency after each barrier.  The barrier
+  // sits between the two halves of a stage: by then this wave's reads of the
+  // stage are complete (the buffer may be refilled with stage it + 3) and the
+  // next stage's copies have landed (its first half may be read).
+  auto read_frags = [&](const char* st, int ks, u32x4 (&xa)[2][2], u32x4 (&xb)[2][2]) {
+    const int s0 = ks * 4 + half * 2;      // hi slot of this lane's 4 k (lo slot: s0 + 1)
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi) {
+      const int r = wm * 64 + mi * 32 + (lane & 31);
+      xa[mi][0] = *reinterpret_cast<const u32x4*>(st + r * 128 + ((s0 ^ dma_swz(r)) << 4));
+      xa[mi][1] = *reinterpret_cast<const u32x4*>(st + r * 128 + (((s0 + 1) ^ dma_swz(r)) << 4));
+    }
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      const int n = wn * 64 + nb * 32 + (lane & 31);
+      const char* bp = st + DMA_A_BYTES + n * 128;
+      xb[nb][0] = *reinterpret_cast<const u32x4*>(bp + ((s0 ^ dma_swz(n)) << 4));
+      xb[nb][1] = *reinterpret_cast<const u32x4*>(bp + (((s0 + 1) ^ dma_swz(n)) << 4));
+    }
+  };
+  // block ni < 2: (Br, -Bi) of column block ni; ni >= 2: (Bi, Br) of block ni - 2
+  auto expand = [&](const u32x4 (&x)[2][2], int ni, int hl) {
+    const u32x4& v = x[ni & 1][hl];
+    if (ni < 2) return u32x4{v.x ^ 0x80000000u, v.y ^ 0x80000000u, v.z ^ 0x80000000u, v.w ^ 0x80000000u};
+    return u32x4{__builtin_amdgcn_alignbit(v.x, v.x, 16), __builtin_amdgcn_alignbit(v.y, v.y, 16),
+                 __builtin_amdgcn_alignbit(v.z, v.z, 16), __builtin_amdgcn_alignbit(v.w, v.w, 16)};
+  };
+  // hi x hi, hi x lo, lo x hi (slot 2q: hi quad, slot 2q + 1: lo quad), column-major
+  // over the wave tile (dependent products on one accumulator stay 8 MFMAs apart)
+  auto products = [&](const u32x4 (&xa)[2][2], const u32x4 (&xb)[2][2]) {
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) {
+      const u32x4 bh = expand(xb, ni, 0);
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(xa[mi][0], bh, acc[mi][ni]);
+    }
+    if (g.terms == 1) return;   // hi x hi only
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) {
+      const u32x4 bl = expand(xb, ni, 1);
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(xa[mi][0], bl, acc[mi][ni]);
+    }
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) {
+      const u32x4 bh = expand(xb, ni, 0);
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(xa[mi][1], bh, acc[mi][ni]);
+    }
+  };
+
   issue();
   if (n_iters > 1) issue();
+  if (n_iters > 1) wait_vmcnt<6>();   // stage 0 landed, stage 1 may fly
+  else wait_vmcnt<0>();
+  asm volatile("s_barrier" ::: "memory");
+  if (n_iters > 2) issue();
+  u32x4 fa[2][2], fb[2][2], ga[2][2], gb[2][2];
+  read_frags(lds, 0, fa, fb);
   for (int64_t it = 0; it < n_iters; ++it) {
-    if (it + 1 < n_iters) wait_vmcnt<6>();   // this stage's 6 copies are done, the next stage's may fly
-    else wait_vmcnt<0>();
-    // Every wave's copies of this stage have landed and every wave is done reading
-    // stage it - 1 (its reads completed before its last MFMA of that stage).  A plain
-    // barrier with a compiler memory clobber: a fence here would also wait for the
-    // copies of the next stage.
-    asm volatile("s_barrier" ::: "memory");
-    if (it + 2 < n_iters) issue();
     const char* st = lds + (int)(it % DMA_STAGES) * DMA_STAGE_BYTES;
-#pragma unroll 1
-    for (int ks = 0; ks < 2; ++ks) {
-      const int s0 = ks * 4 + half * 2;      // hi slot of this lane's 4 k (lo slot: s0 + 1)
-      // all LDS reads of the K step first (A, then B column by column), so that the
-      // products of the first columns can start while later columns are in flight
-      u32x4 xa[2][2], xb[2][2];
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi) {
-        const int r = wm * 64 + mi * 32 + (lane & 31);
-        xa[mi][0] = *reinterpret_cast<const u32x4*>(st + r * 128 + ((s0 ^ dma_swz(r)) << 4));
-        xa[mi][1] = *reinterpret_cast<const u32x4*>(st + r * 128 + (((s0 + 1) ^ dma_swz(r)) << 4));
-      }
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        const int n = wn * 64 + nb * 32 + (lane & 31);
-        const char* bp = st + DMA_A_BYTES + n * 128;
-        xb[nb][0] = *reinterpret_cast<const u32x4*>(bp + ((s0 ^ dma_swz(n)) << 4));
-        xb[nb][1] = *reinterpret_cast<const u32x4*>(bp + (((s0 + 1) ^ dma_swz(n)) << 4));
-      }
-      u32x4 ah[2], al[2], bh[4], bl[4];
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi) {   // slot 2q: hi quad, slot 2q + 1: lo quad
-        ah[mi] = xa[mi][0];
-        al[mi] = xa[mi][1];
-      }
-      // block ni < 2: (Br, -Bi) of column block ni; ni >= 2: (Bi, Br) of block ni - 2
-      auto expand = [&](const u32x4 (&x)[2][2], int ni, int hl) {
-        const u32x4& v = x[ni & 1][hl];
-        if (ni < 2) return u32x4{v.x ^ 0x80000000u, v.y ^ 0x80000000u, v.z ^ 0x80000000u, v.w ^ 0x80000000u};
-        return u32x4{__builtin_amdgcn_alignbit(v.x, v.x, 16), __builtin_amdgcn_alignbit(v.y, v.y, 16),
-                     __builtin_amdgcn_alignbit(v.z, v.z, 16), __builtin_amdgcn_alignbit(v.w, v.w, 16)};
-      };
-      // hi x hi, column-major over the wave tile (dependent products on one
-      // accumulator stay 8 MFMAs apart)
-#pragma unroll
-      for (int ni = 0; ni < 4; ++ni) {
-        bh[ni] = expand(xb, ni, 0);
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(ah[mi], bh[ni], acc[mi][ni]);
-      }
-      if (g.terms == 1) continue;   // hi x hi only
-#pragma unroll
-      for (int ni = 0; ni < 4; ++ni) {
-        bl[ni] = expand(xb, ni, 1);
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(ah[mi], bl[ni], acc[mi][ni]);
-      }
-#pragma unroll
-      for (int ni = 0; ni < 4; ++ni)
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(al[mi], bh[ni], acc[mi][ni]);
+    read_frags(st, 1, ga, gb);       // second half of stage it, in flight during the first half's products
+    products(fa, fb);
+    if (it + 1 < n_iters) {
+      if (it + 2 < n_iters) wait_vmcnt<6>();   // stage it + 1 landed, stage it + 2 may fly
+      else wait_vmcnt<0>();
+      // this wave's reads of stage it are done (its buffer takes stage it + 3), every
+      // wave's copies of stage it + 1 have landed
+      asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+      if (it + 3 < n_iters) issue();
+      read_frags(lds + (int)((it + 1) % DMA_STAGES) * DMA_STAGE_BYTES, 0, fa, fb);
     }
+    products(ga, gb);
   }
   __syncthreads();   // the epilogue reuses the stage buffers
   store_tile<P, 4, 2, true>(d, g, cx, acc, smem, red);
