@@ -111,7 +111,8 @@ def run_precision(tn, torch, net, best, prec, steps, warmup, sample_slice, tunin
 def run_batching(tn, torch, configs, workload, prec, n_small, n_slices, steps):
     """Batching form: a slice range of a large network plus n_small uneven 16-28-qubit
     circuits, contracted plan by plan (tn_contract_slices each) and as one graph replay
-    (tn_group_*)."""
+    (tn_group_*); then the large network alone, and the small circuits alone plan by plan
+    and as a graph of their own."""
     _, net, best = configs.build(workload)
     first = sample_slices(1 << len(best["sliced"]), 1, 404)[0] & ~(n_slices - 1)
     items = [(net, best, first, n_slices)] + [(n, b, 0, 1) for n, b in
@@ -150,6 +151,23 @@ def run_batching(tn, torch, configs, workload, prec, n_small, n_slices, steps):
         info = g.describe()
         grp_amps = [p.amplitudes()[0] for p in plans]
     same = all(np.array_equal(a, b) for a, b in zip(seq_amps, grp_amps))
+    # where the graph's gain comes from: the large network alone, and the uneven circuits
+    # alone plan by plan and as their own graph
+    big_ms = timed(lambda: plans[0].contract(firsts[0], counts[0]))
+
+    def small_sequential():
+        for p in plans[1:]:
+            p.contract(0, 1)
+
+    for p in plans[1:]:
+        p.reset()
+    small_seq_ms = timed(small_sequential)
+    small_amps = [p.amplitudes()[0] for p in plans[1:]]
+    for p in plans[1:]:
+        p.reset()
+    with tn.Group(plans[1:], stream=stream) as g:
+        small_grp_ms = timed(lambda: g.contract([0] * (len(plans) - 1), [1] * (len(plans) - 1)))
+        small_same = all(np.array_equal(a, p.amplitudes()[0]) for a, p in zip(small_amps, plans[1:]))
     for p in plans:
         p.close()
     return {"workload": workload, "plans": len(plans), "workload_slices": [first, first + n_slices],
@@ -157,7 +175,11 @@ def run_batching(tn, torch, configs, workload, prec, n_small, n_slices, steps):
             "graph_ms": round(grp_ms, 3), "speedup": round(seq_ms / grp_ms, 3),
             "graph_tflops": round(flops / (grp_ms * 1e-3) / 1e12, 3),
             "graph_kernels": info["n_kernels"], "graph_branches": info["n_branches"],
-            "amplitudes_identical": bool(same), "precision": prec}
+            "amplitudes_identical": bool(same), "precision": prec,
+            "large_network_alone_ms": round(big_ms, 3),
+            "small_circuits_alone": {"sequential_ms": round(small_seq_ms, 3), "graph_ms": round(small_grp_ms, 3),
+                                     "speedup": round(small_seq_ms / small_grp_ms, 3),
+                                     "amplitudes_identical": bool(small_same)}}
 
 
 def run_tuning_modes(tn, torch, net, best, prec, n_slices):

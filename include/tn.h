@@ -230,11 +230,17 @@ tn_status tn_reset(tn_plan plan);
  * Sec. 3.2).  The group captures, once per set of ranges, every plan's kernel chain
  * (its slice-independent steps, then per chunk of slices its slice-dependent steps
  * and the FP64 cross-slice sum) into one graph whose parallel branches each run
- * the chains of a subset of the plans in sequence.  Plans go to branches by
+ * the chains of a subset of the plans.  Plans go to branches by
  * longest-processing-time-first on their flop counts, so branches carry similar
- * work; branches run concurrently on the device.  Every kernel is the one the plan
- * runs on its own, with the plan's own tiles, so a group adds exactly what
- * tn_contract_slices on each plan adds.
+ * work; branches run concurrently on the device.  Within a branch the chains
+ * advance in rounds: round r is the r-th launch of each of the branch's plans.
+ * The element-wise launches of a round (small steps, split-K sums, FP64 slice
+ * sums, fills) go out as ONE batched launch whose blocks look their task up in a
+ * table; the round's MFMA launches follow one by one.  Every block runs the code
+ * the plan runs on its own, with the plan's own tiles, so a group adds exactly
+ * what tn_contract_slices on each plan adds (bit for bit).  The task tables live
+ * in device memory the group allocates with each captured graph (about 300 bytes
+ * per batched task and 4 bytes per block).
  *
  * tn_group_create: plans[0..n) must be device plans of one precision; they stay
  *   owned by the caller and must outlive the group, and must not be used for
@@ -246,7 +252,8 @@ tn_status tn_reset(tn_plan plan);
  *   Asynchronous; read results with tn_amplitudes on each plan.  The graph is
  *   captured on the first call with a given set of ranges and replayed (one
  *   hipGraphLaunch) on later calls with the same ranges.
- * tn_group_describe: kernel nodes and branches of the graph of the last call. */
+ * tn_group_describe: kernel nodes (a batched launch counts once) and branches of
+ *   the graph of the last call. */
 tn_status tn_group_create(tn_group* out, const tn_plan* plans, int32_t n_plans, const tn_options* opts);
 tn_status tn_group_contract(tn_group group, const int64_t* first, const int64_t* count);
 tn_status tn_group_describe(tn_group group, int64_t* n_kernels, int32_t* n_branches);

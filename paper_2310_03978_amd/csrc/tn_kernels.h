@@ -50,6 +50,21 @@ struct PermDesc {
 hipError_t tn_launch_gett(int kind, int tile, const GettDesc* d, const GettArgs& g, int64_t blocks, hipStream_t s);
 hipError_t tn_launch_permute(const PermDesc* p, int pairs, int64_t blocks, const void* in, void* out,
                              hipStream_t s);
+// One element-wise launch (a small step, a split-K sum, an FP64 slice sum or a fill)
+// inside a batched launch: its blocks are first_block .. first_block + blocks - 1 of
+// the batched grid, and block_task maps each block of the grid to its task.
+struct BatchTask {
+  int32_t kind;                 // TN_K_SMALL (not the dot form), TN_K_SPLITK_REDUCE, TN_K_SLICE_REDUCE, TN_K_FILL
+  int32_t pad_;
+  int64_t first_block;
+  const GettDesc* desc;
+  GettArgs g;
+  ReduceArgs r;
+  uint32_t* fill_ptr;
+  int64_t fill_n;
+};
+
+hipError_t tn_launch_batch(const BatchTask* tasks, const int32_t* block_task, int64_t blocks, hipStream_t s);
 hipError_t tn_launch_slice_reduce(const ReduceArgs& r, hipStream_t s);
 hipError_t tn_launch_absmax(const void* x, int64_t n, uint32_t* dst, hipStream_t s);
 hipError_t tn_launch_fill_u32(void* p, uint32_t v, int64_t n, hipStream_t s);

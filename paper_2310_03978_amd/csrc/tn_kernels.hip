@@ -1175,6 +1175,24 @@ __device__ __forceinline__ void fill_block(uint32_t* p, uint32_t v, int64_t n, i
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) { fill_block(p, v, n, blockIdx.x); }
 
 // ---------------------------------------------------------------------------
+// Batched element-wise launches: each block looks up its task (one launch of one
+// plan) and runs that launch's block, so the element-wise launches of many
+// independent plans go out as one kernel.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_batch(const BatchTask* __restrict__ tasks,
+                                               const int32_t* __restrict__ block_task) {
+  __shared__ uint32_t red[8];
+  const BatchTask& tk = tasks[block_task[blockIdx.x]];
+  const int64_t b = (int64_t)blockIdx.x - tk.first_block;
+  switch (tk.kind) {
+    case TN_K_SMALL: gett_small_block(tk.desc, tk.g, b, red); break;
+    case TN_K_SPLITK_REDUCE: splitk_reduce_block(tk.desc, tk.g, b, red); break;
+    case TN_K_SLICE_REDUCE: slice_reduce_block(tk.r, b); break;
+    default: fill_block(tk.fill_ptr, 0, tk.fill_n, b); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 namespace {
@@ -1236,6 +1254,12 @@ hipError_t tn_launch_permute(const PermDesc* p, int pairs, int64_t blocks, const
   else
     hipLaunchKernelGGL(k_permute<1>, dim3((unsigned)blocks), dim3(256), 0, s, p, reinterpret_cast<const float2*>(in),
                        reinterpret_cast<float2*>(out));
+  return hipGetLastError();
+}
+
+hipError_t tn_launch_batch(const BatchTask* tasks, const int32_t* block_task, int64_t blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch, dim3((unsigned)blocks), dim3(256), 0, s, tasks, block_task);
   return hipGetLastError();
 }
 

@@ -1884,8 +1884,17 @@ struct tn_group_s {
     std::vector<int64_t> key;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    void* d_batch = nullptr;                 // task and block tables of the batched launches
     int64_t n_kernels = 0;
     int32_t n_branches = 0;
+    void release() {
+      if (exec) hipGraphExecDestroy(exec);
+      if (graph) hipGraphDestroy(graph);
+      if (d_batch) hipFree(d_batch);
+      exec = nullptr;
+      graph = nullptr;
+      d_batch = nullptr;
+    }
   };
   std::vector<Cached> cache;
   int64_t last_kernels = 0;
@@ -1893,10 +1902,7 @@ struct tn_group_s {
 
   ~tn_group_s() {
     if (stream) hipStreamSynchronize(stream);
-    for (auto& c : cache) {
-      if (c.exec) hipGraphExecDestroy(c.exec);
-      if (c.graph) hipGraphDestroy(c.graph);
-    }
+    for (auto& c : cache) c.release();
     for (auto e : branch_done)
       if (e) hipEventDestroy(e);
     for (auto b : branch)
@@ -1910,9 +1916,13 @@ struct tn_group_s {
 namespace {
 
 // Capture every plan's launch chain for the ranges in `key` into one graph:
-// plans are assigned to branches longest-processing-time first (by flops),
-// each branch runs its plans' chains in sequence, branches fork from and join
-// into the group stream.
+// plans are assigned to branches longest-processing-time first (by flops), and
+// branches fork from and join into the group stream.  Within a branch the plans'
+// chains advance in rounds: round r holds the r-th launch of each of the branch's
+// plans (launches of different plans are independent, and a plan's launches stay
+// in order because rounds do).  The element-wise launches of a round (small
+// steps, split-K sums, FP64 slice sums, fills) go out as one batched launch; its
+// MFMA launches follow it one by one.
 tn_status group_build(tn_group_s* G, const std::vector<int64_t>& key, tn_group_s::Cached& C) {
   const int P = (int)G->plans.size();
   std::vector<std::vector<Launch>> chains(P);
@@ -1936,18 +1946,91 @@ tn_status group_build(tn_group_s* G, const std::vector<int64_t>& key, tn_group_s
     load[b] += w.first;
     assign[b].push_back(w.second);
   }
+  struct Round {
+    int64_t task0 = 0, ntask = 0, block0 = 0, nblock = 0;
+    std::vector<std::pair<int, const Launch*>> single;   // (plan, launch) issued on their own
+  };
+  std::vector<std::vector<Round>> rounds(B);
+  std::vector<BatchTask> tasks;
+  std::vector<int32_t> block_task;
+  for (int b = 0; b < B; ++b) {
+    size_t len = 0;
+    for (int i : assign[b]) len = std::max(len, chains[i].size());
+    for (size_t r = 0; r < len; ++r) {
+      Round R;
+      std::vector<std::pair<int, const Launch*>> batch;
+      for (int i : assign[b]) {
+        if (r >= chains[i].size()) continue;
+        const Launch& L = chains[i][r];
+        const bool elementwise = (L.kind == TN_K_SMALL && !L.g.dot) || L.kind == TN_K_SPLITK_REDUCE ||
+                                 L.kind == TN_K_SLICE_REDUCE || L.kind == TN_K_FILL;
+        if (elementwise && L.nblocks(256) > 0) batch.push_back({i, &L});
+        else R.single.push_back({i, &L});
+      }
+      if (batch.size() == 1) {
+        R.single.insert(R.single.begin(), batch[0]);
+        batch.clear();
+      }
+      R.task0 = (int64_t)tasks.size();
+      R.block0 = (int64_t)block_task.size();
+      for (auto& e : batch) {
+        const Launch& L = *e.second;
+        BatchTask t;
+        memset(&t, 0, sizeof(t));
+        t.kind = L.kind;
+        t.first_block = R.nblock;
+        t.desc = L.desc;
+        t.g = L.g;
+        t.r = L.r;
+        t.fill_ptr = L.fill_ptr;
+        t.fill_n = L.fill_n;
+        const int64_t nb = L.nblocks(256);
+        block_task.insert(block_task.end(), (size_t)nb, (int32_t)R.ntask);
+        tasks.push_back(t);
+        ++R.ntask;
+        R.nblock += nb;
+      }
+      rounds[b].push_back(std::move(R));
+    }
+  }
+  const BatchTask* d_tasks = nullptr;
+  const int32_t* d_block_task = nullptr;
+  if (!tasks.empty()) {
+    const size_t tb = tasks.size() * sizeof(BatchTask), bb = block_task.size() * sizeof(int32_t);
+    if (hipMalloc(&C.d_batch, tb + bb) != hipSuccess) {
+      hipGetLastError();
+      return fail(TN_E_NOMEM, "group task tables: device allocation failed");
+    }
+    tn_status st = check(hipMemcpy(C.d_batch, tasks.data(), tb, hipMemcpyHostToDevice), "task table upload");
+    if (!st)
+      st = check(hipMemcpy(static_cast<char*>(C.d_batch) + tb, block_task.data(), bb, hipMemcpyHostToDevice),
+                 "block table upload");
+    if (st) return st;
+    d_tasks = static_cast<const BatchTask*>(C.d_batch);
+    d_block_task = reinterpret_cast<const int32_t*>(static_cast<const char*>(C.d_batch) + tb);
+  }
   C.key = key;
   C.n_kernels = 0;
   C.n_branches = B;
   tn_status st = check(hipStreamBeginCapture(G->stream, hipStreamCaptureModeThreadLocal), "begin capture");
   if (st) return st;
   st = check(hipEventRecord(G->fork, G->stream), "fork");
+  std::vector<Launch> one(1);
   for (int b = 0; b < B && !st; ++b) {
     st = check(hipStreamWaitEvent(G->branch[b], G->fork, 0), "fork wait");
-    for (int i : assign[b]) {
+    for (const Round& R : rounds[b]) {
       if (st) break;
-      st = execute_on(G->plans[i], chains[i], G->branch[b], false);
-      C.n_kernels += (int64_t)chains[i].size();
+      if (R.ntask > 0) {
+        st = check(tn_launch_batch(d_tasks + R.task0, d_block_task + R.block0, R.nblock, G->branch[b]),
+                   "batched launch");
+        ++C.n_kernels;
+      }
+      for (auto& e : R.single) {
+        if (st) break;
+        one[0] = *e.second;
+        st = execute_on(G->plans[e.first], one, G->branch[b], false);
+        ++C.n_kernels;
+      }
     }
     if (!st) st = check(hipEventRecord(G->branch_done[b], G->branch[b]), "join");
     if (!st) st = check(hipStreamWaitEvent(G->stream, G->branch_done[b], 0), "join wait");
@@ -2037,8 +2120,7 @@ tn_status tn_group_contract(tn_group G, const int64_t* first, const int64_t* cou
           if (st) return st;
           synced = true;
         }
-        if (G->cache[j].exec) hipGraphExecDestroy(G->cache[j].exec);
-        if (G->cache[j].graph) hipGraphDestroy(G->cache[j].graph);
+        G->cache[j].release();
         G->cache.erase(G->cache.begin() + j);
       } else {
         ++j;
@@ -2048,6 +2130,7 @@ tn_status tn_group_contract(tn_group G, const int64_t* first, const int64_t* cou
     C = &G->cache.back();
     tn_status st = group_build(G, key, *C);
     if (st) {
+      C->release();
       G->cache.pop_back();
       return st;
     }
