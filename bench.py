@@ -43,7 +43,7 @@ def kernel_name(step) -> str:
         return "k_gett_small"
     p = kind - 1
     if step.get("lds_copy"):
-        return f"void k_gett_dma<{p}>"
+        return f"void k_gett_dma<{p}, {step['lds_copy'] - 1}>"
     wm, wn = WAVES[step["tile"]]
     return f"void k_gett_mfma<{p}, {wm}, {wn}>"
 

@@ -117,8 +117,10 @@ typedef struct {
   int32_t a_contig, b_contig;  /* log2 of the contiguous run (elements) of A and B along the tile */
   double flops, bytes;
   int32_t tile;                /* tile id (0..3, see TN_N_TILE_SHAPES) of an MFMA step; -1 for the small kernel */
-  int32_t lds_copy;            /* 1 = split operands copied global -> LDS without registers (three-stage
-                                  pipeline; both operands stored split, k pairs contiguous, 256 x 128 tiles) */
+  int32_t lds_copy;            /* split operands copied global -> LDS without registers (both operands
+                                  stored split, k pairs contiguous, tile id 256x128): 1 = 256 x 128 tiles,
+                                  three stages; 2 = 512 x 64 tiles for steps with exactly 64 columns, two
+                                  stages; 0 = not */
   int32_t terms;               /* split steps: 3 = hi*hi + hi*lo + lo*hi (default), 1 = hi*hi only
                                   (tn_plan_set_step_terms); 0 for the other kernels */
   int32_t merged_bits;         /* sparse-state plans: bits of the merged open bond of a sparse einsum

@@ -405,7 +405,7 @@ __device__ __forceinline__ TileCtx tile_ctx(const GettDesc* __restrict__ d, cons
   c.tile_n = ((tix >> gm) & ((1ull << gn) - 1)) | ((tix >> (gm + gn + tmb - gm)) << gn);
   c.bidx = bid & ((1ull << c.nbb) - 1);
   c.split = (int)(bid >> c.nbb);
-  constexpr int LMAX = WM == 4 ? 8 : WM == 2 ? 7 : 6;
+  constexpr int LMAX = WM == 8 ? 9 : WM == 4 ? 8 : WM == 2 ? 7 : 6;
   constexpr int NMAX = WN == 4 ? 8 : WN == 2 ? 7 : 6;
   c.lm = d->mb < LMAX ? d->mb : LMAX;
   c.ln = d->nb < NMAX ? d->nb : NMAX;
@@ -782,10 +782,20 @@ __device__ __forceinline__ void store_tile(const GettDesc* __restrict__ d, const
 // kernel forms in LDS.
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int DMA_STAGES = 3;
-constexpr int DMA_A_BYTES = 256 * 128, DMA_B_BYTES = 128 * 128;
-constexpr int DMA_STAGE_BYTES = DMA_A_BYTES + DMA_B_BYTES;
-constexpr int DMA_SMEM = DMA_STAGES * DMA_STAGE_BYTES;    // 144 KiB (the epilogue reuses it)
+// Tile layouts of the LDS-copy kernel: L = 0 is 256 x 128 complex (4 x 2 waves, three
+// stages), L = 1 is 512 x 64 (8 x 1 waves, two stages) for steps with 64 columns.
+template <int L>
+struct DmaShape {
+  static constexpr int WM = L ? 8 : 4, WN = L ? 1 : 2;
+  static constexpr int ROWS = 64 * WM, COLS = 64 * WN;       // A rows and B columns of a tile
+  static constexpr int MBITS = L ? 9 : 8, NBITS = L ? 6 : 7;
+  static constexpr int A_BYTES = ROWS * 128, STAGE = (ROWS + COLS) * 128;
+  static constexpr int STAGES = L ? 2 : 3;
+  static constexpr int CA = ROWS / 64, CB = COLS / 64;       // copies per wave per stage
+  static constexpr int NCOPY = CA + CB;
+};
+constexpr int DMA_SMEM = 3 * DmaShape<0>::STAGE;              // 144 KiB (the epilogue reuses it)
+static_assert(2 * DmaShape<1>::STAGE <= DMA_SMEM, "both layouts fit the same LDS");
 static_assert(DMA_SMEM >= 4 * 64 * (2 * 128 + 8), "epilogue staging must fit");
 
 // s_waitcnt with only the vector-memory counter constrained (gfx9 encoding:
@@ -800,38 +810,43 @@ __device__ __forceinline__ void wait_vmcnt() {
 }
 }  // namespace
 
-template <int P>
+template <int P, int L>
 __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g, uint64_t bid, uint32_t* smem,
                               uint32_t* red) {
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
-  const int wm = w >> 1, wn = w & 1;
-  const TileCtx cx = tile_ctx<4, 2>(d, g, bid);
+  using S = DmaShape<L>;
+  const int wm = w / S::WN, wn = w % S::WN;
+  const TileCtx cx = tile_ctx<S::WM, S::WN>(d, g, bid);
   const int nbb = cx.nbb;
 
-  const int64_t a_base = bits_offset(cx.bidx, d->a_b, nbb) + bits_offset(cx.tile_m << 8, d->a_m, d->mb) + cx.a_tab;
-  const int64_t b_base = bits_offset(cx.bidx, d->b_b, nbb) + bits_offset(cx.tile_n << 7, d->b_n, d->nb) + cx.b_tab;
+  const int64_t a_base =
+      bits_offset(cx.bidx, d->a_b, nbb) + bits_offset(cx.tile_m << S::MBITS, d->a_m, d->mb) + cx.a_tab;
+  const int64_t b_base =
+      bits_offset(cx.bidx, d->b_b, nbb) + bits_offset(cx.tile_n << S::NBITS, d->b_n, d->nb) + cx.b_tab;
   char* lds = reinterpret_cast<char*>(smem);
 
   // The quad each lane copies: DMA instruction i of wave w fills rows (8 i + w) * 8 + lane / 8
-  // (A: i < 4, 256 rows; B: i < 2, 128 columns).  Logical slot s of a row holds the hi
+  // (A: i < CA, 64 CA rows; B: i < CB, 64 CB columns).  Logical slot s of a row holds the hi
   // (s even) or lo (s odd) quad of k = 4 (s / 2) .. 4 (s / 2) + 3; the lane in physical
   // slot p = lane % 8 copies logical slot p ^ dma_swz(row).  a_word / b_word: word offset
   // of that quad from the stage's element offset (doubled: two words per element).
   const int prow = lane >> 3, pslot = lane & 7;
-  int32_t a_word[4], b_word[2];
+  int32_t a_word[S::CA], b_word[S::CB];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < S::CA; ++i) {
     const int r = (8 * i + w) * 8 + prow;
     const int sl = pslot ^ dma_swz(r);
-    a_word[i] = (int32_t)(2 * (bits_offset((uint64_t)r, d->a_m, 8) + bits_offset((uint64_t)(4 * (sl >> 1)), d->a_k, 4)) +
+    a_word[i] = (int32_t)(2 * (bits_offset((uint64_t)r, d->a_m, S::MBITS) +
+                               bits_offset((uint64_t)(4 * (sl >> 1)), d->a_k, 4)) +
                           4 * (sl & 1));
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < S::CB; ++i) {
     const int c = (8 * i + w) * 8 + prow;
     const int sl = pslot ^ dma_swz(c);
-    b_word[i] = (int32_t)(2 * (bits_offset((uint64_t)c, d->b_n, 7) + bits_offset((uint64_t)(4 * (sl >> 1)), d->b_k, 4)) +
+    b_word[i] = (int32_t)(2 * (bits_offset((uint64_t)c, d->b_n, S::NBITS) +
+                               bits_offset((uint64_t)(4 * (sl >> 1)), d->b_k, 4)) +
                           4 * (sl & 1));
   }
   const uint32_t* Aw = reinterpret_cast<const uint32_t*>(g.A);
@@ -845,13 +860,13 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
   const int64_t a_kstep = d->a_kstep, b_kstep = d->b_kstep;
   int64_t next_it = 0;   // stage whose copy is issued next
   auto issue = [&]() {
-    char* st = lds + (int)(next_it % DMA_STAGES) * DMA_STAGE_BYTES;
+    char* st = lds + (int)(next_it % S::STAGES) * S::STAGE;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < S::CA; ++i)
       __builtin_amdgcn_global_load_lds(Aw + 2 * ak + a_word[i], st + (8 * i + w) * 1024, 16, 0, 0);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-      __builtin_amdgcn_global_load_lds(Bw + 2 * bk + b_word[i], st + DMA_A_BYTES + (8 * i + w) * 1024, 16, 0, 0);
+    for (int i = 0; i < S::CB; ++i)
+      __builtin_amdgcn_global_load_lds(Bw + 2 * bk + b_word[i], st + S::A_BYTES + (8 * i + w) * 1024, 16, 0, 0);
     if (next_it + 1 < n_iters) {
       if (k_linear) {
         ak += a_kstep;
@@ -894,7 +909,7 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
       const int n = wn * 64 + nb * 32 + (lane & 31);
-      const char* bp = st + DMA_A_BYTES + n * 128;
+      const char* bp = st + S::A_BYTES + n * 128;
       xb[nb][0] = *reinterpret_cast<const u32x4*>(bp + ((s0 ^ dma_swz(n)) << 4));
       xb[nb][1] = *reinterpret_cast<const u32x4*>(bp + (((s0 + 1) ^ dma_swz(n)) << 4));
     }
@@ -930,40 +945,47 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
     }
   };
 
-  issue();
-  if (n_iters > 1) issue();
-  if (n_iters > 1) wait_vmcnt<6>();   // stage 0 landed, stage 1 may fly
-  else wait_vmcnt<0>();
+  // wait until the stage a wave needs has landed; with `one_younger` the copies of the
+  // stage after it may still fly (at most one: the last stage is issued only after the
+  // first barrier, into a buffer no wave has read yet)
+  auto wait_landed = [&](bool one_younger) {
+    if (one_younger) wait_vmcnt<S::NCOPY>();
+    else wait_vmcnt<0>();
+  };
+#pragma unroll
+  for (int st0 = 0; st0 + 1 < S::STAGES; ++st0)
+    if (st0 < n_iters) issue();
+  wait_landed(S::STAGES >= 3 && n_iters > 1);
   asm volatile("s_barrier" ::: "memory");
-  if (n_iters > 2) issue();
+  if (S::STAGES - 1 < n_iters) issue();
   u32x4 fa[2][2], fb[2][2], ga[2][2], gb[2][2];
   read_frags(lds, 0, fa, fb);
   for (int64_t it = 0; it < n_iters; ++it) {
-    const char* st = lds + (int)(it % DMA_STAGES) * DMA_STAGE_BYTES;
+    const char* st = lds + (int)(it % S::STAGES) * S::STAGE;
     read_frags(st, 1, ga, gb);       // second half of stage it, in flight during the first half's products
     products(fa, fb);
     if (it + 1 < n_iters) {
-      if (it + 2 < n_iters) wait_vmcnt<6>();   // stage it + 1 landed, stage it + 2 may fly
-      else wait_vmcnt<0>();
-      // this wave's reads of stage it are done (its buffer takes stage it + 3), every
+      // stage it + 1 landed; stage it + 2, if issued, may fly
+      wait_landed(S::STAGES >= 3 && it + 2 < n_iters);
+      // this wave's reads of stage it are done (its buffer takes stage it + STAGES), every
       // wave's copies of stage it + 1 have landed
       asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-      if (it + 3 < n_iters) issue();
-      read_frags(lds + (int)((it + 1) % DMA_STAGES) * DMA_STAGE_BYTES, 0, fa, fb);
+      if (it + S::STAGES < n_iters) issue();
+      read_frags(lds + (int)((it + 1) % S::STAGES) * S::STAGE, 0, fa, fb);
     }
     products(ga, gb);
   }
   __syncthreads();   // the epilogue reuses the stage buffers
-  store_tile<P, 4, 2, true>(d, g, cx, acc, smem, red);
+  store_tile<P, S::WM, S::WN, true>(d, g, cx, acc, smem, red);
 }
 
-template <int P>
+template <int P, int L>
 __global__ __launch_bounds__(512, 2) void k_gett_dma(const GettDesc* __restrict__ d, GettArgs g) {
   extern __shared__ __align__(16) uint32_t smem[];
   __shared__ uint32_t red[16];
   uint64_t bid = blockIdx.x;
   if ((gridDim.x & 7u) == 0) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
-  gett_dma_tile<P>(d, g, bid, smem, red);
+  gett_dma_tile<P, L>(d, g, bid, smem, red);
 }
 
 template <int P, int WM, int WN>
@@ -1209,7 +1231,10 @@ template <int P>
 hipError_t launch_dma(const GettDesc* d, const GettArgs& g, int64_t blocks, hipStream_t s) {
   hipError_t e = tn_prepare_kernels();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_gett_dma<P>), dim3((unsigned)blocks), dim3(512), DMA_SMEM, s, d, g);
+  if (g.dma == 2)
+    hipLaunchKernelGGL((k_gett_dma<P, 1>), dim3((unsigned)blocks), dim3(512), DMA_SMEM, s, d, g);
+  else
+    hipLaunchKernelGGL((k_gett_dma<P, 0>), dim3((unsigned)blocks), dim3(512), DMA_SMEM, s, d, g);
   return hipGetLastError();
 }
 
@@ -1305,8 +1330,10 @@ hipError_t tn_prepare_kernels() {
   TN_SET_ATTR(1, 4, 2); TN_SET_ATTR(1, 2, 2); TN_SET_ATTR(1, 2, 1); TN_SET_ATTR(1, 1, 1);
   TN_SET_ATTR(2, 4, 2); TN_SET_ATTR(2, 2, 2); TN_SET_ATTR(2, 2, 1); TN_SET_ATTR(2, 1, 1);
 #undef TN_SET_ATTR
-  set(reinterpret_cast<const void*>(&k_gett_dma<1>), DMA_SMEM);
-  set(reinterpret_cast<const void*>(&k_gett_dma<2>), DMA_SMEM);
+  set(reinterpret_cast<const void*>(&k_gett_dma<1, 0>), DMA_SMEM);
+  set(reinterpret_cast<const void*>(&k_gett_dma<2, 0>), DMA_SMEM);
+  set(reinterpret_cast<const void*>(&k_gett_dma<1, 1>), DMA_SMEM);
+  set(reinterpret_cast<const void*>(&k_gett_dma<2, 1>), DMA_SMEM);
   if (e == hipSuccess) done = true;
   return e;
 }

@@ -699,3 +699,53 @@ def test_sparse_state_matches_oracle(prec, sliced_bits):
     rep = metrics.report(got, ref)
     print(f"sparse state {prec} sliced {sliced_bits}: {rep}", flush=True)
     assert rep["rel_l2"] <= TOL[prec]
+
+
+def _wide_copy_steps(p):
+    """Steps whose 256x128 tile id takes the LDS-copy kernel's 512 x 64 layout once set."""
+    out = []
+    for i, s in enumerate(p.steps()):
+        if s["kernel"] in (2, 3) and s["n"] == 64 and s["m"] >= 512:
+            p.set_tile(i, 0)
+            if p.steps()[i]["lds_copy"] == 2:
+                out.append(i)
+    return out
+
+
+def test_lds_copy_512x64_layout_on_a_single_stage_step():
+    """A 64-column split step of the 30-qubit network (m = 4096, k = 16: one K stage) on the
+    LDS-copy kernel's 512 x 64 layout gives the amplitudes of the same plan with the step on
+    the staged kernel, to rounding (2 slices, split FP16)."""
+    print("copy layout 512x64 on rqc30", flush=True)
+    circ, net, best = configs.build("rqc30")
+    with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best["sliced"], precision="f16x3",
+                 tuning=0) as p:
+        p.contract(0, 2)
+        ref, _ = p.amplitudes()
+        p.reset()
+        wide = _wide_copy_steps(p)
+        assert wide, "no 64-column split step in the plan"
+        assert any(p.steps()[i]["k"] == 16 for i in wide)
+        p.contract(0, 2)
+        got, _ = p.amplitudes()
+    assert metrics.rel_l2(got, ref) <= 1e-5
+
+
+def test_lds_copy_512x64_layout_on_the_sparse_state():
+    """The sparse state of the 30-qubit 12-cycle circuit (4096 bitstrings), whose largest
+    sparse einsum (1024 merged values x 65536 x 64 x 4096) runs on the 512 x 64 layout,
+    against the complex64 contraction of the same plan."""
+    print("copy layout 512x64 on the sparse state", flush=True)
+    net, path, bits = configs.sparse_state_workload()
+    with tn.Plan(net.tensors, net.labels, net.open_labels, path, precision="c64", bitstrings=bits) as q:
+        q.contract()
+        ref, _ = q.amplitudes()
+    with tn.Plan(net.tensors, net.labels, net.open_labels, path, precision="f16x3", bitstrings=bits,
+                 tuning=0) as p:
+        wide = _wide_copy_steps(p)
+        assert any(p.steps()[i]["merged_bits"] >= 0 and p.steps()[i]["k"] == 4096 for i in wide)
+        p.contract()
+        got, _ = p.amplitudes()
+    rel = metrics.rel_l2(got, ref)
+    print(f"sparse state on the 512 x 64 layout: rel_l2 vs complex64 {rel:.2e}", flush=True)
+    assert rel <= 1e-4
