@@ -3,9 +3,9 @@
     python -m paper_2310_03978_amd.train_costmodel --out paper_2310_03978_amd/data/costmodel_mi355x.json
 
 Data: every step of the plans of seeded uneven lattice circuits (16-28 qubits, depth 8-14),
-the 30-qubit 12-cycle workload and the 30-qubit 14-cycle sliced workload (chunks of 8 slices
-and of 1 slice), in the three precisions, each MFMA step timed with all four tile shapes
-(HIP events on the plan's stream).  The model is trained on all circuits but the last
+the 30-qubit 12-cycle workload, a sparse state of that circuit (2048 bitstrings, seed 13) and
+the 30-qubit 14-cycle sliced workload (chunks of 8 slices and of 1 slice), in the three
+precisions, each MFMA step timed with all four tile shapes (HIP events on the plan's stream).  The model is trained on all circuits but the last
 `--held-out` ones and the 14-cycle workload; the saved file records the held-out error and
 the measured time of the tiles the model picks against the shape heuristic's picks.
 """
@@ -33,18 +33,20 @@ def log(*a):
 
 def harvest_all(n_circuits: int, precisions, reps: int):
     circs = configs.uneven_circuits(n_circuits, seed=5000, cap_log2=25)
-    items = [(f"u{i}", net, best, 0) for i, (net, best) in enumerate(circs)]
+    items = [(f"u{i}", net, best, 0, None) for i, (net, best) in enumerate(circs)]
     for name in ["rqc30d12", "rqc30"]:
         _, net, best = configs.build(name)
-        items.append((name, net, best, 0))
+        items.append((name, net, best, 0, None))
+    net, path, bits = configs.sparse_state_workload(count=2048, seed=13)
+    items.append(("sparse2048", net, {"path": path}, 0, bits))
     _, net, best = configs.build("rqc30")
-    items.append(("rqc30sb1", net, best, 1))
+    items.append(("rqc30sb1", net, best, 1, None))
     records, defaults = [], {}
     for prec in precisions:
-        for tag, net, best, sb in items:
+        for tag, net, best, sb, bits in items:
             t0 = time.time()
             with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best.get("sliced", ()),
-                         precision=prec, record_steps=True, slice_batch=sb) as p:
+                         precision=prec, record_steps=True, slice_batch=sb, bitstrings=bits) as p:
                 for i, t in enumerate(costmodel.step_tile_ids(p)):
                     defaults[(f"{prec}:{tag}", i)] = t
                 recs = costmodel.harvest(p, tag=f"{prec}:{tag}", reps=reps)
