@@ -251,14 +251,36 @@ __device__ void gett_small_block(const GettDesc* __restrict__ d, const GettArgs&
     const float2* B = reinterpret_cast<const float2*>(g.B);
     float cr = 0.f, ci = 0.f;
     const int64_t K = (int64_t)1 << d->kb;
-    for (int64_t k = 0; k < K; ++k) {
-      const float2 a = A[oa + bits_offset(k, d->a_k, d->kb)];
-      const float2 b = B[ob + bits_offset(k, d->b_k, d->kb)];
-      const float ar = a.x * sc.fa, ai = a.y * sc.fa, br = b.x * sc.fb, bi = b.y * sc.fb;
-      cr = fmaf(ar, br, cr);
-      cr = fmaf(-ai, bi, cr);
-      ci = fmaf(ar, bi, ci);
-      ci = fmaf(ai, br, ci);
+    // K in groups of 8: the group's 16 loads are issued before its products, so a
+    // thread waits for memory once per group rather than once per k (the products
+    // still run in increasing k)
+    constexpr int KU = 8;
+    const int lb = d->kb < 3 ? d->kb : 3;
+    int64_t lo_a[KU], lo_b[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      lo_a[u] = bits_offset((uint64_t)u, d->a_k, lb);
+      lo_b[u] = bits_offset((uint64_t)u, d->b_k, lb);
+    }
+    for (int64_t k0 = 0; k0 < K; k0 += KU) {
+      const int64_t ga = oa + bits_offset((uint64_t)k0, d->a_k, d->kb);
+      const int64_t gb = ob + bits_offset((uint64_t)k0, d->b_k, d->kb);
+      float2 av[KU], bv[KU];
+#pragma unroll
+      for (int u = 0; u < KU; ++u)
+        if (u < K) {
+          av[u] = A[ga + lo_a[u]];
+          bv[u] = B[gb + lo_b[u]];
+        }
+#pragma unroll
+      for (int u = 0; u < KU; ++u)
+        if (u < K) {
+          const float ar = av[u].x * sc.fa, ai = av[u].y * sc.fa, br = bv[u].x * sc.fb, bi = bv[u].y * sc.fb;
+          cr = fmaf(ar, br, cr);
+          cr = fmaf(-ai, bi, cr);
+          ci = fmaf(ar, bi, ci);
+          ci = fmaf(ai, br, ci);
+        }
     }
     mx = store_c(g.C, e, make_float2(cr, ci), g, sc.ft);
     const uint64_t own_mask = (1ull << d->own_bb) - 1;
