@@ -3,9 +3,9 @@
     python -m paper_2310_03978_amd.train_costmodel --out paper_2310_03978_amd/data/costmodel_mi355x.json
 
 Data: every step of the plans of seeded uneven lattice circuits (16-28 qubits, depth 8-14),
-the 30-qubit 12-cycle workload, a sparse state of that circuit (2048 bitstrings, seed 13) and
-the 30-qubit 14-cycle sliced workload (chunks of 8 slices and of 1 slice), in the three
-precisions, each MFMA step timed with all four tile shapes (HIP events on the plan's stream).  The model is trained on all circuits but the last
+the 30-qubit 12-cycle workload, a sparse state of that circuit (2048 bitstrings, seed 13), one
+slice of the 53-qubit 12-cycle workload (intermediates up to 2^30 elements) and the 30-qubit
+14-cycle sliced workload (chunks of 8 slices and of 1 slice), in the three precisions, each MFMA step timed with all four tile shapes (HIP events on the plan's stream).  The model is trained on all circuits but the last
 `--held-out` ones and the 14-cycle workload; the saved file records the held-out error and
 the measured time of the tiles the model picks against the shape heuristic's picks.
 """
@@ -39,6 +39,8 @@ def harvest_all(n_circuits: int, precisions, reps: int):
         items.append((name, net, best, 0, None))
     net, path, bits = configs.sparse_state_workload(count=2048, seed=13)
     items.append(("sparse2048", net, {"path": path}, 0, bits))
+    _, net, best = configs.build("rqc53d12")
+    items.append(("rqc53d12sb1", net, best, 1, None))
     _, net, best = configs.build("rqc30")
     items.append(("rqc30sb1", net, best, 1, None))
     records, defaults = [], {}
