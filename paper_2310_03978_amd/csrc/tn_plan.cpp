@@ -2019,10 +2019,14 @@ tn_status group_build(tn_group_s* G, const std::vector<int64_t>& key, tn_group_s
       hipGetLastError();
       return fail(TN_E_NOMEM, "group task tables: device allocation failed");
     }
-    tn_status st = check(hipMemcpy(C.d_batch, tasks.data(), tb, hipMemcpyHostToDevice), "task table upload");
+    // on the group's stream (after any replay still running there), finished before capture
+    tn_status st = check(hipMemcpyAsync(C.d_batch, tasks.data(), tb, hipMemcpyHostToDevice, G->stream),
+                         "task table upload");
     if (!st)
-      st = check(hipMemcpy(static_cast<char*>(C.d_batch) + tb, block_task.data(), bb, hipMemcpyHostToDevice),
+      st = check(hipMemcpyAsync(static_cast<char*>(C.d_batch) + tb, block_task.data(), bb, hipMemcpyHostToDevice,
+                                G->stream),
                  "block table upload");
+    if (!st) st = check(hipStreamSynchronize(G->stream), "task table sync");
     if (st) return st;
     d_tasks = static_cast<const BatchTask*>(C.d_batch);
     d_block_task = reinterpret_cast<const int32_t*>(static_cast<const char*>(C.d_batch) + tb);
