@@ -120,6 +120,7 @@ typedef struct {
   int32_t lds_copy;            /* split operands copied global -> LDS without registers (both operands
                                   stored split, k pairs contiguous, tile id 256x128): 1 = 256 x 128 tiles,
                                   three stages; 2 = 512 x 64 tiles for steps with exactly 64 columns, two
+                                  stages; 3 = 512 x 32 tiles for steps with exactly 32 columns, two
                                   stages; 0 = not */
   int32_t terms;               /* split steps: 3 = hi*hi + hi*lo + lo*hi (default), 1 = hi*hi only
                                   (tn_plan_set_step_terms); 0 for the other kernels */

@@ -446,7 +446,7 @@ __device__ __forceinline__ TileCtx tile_ctx(const GettDesc* __restrict__ d, cons
 // PAIRED: accumulator blocks 0, 1 hold the real parts and blocks 2, 3 the imaginary
 // parts of the wave's complex columns 0-31 and 32-63 (else real columns 2n, 2n + 1 sit
 // in adjacent lanes of one block).
-template <int P, int WM, int WN, bool PAIRED = false>
+template <int P, int WM, int WN, bool PAIRED = false, int NBLK = 4>
 __device__ __forceinline__ void store_tile(const GettDesc* __restrict__ d, const GettArgs& g, const TileCtx& cx,
                            floatx16 (&acc)[2][4], uint32_t* smem, uint32_t* red);
 
@@ -709,7 +709,7 @@ __device__ void gett_mfma_tile(const GettDesc* __restrict__ d, const GettArgs& g
 
 // Epilogue: accumulators -> LDS (64 rows per pass) -> C in its layout and format
 // (or split-K partials to scratch), plus the tile's contribution to C's maximum.
-template <int P, int WM, int WN, bool PAIRED>
+template <int P, int WM, int WN, bool PAIRED, int NBLK>
 __device__ __forceinline__ void store_tile(const GettDesc* __restrict__ d, const GettArgs& g, const TileCtx& cx,
                            floatx16 (&acc)[2][4], uint32_t* smem, uint32_t* red) {
   using T = Tile<P, WM, WN>;
@@ -745,11 +745,13 @@ __device__ __forceinline__ void store_tile(const GettDesc* __restrict__ d, const
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni)
+        for (int ni = 0; ni < NBLK; ++ni)
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const int row = mi * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-            const int col = wn * 128 + (PAIRED ? 2 * ((ni & 1) * 32 + (lane & 31)) + (ni >> 1) : ni * 32 + (lane & 31));
+            // PAIRED: blocks ni < NBLK / 2 hold real parts, the others imaginary parts
+            const int col = wn * 128 + (PAIRED ? 2 * ((ni % (NBLK / 2)) * 32 + (lane & 31)) + ni / (NBLK / 2)
+                                               : ni * 32 + (lane & 31));
             Cs[row * T::LDC + col] = acc[mi][ni][v];
           }
     }
@@ -805,19 +807,23 @@ __device__ __forceinline__ void store_tile(const GettDesc* __restrict__ d, const
 // ---------------------------------------------------------------------------
 namespace {
 // Tile layouts of the LDS-copy kernel: L = 0 is 256 x 128 complex (4 x 2 waves, three
-// stages), L = 1 is 512 x 64 (8 x 1 waves, two stages) for steps with 64 columns.
+// stages), L = 1 is 512 x 64 (8 x 1 waves, two stages) for steps with 64 columns, L = 2
+// is 512 x 32 (8 x 1 waves of 64 x 32, two stages) for steps with 32 columns.
 template <int L>
 struct DmaShape {
   static constexpr int WM = L ? 8 : 4, WN = L ? 1 : 2;
-  static constexpr int ROWS = 64 * WM, COLS = 64 * WN;       // A rows and B columns of a tile
-  static constexpr int MBITS = L ? 9 : 8, NBITS = L ? 6 : 7;
+  static constexpr int NB = L == 2 ? 1 : 2;                  // 32-column blocks per wave
+  static constexpr int ROWS = 64 * WM, COLS = 32 * NB * WN;  // A rows and B columns of a tile
+  static constexpr int MBITS = L ? 9 : 8, NBITS = L == 0 ? 7 : L == 1 ? 6 : 5;
   static constexpr int A_BYTES = ROWS * 128, STAGE = (ROWS + COLS) * 128;
   static constexpr int STAGES = L ? 2 : 3;
-  static constexpr int CA = ROWS / 64, CB = COLS / 64;       // copies per wave per stage
+  // copies per wave per stage (one copy fills 8 rows); with 32 columns only waves 0-3 copy B
+  static constexpr int CA = ROWS / 64, CB = (COLS / 8 + 7) / 8;
   static constexpr int NCOPY = CA + CB;
 };
 constexpr int DMA_SMEM = 3 * DmaShape<0>::STAGE;              // 144 KiB (the epilogue reuses it)
-static_assert(2 * DmaShape<1>::STAGE <= DMA_SMEM, "both layouts fit the same LDS");
+static_assert(2 * DmaShape<1>::STAGE <= DMA_SMEM && 2 * DmaShape<2>::STAGE <= DMA_SMEM,
+              "every layout fits the same LDS");
 static_assert(DMA_SMEM >= 4 * 64 * (2 * 128 + 8), "epilogue staging must fit");
 
 // s_waitcnt with only the vector-memory counter constrained (gfx9 encoding:
@@ -865,7 +871,7 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
   }
 #pragma unroll
   for (int i = 0; i < S::CB; ++i) {
-    const int c = (8 * i + w) * 8 + prow;
+    const int c = ((8 * i + w) * 8 + prow) & (S::COLS - 1);   // (wraps only for copies not issued)
     const int sl = pslot ^ dma_swz(c);
     b_word[i] = (int32_t)(2 * (bits_offset((uint64_t)c, d->b_n, S::NBITS) +
                                bits_offset((uint64_t)(4 * (sl >> 1)), d->b_k, 4)) +
@@ -888,7 +894,8 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
       __builtin_amdgcn_global_load_lds(Aw + 2 * ak + a_word[i], st + (8 * i + w) * 1024, 16, 0, 0);
 #pragma unroll
     for (int i = 0; i < S::CB; ++i)
-      __builtin_amdgcn_global_load_lds(Bw + 2 * bk + b_word[i], st + S::A_BYTES + (8 * i + w) * 1024, 16, 0, 0);
+      if ((8 * i + w) * 8 < S::COLS)
+        __builtin_amdgcn_global_load_lds(Bw + 2 * bk + b_word[i], st + S::A_BYTES + (8 * i + w) * 1024, 16, 0, 0);
     if (next_it + 1 < n_iters) {
       if (k_linear) {
         ak += a_kstep;
@@ -929,17 +936,17 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
       xa[mi][1] = *reinterpret_cast<const u32x4*>(st + r * 128 + (((s0 + 1) ^ dma_swz(r)) << 4));
     }
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
+    for (int nb = 0; nb < S::NB; ++nb) {
       const int n = wn * 64 + nb * 32 + (lane & 31);
       const char* bp = st + S::A_BYTES + n * 128;
       xb[nb][0] = *reinterpret_cast<const u32x4*>(bp + ((s0 ^ dma_swz(n)) << 4));
       xb[nb][1] = *reinterpret_cast<const u32x4*>(bp + (((s0 + 1) ^ dma_swz(n)) << 4));
     }
   };
-  // block ni < 2: (Br, -Bi) of column block ni; ni >= 2: (Bi, Br) of block ni - 2
+  // block ni < NB: (Br, -Bi) of column block ni; ni >= NB: (Bi, Br) of block ni - NB
   auto expand = [&](const u32x4 (&x)[2][2], int ni, int hl) {
-    const u32x4& v = x[ni & 1][hl];
-    if (ni < 2) return u32x4{v.x ^ 0x80000000u, v.y ^ 0x80000000u, v.z ^ 0x80000000u, v.w ^ 0x80000000u};
+    const u32x4& v = x[ni % S::NB][hl];
+    if (ni < S::NB) return u32x4{v.x ^ 0x80000000u, v.y ^ 0x80000000u, v.z ^ 0x80000000u, v.w ^ 0x80000000u};
     return u32x4{__builtin_amdgcn_alignbit(v.x, v.x, 16), __builtin_amdgcn_alignbit(v.y, v.y, 16),
                  __builtin_amdgcn_alignbit(v.z, v.z, 16), __builtin_amdgcn_alignbit(v.w, v.w, 16)};
   };
@@ -947,20 +954,20 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
   // over the wave tile (dependent products on one accumulator stay 8 MFMAs apart)
   auto products = [&](const u32x4 (&xa)[2][2], const u32x4 (&xb)[2][2]) {
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni) {
+    for (int ni = 0; ni < 2 * S::NB; ++ni) {
       const u32x4 bh = expand(xb, ni, 0);
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(xa[mi][0], bh, acc[mi][ni]);
     }
     if (g.terms == 1) return;   // hi x hi only
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni) {
+    for (int ni = 0; ni < 2 * S::NB; ++ni) {
       const u32x4 bl = expand(xb, ni, 1);
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(xa[mi][0], bl, acc[mi][ni]);
     }
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni) {
+    for (int ni = 0; ni < 2 * S::NB; ++ni) {
       const u32x4 bh = expand(xb, ni, 0);
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(xa[mi][1], bh, acc[mi][ni]);
@@ -998,7 +1005,7 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
     products(ga, gb);
   }
   __syncthreads();   // the epilogue reuses the stage buffers
-  store_tile<P, S::WM, S::WN, true>(d, g, cx, acc, smem, red);
+  store_tile<P, S::WM, S::WN, true, 2 * S::NB>(d, g, cx, acc, smem, red);
 }
 
 template <int P, int L>
@@ -1253,7 +1260,9 @@ template <int P>
 hipError_t launch_dma(const GettDesc* d, const GettArgs& g, int64_t blocks, hipStream_t s) {
   hipError_t e = tn_prepare_kernels();
   if (e != hipSuccess) return e;
-  if (g.dma == 2)
+  if (g.dma == 3)
+    hipLaunchKernelGGL((k_gett_dma<P, 2>), dim3((unsigned)blocks), dim3(512), DMA_SMEM, s, d, g);
+  else if (g.dma == 2)
     hipLaunchKernelGGL((k_gett_dma<P, 1>), dim3((unsigned)blocks), dim3(512), DMA_SMEM, s, d, g);
   else
     hipLaunchKernelGGL((k_gett_dma<P, 0>), dim3((unsigned)blocks), dim3(512), DMA_SMEM, s, d, g);
@@ -1356,6 +1365,8 @@ hipError_t tn_prepare_kernels() {
   set(reinterpret_cast<const void*>(&k_gett_dma<2, 0>), DMA_SMEM);
   set(reinterpret_cast<const void*>(&k_gett_dma<1, 1>), DMA_SMEM);
   set(reinterpret_cast<const void*>(&k_gett_dma<2, 1>), DMA_SMEM);
+  set(reinterpret_cast<const void*>(&k_gett_dma<1, 2>), DMA_SMEM);
+  set(reinterpret_cast<const void*>(&k_gett_dma<2, 2>), DMA_SMEM);
   if (e == hipSuccess) done = true;
   return e;
 }

@@ -101,7 +101,7 @@ struct Step {
   int k_split_bits = 0;
   int tiles_m_bits = 0, tiles_n_bits = 0;
   int a_contig = 0, b_contig = 0;
-  int dma = 0;                       // split tile fed by global -> LDS copies: 1 = 256x128, 2 = 512x64
+  int dma = 0;                       // split tile fed by global -> LDS copies: 1 = 256x128, 2 = 512x64, 3 = 512x32
   int terms = 3;                     // split steps: products per complex multiply-add term (3 or 1)
   bool dot = false;                  // small steps with <= 4 outputs per batch and long K: block per output
   double flops = 0, bytes = 0;
@@ -356,19 +356,23 @@ void build_desc(tn_plan_s* p, Step& st) {
   for (int j = 0; j < sb; ++j) d.c_pos[C.bits.size() + j] = (0 << 8) | (own + j);
   // the global -> LDS copy path: both operands stored split, quads of consecutive k
   // adjacent in memory (one hi quad, one lo quad), whole 16-k stages, the 256x128 tile
-  // id; full 256 x 128 tiles, or 512 x 64 tiles for steps with exactly 64 columns (which
-  // would leave half of a 256 x 128 tile empty)
+  // id; full 256 x 128 tiles, or 512 x 64 / 512 x 32 tiles for steps with exactly 64 / 32
+  // columns (which would leave half or three quarters of a 256 x 128 tile empty)
   const bool copy_path = (st.kernel == TN_K_MFMA_F16X3 || st.kernel == TN_K_MFMA_BF16X3) &&
                          st.tile == TN_TILE_256x128 && A.fmt == TN_FMT_SPLIT && B.fmt == TN_FMT_SPLIT &&
                          d.kb >= 4 && st.k_split_bits >= 4 && d.a_k[0] == 1 && d.a_k[1] == 2 && d.b_k[0] == 1 &&
                          d.b_k[1] == 2;
-  st.dma = !copy_path ? 0 : (d.mb >= 8 && d.nb >= 7) ? 1 : (d.mb >= 9 && d.nb == 6) ? 2 : 0;
+  st.dma = !copy_path ? 0
+           : (d.mb >= 8 && d.nb >= 7) ? 1
+           : (d.mb >= 9 && d.nb == 6) ? 2
+           : (d.mb >= 9 && d.nb == 5) ? 3
+                                      : 0;
   // tile enumerations for the MFMA kernels (the step's tile shape)
   int bm = 128, bn = 128, nt = 256;
   tn_tile_shape(st.tile, &bm, &bn, &nt);
-  if (st.dma == 2) {
+  if (st.dma >= 2) {
     bm = 512;
-    bn = 64;
+    bn = st.dma == 2 ? 64 : 32;
   }
   const int lm = std::min(d.mb, ilog2_exact(bm)), ln = std::min(d.nb, ilog2_exact(bn)), lk = std::min(d.kb, 4);
   st.tiles_m_bits = d.mb - lm;
@@ -1511,9 +1515,9 @@ void step_features(const tn_plan_s* p, const Step& st0, int tile, float* f) {
   if (mfma) {
     int bm = 128, bn = 128, nt = 256;
     tn_tile_shape(st.tile, &bm, &bn, &nt);
-    if (st.dma == 2) {   // the copy path's 512 x 64 layout of the 256x128 tile id
+    if (st.dma >= 2) {   // the copy path's 512 x 64 / 512 x 32 layouts of the 256x128 tile id
       bm = 512;
-      bn = 64;
+      bn = st.dma == 2 ? 64 : 32;
     }
     const int sb = ilog2_exact(st.splits);
     f[7] = (float)st.tiles_m_bits;
@@ -1695,9 +1699,9 @@ tn_status tn_plan_steps(tn_plan p, tn_step_info* steps, int32_t cap) {
     o.split_k = st.splits;
     int bm = 1, bn = 1, nt = 0;
     if (st.kernel != TN_K_SMALL) tn_tile_shape(st.tile, &bm, &bn, &nt);
-    if (st.dma == 2) {
+    if (st.dma >= 2) {
       bm = 512;
-      bn = 64;
+      bn = st.dma == 2 ? 64 : 32;
     }
     o.tile_m = (int)std::min<int64_t>(o.m, bm);
     o.tile_n = (int)std::min<int64_t>(o.n, bn);

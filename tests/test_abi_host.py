@@ -141,25 +141,25 @@ def test_step_features_describe_the_step_and_tile():
                 continue
             tile = s["tile"]
             bm, bn = [(256, 128), (128, 128), (128, 64), (64, 64)][tile]
-            if s["lds_copy"] == 2:   # the copy path lays a 256x128 tile id out as 512 x 64
-                assert tile == 0 and s["n"] == 64 and s["m"] >= 512
-                bm, bn = 512, 64
+            if s["lds_copy"] >= 2:   # the copy path lays a 256x128 tile id out as 512 x 64 / 512 x 32
+                assert tile == 0 and s["n"] == (64 if s["lds_copy"] == 2 else 32) and s["m"] >= 512
+                bm, bn = 512, s["n"]
             assert (s["tile_m"], s["tile_n"]) == (min(bm, s["m"]), min(bn, s["n"]))
             assert f[16 + tile] == 1 and f[16:20].sum() == 1
             assert f[9] == np.log2(s["split_k"])
             assert f[20] == s["a_contig"] and f[21] == s["b_contig"]
             # other tiles: only tile-dependent features move
             wide = False
-            if s["n"] == 64 and s["m"] >= 512:   # would tile id 0 take the 512 x 64 copy layout?
+            if s["n"] in (32, 64) and s["m"] >= 512:   # would tile id 0 take a 512-row copy layout?
                 tn.tn_plan_set_tile(h, i, 0)
-                wide = tn.tn_plan_steps(h)[i]["lds_copy"] == 2
+                wide = tn.tn_plan_steps(h)[i]["lds_copy"] >= 2
                 tn.tn_plan_set_tile(h, i, tile)
             for t in range(4):
                 g = tn.tn_plan_step_features(h, i, t)
                 assert np.array_equal(g[:7], f[:7]) and g[16 + t] == 1
                 bm, bn = [(256, 128), (128, 128), (128, 64), (64, 64)][t]
                 if t == 0 and wide:
-                    bm, bn = 512, 64
+                    bm, bn = 512, s["n"]
                 assert g[7] == max(0, f[1] - np.log2(bm)) and g[8] == max(0, f[2] - np.log2(bn))
     finally:
         tn.tn_plan_destroy(h)

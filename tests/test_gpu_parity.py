@@ -702,12 +702,13 @@ def test_sparse_state_matches_oracle(prec, sliced_bits):
 
 
 def _wide_copy_steps(p):
-    """Steps whose 256x128 tile id takes the LDS-copy kernel's 512 x 64 layout once set."""
+    """Steps whose 256x128 tile id takes one of the LDS-copy kernel's 512-row layouts
+    (512 x 64 for 64 columns, 512 x 32 for 32) once set."""
     out = []
     for i, s in enumerate(p.steps()):
-        if s["kernel"] in (2, 3) and s["n"] == 64 and s["m"] >= 512:
+        if s["kernel"] in (2, 3) and s["n"] in (32, 64) and s["m"] >= 512:
             p.set_tile(i, 0)
-            if p.steps()[i]["lds_copy"] == 2:
+            if p.steps()[i]["lds_copy"] >= 2:
                 out.append(i)
     return out
 
@@ -733,8 +734,9 @@ def test_lds_copy_512x64_layout_on_a_single_stage_step():
 
 def test_lds_copy_512x64_layout_on_the_sparse_state():
     """The sparse state of the 30-qubit 12-cycle circuit (4096 bitstrings), whose largest
-    sparse einsum (1024 merged values x 65536 x 64 x 4096) runs on the 512 x 64 layout,
-    against the complex64 contraction of the same plan."""
+    sparse einsum (1024 merged values x 65536 x 64 x 4096) runs on the 512 x 64 layout and
+    whose 4096 values x 8192 x 32 x 512 einsum runs on the 512 x 32 layout, against the
+    complex64 contraction of the same plan."""
     print("copy layout 512x64 on the sparse state", flush=True)
     net, path, bits = configs.sparse_state_workload()
     with tn.Plan(net.tensors, net.labels, net.open_labels, path, precision="c64", bitstrings=bits) as q:
@@ -743,7 +745,9 @@ def test_lds_copy_512x64_layout_on_the_sparse_state():
     with tn.Plan(net.tensors, net.labels, net.open_labels, path, precision="f16x3", bitstrings=bits,
                  tuning=0) as p:
         wide = _wide_copy_steps(p)
-        assert any(p.steps()[i]["merged_bits"] >= 0 and p.steps()[i]["k"] == 4096 for i in wide)
+        st = p.steps()
+        assert any(st[i]["merged_bits"] >= 0 and st[i]["k"] == 4096 and st[i]["lds_copy"] == 2 for i in wide)
+        assert any(st[i]["merged_bits"] >= 0 and st[i]["n"] == 32 and st[i]["lds_copy"] == 3 for i in wide)
         p.contract()
         got, _ = p.amplitudes()
     rel = metrics.rel_l2(got, ref)
