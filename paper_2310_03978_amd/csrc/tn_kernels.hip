@@ -10,13 +10,17 @@
 //                     FP32 (lo*lo dropped).  WM x WN waves, 64 x 64 complex outputs
 //                     per wave, K step 16 complex, double-buffered LDS with the next
 //                     stage prefetched into registers during the MFMA phase.
-//  k_gett_dma<P>      the split kernels' 256 x 128 tile for steps whose operands are
+//  k_gett_dma<P,L>    the split kernels' 256x128 tile id for steps whose operands are
 //                     both stored split with k pairs contiguous: operands are copied
 //                     global -> LDS by the DMA path (no registers, no LDS stores),
-//                     three stages deep, one barrier per stage.
+//                     one barrier per stage; L = 0: 256 x 128 tiles, three stages;
+//                     L = 1 / 2: 512 x 64 / 512 x 32 tiles for 64- / 32-column steps,
+//                     two stages.
+//  k_gett_dot         batched dot products: one block per output element.
 //  k_splitk_reduce    sums K partitions in fixed order, writes C in its layout.
-//  k_permute          LDS-staged index permutation, coalesced on both sides.
+//  k_permute<V>       LDS-staged index permutation, coalesced on both sides.
 //  k_slice_reduce     FP64 cross-slice sum in increasing slice order.
+//  k_batch            element-wise launches of many plans as one kernel (groups).
 //
 // The complex product is a real GEMM on stacked blocks: A is read as the real
 // matrix [Ar Ai] (M x 2K, the interleaved complex storage itself), B is expanded
