@@ -511,7 +511,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: slices are independent sub-tasks and the "
-              "multi-GPU sum of partial amplitudes is not part of this build.", file=sys.stderr)
+              "multi-GPU sum of partial amplitudes is not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
