@@ -701,6 +701,9 @@ def test_sparse_state_matches_oracle(prec, sliced_bits):
     assert rep["rel_l2"] <= TOL[prec]
 
 
+_SPARSE_C64 = {}
+
+
 def _wide_copy_steps(p):
     """Steps whose 256x128 tile id takes one of the LDS-copy kernel's 512-row layouts
     (512 x 64 for 64 columns, 512 x 32 for 32) once set."""
@@ -732,17 +735,20 @@ def test_lds_copy_512x64_layout_on_a_single_stage_step():
     assert metrics.rel_l2(got, ref) <= 1e-5
 
 
-def test_lds_copy_512x64_layout_on_the_sparse_state():
+@pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
+def test_lds_copy_512x64_layout_on_the_sparse_state(prec):
     """The sparse state of the 30-qubit 12-cycle circuit (4096 bitstrings), whose largest
     sparse einsum (1024 merged values x 65536 x 64 x 4096) runs on the 512 x 64 layout and
     whose 4096 values x 8192 x 32 x 512 einsum runs on the 512 x 32 layout, against the
     complex64 contraction of the same plan."""
-    print("copy layout 512x64 on the sparse state", flush=True)
+    print(f"copy layouts 512x64 and 512x32 on the sparse state, {prec}", flush=True)
     net, path, bits = configs.sparse_state_workload()
-    with tn.Plan(net.tensors, net.labels, net.open_labels, path, precision="c64", bitstrings=bits) as q:
-        q.contract()
-        ref, _ = q.amplitudes()
-    with tn.Plan(net.tensors, net.labels, net.open_labels, path, precision="f16x3", bitstrings=bits,
+    if "ref" not in _SPARSE_C64:
+        with tn.Plan(net.tensors, net.labels, net.open_labels, path, precision="c64", bitstrings=bits) as q:
+            q.contract()
+            _SPARSE_C64["ref"] = q.amplitudes()[0]
+    ref = _SPARSE_C64["ref"]
+    with tn.Plan(net.tensors, net.labels, net.open_labels, path, precision=prec, bitstrings=bits,
                  tuning=0) as p:
         wide = _wide_copy_steps(p)
         st = p.steps()
@@ -751,5 +757,5 @@ def test_lds_copy_512x64_layout_on_the_sparse_state():
         p.contract()
         got, _ = p.amplitudes()
     rel = metrics.rel_l2(got, ref)
-    print(f"sparse state on the 512 x 64 layout: rel_l2 vs complex64 {rel:.2e}", flush=True)
-    assert rel <= 1e-4
+    print(f"sparse state on the 512-row layouts, {prec}: rel_l2 vs complex64 {rel:.2e}", flush=True)
+    assert rel <= (1e-4 if prec == "f16x3" else 1e-3)
