@@ -343,6 +343,43 @@ def run_permute(tn, torch, reps):
     return out
 
 
+def run_harvest_check(tn, torch, configs):
+    """The step timings the learned cost model trains on, aggregated per kernel instance:
+    one harvest-style pass of the 30-qubit 12-cycle workload in split FP16 (every MFMA step
+    with each of the four tile ids: one warm-up contraction, then two recorded), timed with
+    HIP events on the plan's stream around each launch (tn_plan_step_times).  Run under
+    rocprofv3 --kernel-trace, the per-dispatch durations of the same kernels can be
+    compared with these means.  Split-K steps are counted but left out of the means (their
+    recorded time includes the reduction launch)."""
+    _, net, best = configs.build("rqc30d12")
+    agg = {}
+    with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best["sliced"], precision="f16x3",
+                 record_steps=True, tuning=0) as p:
+        mfma = [i for i, s in enumerate(p.steps()) if s["kernel"] != 0]
+        for tile in range(4):
+            for i in mfma:
+                p.set_tile(i, tile)
+            steps = p.steps()
+            p.contract(0, 1)
+            p.step_times()
+            for _ in range(2):
+                p.contract(0, 1)
+            ms, cnt = p.step_times()
+            for i in mfma:
+                if cnt[i] == 0:
+                    continue
+                a = agg.setdefault(kernel_name(steps[i]), {"launches": 0, "ms": 0.0, "split_k_launches": 0})
+                if steps[i]["split_k"] > 1:
+                    a["split_k_launches"] += int(cnt[i])
+                    continue
+                a["launches"] += int(cnt[i])
+                a["ms"] += float(ms[i])
+        torch.cuda.synchronize()
+    return {k: {"launches": v["launches"], "split_k_launches": v["split_k_launches"],
+                "mean_us": round(1e3 * v["ms"] / v["launches"], 3) if v["launches"] else None}
+            for k, v in sorted(agg.items())}
+
+
 def sample_slices(n_slices: int, count: int, seed: int = 137):
     """Seeded sample of distinct slice ids (sorted)."""
     rng = np.random.default_rng(seed)
@@ -502,6 +539,8 @@ def main():
                     help="skip the permutation-kernel bandwidth measurement")
     ap.add_argument("--permute-only", action="store_true",
                     help="only the permutation-kernel bandwidth measurement (one JSON line)")
+    ap.add_argument("--harvest-check", action="store_true",
+                    help="only the cost model's event-timed step means per kernel (one JSON line)")
     ap.add_argument("--no-sparse-state", dest="sparse_state", action="store_false",
                     help="skip the sparse-state (sampled bitstrings) measurement")
     ap.add_argument("--no-mixed-precision", dest="mixed_precision", action="store_false",
@@ -522,6 +561,9 @@ def main():
     from tn_inputs import configs
     if args.permute_only:
         print(json.dumps({"permute": run_permute(tn, torch, max(args.steps, 5))}), flush=True)
+        return
+    if args.harvest_check:
+        print(json.dumps({"harvest_check": run_harvest_check(tn, torch, configs)}), flush=True)
         return
 
     t0 = time.perf_counter()
