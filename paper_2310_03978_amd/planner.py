@@ -1,0 +1,237 @@
+"""Contraction-tree refinement by simulated annealing, with dynamic slicing (host-side planning).
+
+Sec. 3.1 scores a contraction tree with log(T_cc + alpha T_mc) + beta log(T_sc): T_cc the
+compute cost of all pairwise steps (Eq. for T_cc, Sec. 2.4), T_mc their memory traffic (Eq. for
+T_mc), T_sc the size of the largest intermediate; alpha weighs bytes against flops for the
+hardware and beta the largest intermediate.  Its local update re-pairs the three nearest
+descendants of a vertex (for a vertex with children x and y = (a, b): ((x, a), b) or
+((x, b), a)), and a sweep visits every vertex from the root towards the leaves.  Here the
+sliced labels are given (Sec. 3.2's slicing is done by the caller) and the annealing keeps every
+intermediate under a memory cap.
+
+The trees come in and go out as the linear paths that tn_plan_create takes (pair (i, j): the
+result takes slot i).  Networks must have every label of extent 2 on exactly two tensors, or on
+one if it is open (the tensor networks of qubit circuits); a pairwise step then keeps exactly the
+labels of one operand only, so a vertex's label set is the XOR of its children's bitmasks.  Costs
+are per slice (sliced labels removed), which for a fixed slicing changes every score by the same
+constant.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from sortedcontainers import SortedList
+
+from paper_2310_03978_amd import costmodel
+
+# bytes -> flop-equivalents: the split-FP16 MFMA rate (three products) over the HBM bandwidth
+DEFAULT_ALPHA = costmodel.PEAK_SPLIT / costmodel.HBM_BW
+DEFAULT_BETA = 0.1
+
+
+class Tree:
+    """Binary contraction tree over n leaves; vertex ids: leaves 0..n-1, then internal ones."""
+
+    def __init__(self, labels, open_labels, path, sliced=()):
+        ids = sorted({l for lab in labels for l in lab})
+        self.bit = {l: i for i, l in enumerate(ids)}
+        counts = {}
+        for lab in labels:
+            for l in lab:
+                counts[l] = counts.get(l, 0) + 1
+        opened = set(open_labels)
+        for l, c in counts.items():
+            if c != (1 if l in opened else 2):
+                raise ValueError("every label must be on two tensors (one if open)")
+        self.n = len(labels)
+        self.leaf_mask = [self._mask(lab) for lab in labels]
+        self.set_sliced(sliced)
+        n = self.n
+        self.left, self.right, self.parent = {}, {}, {}
+        slot = list(range(n))            # slot -> vertex currently stored there
+        nxt = n
+        for i, j in path:
+            v = nxt
+            nxt += 1
+            self.left[v], self.right[v] = slot[i], slot[j]
+            self.parent[slot[i]] = v
+            self.parent[slot[j]] = v
+            slot[i] = v
+            slot[j] = -1
+        if nxt != 2 * n - 1:
+            raise ValueError("the path must contract all tensors into one")
+        self.root = nxt - 1
+        self.parent[self.root] = -1
+        self._recompute()
+
+    def _mask(self, labs):
+        m = 0
+        for l in labs:
+            m |= 1 << self.bit[l]
+        return m
+
+    def set_sliced(self, sliced):
+        self.sliced = list(sliced)
+        self.keep = ~self._mask(self.sliced)
+
+    # -- costs ---------------------------------------------------------------
+    def _size_log(self, m):
+        return (m & self.keep).bit_count()
+
+    def _vertex_costs(self, ml, mr):
+        """(T_cc, T_mc, log2 size of the result) of one pairwise step, per slice."""
+        lu, ll, lr, lc = (self._size_log(ml | mr), self._size_log(ml), self._size_log(mr),
+                          self._size_log(ml ^ mr))
+        return 8.0 * 2.0 ** lu, 8.0 * (2.0 ** ll + 2.0 ** lr + 2.0 ** lc), lc
+
+    def _recompute(self):
+        self.mask = {v: m for v, m in enumerate(self.leaf_mask)}
+        self.cc, self.mc, self.sc = {}, {}, {}
+        for v in range(self.n, 2 * self.n - 1):   # children have smaller ids than parents
+            ml, mr = self.mask[self.left[v]], self.mask[self.right[v]]
+            self.mask[v] = ml ^ mr
+            self.cc[v], self.mc[v], self.sc[v] = self._vertex_costs(ml, mr)
+        self.tcc = sum(self.cc.values())
+        self.tmc = sum(self.mc.values())
+        self.sizes = SortedList(self.sc.values())
+        self.leaf_max = max(self._size_log(m) for m in self.leaf_mask)
+
+    def tsc_log(self):
+        return max(self.sizes[-1] if self.sizes else 0, self.leaf_max)
+
+    def score(self, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA):
+        return math.log2(self.tcc + alpha * self.tmc) + beta * self.tsc_log()
+
+    # -- local updates ---------------------------------------------------------
+    def moves(self, v):
+        """Re-pairings at vertex v: (v, c, k) = make (other child of v, child k of c) a new
+        vertex and pair it with c's remaining child; c an internal child of v."""
+        out = []
+        for c in (self.left[v], self.right[v]):
+            if c >= self.n:
+                out.append((v, c, 0))
+                out.append((v, c, 1))
+        return out
+
+    def apply(self, v, c, k):
+        """Apply a move; returns the undo record.  With x the other child of v and c = (a, b):
+        k = 0 pairs (x, a) under c and leaves v = (c, b); k = 1 pairs (x, b), v = (c, a)."""
+        x = self.right[v] if self.left[v] == c else self.left[v]
+        a, b = self.left[c], self.right[c]
+        keep, move = (b, a) if k == 0 else (a, b)     # keep stays under v, move joins x
+        old = (self.left[v], self.right[v], self.left[c], self.right[c], self.mask[c],
+               self.cc[c], self.mc[c], self.sc[c], self.cc[v], self.mc[v])
+        self.left[c], self.right[c] = x, move
+        self.parent[x] = c
+        self.parent[move] = c
+        self.left[v], self.right[v] = c, keep
+        self.parent[keep] = v
+        self.parent[c] = v
+        self.tcc -= self.cc[c] + self.cc[v]
+        self.tmc -= self.mc[c] + self.mc[v]
+        self.sizes.remove(self.sc[c])
+        mx, mm = self.mask[x], self.mask[move]
+        self.mask[c] = mx ^ mm
+        self.cc[c], self.mc[c], self.sc[c] = self._vertex_costs(mx, mm)
+        self.cc[v], self.mc[v], _ = self._vertex_costs(self.mask[c], self.mask[keep])
+        self.tcc += self.cc[c] + self.cc[v]
+        self.tmc += self.mc[c] + self.mc[v]
+        self.sizes.add(self.sc[c])
+        return (v, c, old)
+
+    def undo(self, rec):
+        v, c, old = rec
+        lv, rv, lc, rc, mcm, ccc, mcc, scc, ccv, mcv = old
+        self.tcc += ccc + ccv - self.cc[c] - self.cc[v]
+        self.tmc += mcc + mcv - self.mc[c] - self.mc[v]
+        self.sizes.remove(self.sc[c])
+        self.sizes.add(scc)
+        self.left[v], self.right[v], self.left[c], self.right[c] = lv, rv, lc, rc
+        for ch in (lv, rv):
+            self.parent[ch] = v
+        for ch in (lc, rc):
+            self.parent[ch] = c
+        self.mask[c], self.cc[c], self.mc[c], self.sc[c], self.cc[v], self.mc[v] = mcm, ccc, mcc, scc, ccv, mcv
+
+    # -- paths -------------------------------------------------------------------
+    def path(self):
+        """The tree as a linear path; a vertex's result takes its left subtree's slot."""
+        out = []
+        slot = {}
+
+        def visit(v):
+            stack = [(v, False)]
+            while stack:
+                u, done = stack.pop()
+                if u < self.n:
+                    slot[u] = u
+                    continue
+                if done:
+                    i, j = slot[self.left[u]], slot[self.right[u]]
+                    out.append((i, j))
+                    slot[u] = i
+                else:
+                    stack.append((u, True))
+                    stack.append((self.right[u], False))
+                    stack.append((self.left[u], False))
+
+        visit(self.root)
+        return out
+
+    def sweep_order(self):
+        """Internal vertices from the root towards the leaves (breadth first)."""
+        order, frontier = [], [self.root]
+        while frontier:
+            nxt = []
+            for v in frontier:
+                if v >= self.n:
+                    order.append(v)
+                    nxt += [self.left[v], self.right[v]]
+            frontier = nxt
+        return order
+
+
+def anneal_tree(tree, sweeps=40, t_start=1e-4, t_end=1e-7, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, rng=None,
+                cap_log2=None):
+    """Metropolis sweeps at temperatures falling geometrically from t_start to t_end (score
+    units: log2 of flop-equivalents); moves that would make an intermediate larger than
+    2^cap_log2 are rejected.  Returns the best tree seen at the end of a sweep, as a path, and
+    its score."""
+    rng = rng if rng is not None else np.random.default_rng(0)
+    cur = tree.score(alpha, beta)
+    best, best_path = cur, tree.path()
+    for s in range(sweeps):
+        t = t_start * (t_end / t_start) ** (s / max(sweeps - 1, 1))
+        for v in tree.sweep_order():
+            mv = tree.moves(v)
+            if not mv:
+                continue
+            rec = tree.apply(*mv[int(rng.integers(len(mv)))])
+            if cap_log2 is not None and tree.tsc_log() > cap_log2:
+                tree.undo(rec)
+                continue
+            new = tree.score(alpha, beta)
+            if new <= cur or rng.random() < math.exp((cur - new) / t):
+                cur = new
+            else:
+                tree.undo(rec)
+        if cur < best - 1e-12:
+            best, best_path = cur, tree.path()
+    return best_path, best
+
+
+def refine(labels, open_labels, path, sliced=(), cap_log2=None, sweeps=40, t_start=1e-4, t_end=1e-7,
+           alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, seed=0):
+    """Anneal the contraction tree of `path` for the given sliced labels; with `cap_log2`, no
+    accepted tree has an intermediate above 2^cap_log2 (the input tree must fit).
+
+    Returns {"path", "score", "start_score", "tsc_log2", "tcc", "tmc"} (costs per slice)."""
+    tree = Tree(labels, open_labels, path, sliced)
+    if cap_log2 is not None and tree.tsc_log() > cap_log2:
+        raise ValueError("the input tree does not fit the cap")
+    start = tree.score(alpha, beta)
+    p, sc = anneal_tree(tree, sweeps, t_start, t_end, alpha, beta, np.random.default_rng(seed), cap_log2)
+    final = Tree(labels, open_labels, p, sliced)
+    return {"path": p, "score": sc, "start_score": start, "tsc_log2": final.tsc_log(), "tcc": final.tcc,
+            "tmc": final.tmc}

@@ -759,3 +759,17 @@ def test_lds_copy_512x64_layout_on_the_sparse_state(prec):
     rel = metrics.rel_l2(got, ref)
     print(f"sparse state on the 512-row layouts, {prec}: rel_l2 vs complex64 {rel:.2e}", flush=True)
     assert rel <= (1e-4 if prec == "f16x3" else 1e-3)
+
+
+@pytest.mark.parametrize("prec", ["c64", "f16x3"])
+def test_annealed_path_matches_oracle(prec):
+    """A tree refined by the annealer (Sec. 3.1) is an ordinary path for the library: its
+    amplitudes match the oracle's along the original greedy path."""
+    from paper_2310_03978_amd import planner
+    print(f"annealed path {prec}", flush=True)
+    circ, net, best = configs.build("rqc12")
+    ref = contract.amplitudes(net.tensors, net.labels, net.open_labels, best["path"])
+    r = planner.refine(net.labels, net.open_labels, best["path"], sweeps=20, seed=2)
+    assert r["path"] != list(best["path"])
+    got, _ = _gpu_amplitudes(net, r["path"], (), prec)
+    assert metrics.rel_l2(got, ref) <= TOL[prec]

@@ -1,0 +1,110 @@
+"""Contraction-tree annealing (Sec. 3.1 score and local update), checked against brute force
+over every tree of a small network, against the oracle's amplitudes along the refined path,
+and for self-consistency of its incremental costs."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import contract, metrics
+from paper_2310_03978_amd import planner
+from tn_inputs import configs
+from tn_inputs.paths import path_cost
+
+
+def _tiny_network():
+    """Six tensors on a ring with two chords, open labels on tensors 2 and 5 (all extents 2)."""
+    edges = [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5), (5, 0), (0, 3), (1, 4)]
+    labels = [[] for _ in range(6)]
+    for e, (a, b) in enumerate(edges):
+        labels[a].append(e)
+        labels[b].append(e)
+    labels[2].append(100)
+    labels[5].append(101)
+    return labels, [100, 101]
+
+
+def _all_trees(leaves):
+    if len(leaves) == 1:
+        yield leaves[0]
+        return
+    first, rest = leaves[0], leaves[1:]
+    for r in range(0, len(rest)):
+        for other in itertools.combinations(rest, r):
+            left = (first,) + other
+            right = tuple(x for x in rest if x not in other)
+            for tl in _all_trees(list(left)):
+                for tr in _all_trees(list(right)):
+                    yield (tl, tr)
+
+
+def _tree_path(tree):
+    out = []
+
+    def go(t):
+        if isinstance(t, int):
+            return t
+        i, j = go(t[0]), go(t[1])
+        out.append((i, j))
+        return i
+
+    go(tree)
+    return out
+
+
+def test_brute_force_minimum_is_reached():
+    labels, opened = _tiny_network()
+    trees = list(_all_trees(list(range(6))))
+    assert len(trees) == 945                      # (2n - 3)!! unordered binary trees on 6 leaves
+    scores = [planner.Tree(labels, opened, _tree_path(t)).score() for t in trees]
+    best = min(scores)
+    worst_tree = trees[int(np.argmax(scores))]
+    found = min(planner.refine(labels, opened, _tree_path(worst_tree), sweeps=300, t_start=1.0, t_end=1e-3,
+                               seed=s)["score"] for s in range(4))
+    assert found == pytest.approx(best, abs=1e-12)
+
+
+@pytest.mark.parametrize("workload", ["rqc12", "rqc30"])
+def test_tree_round_trip_keeps_costs(workload):
+    _, net, best = configs.build(workload)
+    t = planner.Tree(net.labels, net.open_labels, best["path"], best["sliced"])
+    ref = path_cost(net.labels, net.open_labels, net.extents(), best["path"], best["sliced"])
+    assert t.tcc == pytest.approx(ref["flops_per_slice"], rel=1e-12)
+    assert t.tsc_log() == ref["max_log2"]
+    again = path_cost(net.labels, net.open_labels, net.extents(), t.path(), best["sliced"])
+    assert again["flops_per_slice"] == pytest.approx(ref["flops_per_slice"], rel=1e-12)
+
+
+def test_incremental_costs_match_a_fresh_tree():
+    _, net, best = configs.build("rqc30")
+    t = planner.Tree(net.labels, net.open_labels, best["path"], best["sliced"])
+    rng = np.random.default_rng(3)
+    for _ in range(3000):
+        order = t.sweep_order()
+        mv = t.moves(order[int(rng.integers(len(order)))])
+        if not mv:
+            continue
+        rec = t.apply(*mv[int(rng.integers(len(mv)))])
+        if rng.random() < 0.3:
+            t.undo(rec)
+    fresh = planner.Tree(net.labels, net.open_labels, t.path(), best["sliced"])
+    assert t.tcc == pytest.approx(fresh.tcc, rel=1e-9)
+    assert t.tmc == pytest.approx(fresh.tmc, rel=1e-9)
+    assert t.tsc_log() == fresh.tsc_log()
+
+
+def test_refined_path_gives_the_same_amplitudes_and_respects_the_cap():
+    _, net, best = configs.build("rqc12")
+    cap = path_cost(net.labels, net.open_labels, net.extents(), best["path"])["max_log2"]
+    r = planner.refine(net.labels, net.open_labels, best["path"], cap_log2=cap, sweeps=20, seed=1)
+    assert r["score"] <= r["start_score"] and r["tsc_log2"] <= cap
+    a = contract.amplitudes(net.tensors, net.labels, net.open_labels, best["path"])
+    b = contract.amplitudes(net.tensors, net.labels, net.open_labels, r["path"])
+    assert metrics.rel_l2(b, a) <= 1e-12
+    with pytest.raises(ValueError):
+        planner.refine(net.labels, net.open_labels, best["path"], cap_log2=cap - 1)
+
+
+def test_only_two_tensor_bonds_are_accepted():
+    with pytest.raises(ValueError):
+        planner.Tree([[0, 1], [0], [0, 1]], [], [(0, 1), (0, 2)])
