@@ -5,9 +5,10 @@ compute cost of all pairwise steps (Eq. for T_cc, Sec. 2.4), T_mc their memory t
 T_mc), T_sc the size of the largest intermediate; alpha weighs bytes against flops for the
 hardware and beta the largest intermediate.  Its local update re-pairs the three nearest
 descendants of a vertex (for a vertex with children x and y = (a, b): ((x, a), b) or
-((x, b), a)), and a sweep visits every vertex from the root towards the leaves.  Here the
-sliced labels are given (Sec. 3.2's slicing is done by the caller) and the annealing keeps every
-intermediate under a memory cap.
+((x, b), a)), and a sweep visits every vertex from the root towards the leaves.  `refine`
+anneals a tree for given sliced labels, keeping every intermediate under a memory cap;
+`dynamic_slicing` (Sec. 3.2) cuts one bond at a time with a caller-supplied greedy slicer and
+re-anneals the tree after each cut until it fits.
 
 The trees come in and go out as the linear paths that tn_plan_create takes (pair (i, j): the
 result takes slot i).  Networks must have every label of extent 2 on exactly two tensors, or on
@@ -235,3 +236,28 @@ def refine(labels, open_labels, path, sliced=(), cap_log2=None, sweeps=40, t_sta
     final = Tree(labels, open_labels, p, sliced)
     return {"path": p, "score": sc, "start_score": start, "tsc_log2": final.tsc_log(), "tcc": final.tcc,
             "tmc": final.tmc}
+
+
+def dynamic_slicing(labels, open_labels, path, cap_log2, choose, tune_sweeps=30, final_sweeps=200,
+                    alpha=DEFAULT_ALPHA, seed=0):
+    """Sec. 3.2's dynamic slicing: cut bonds one at a time and re-anneal the tree after each
+    cut, until the largest intermediate is at most 2^cap_log2; then anneal under the cap.
+
+    `choose(path, k)` returns k labels to slice for the tree of `path` (a greedy slicer).
+    While the tree does not fit, the annealing weighs the largest intermediate fully
+    (beta = 1).  Returns {"path", "sliced", "score", "tsc_log2", "tcc", "tmc"}."""
+    sliced = []
+    for it in range(256):
+        sliced = list(choose(path, len(sliced) + 1))
+        if Tree(labels, open_labels, path, sliced).tsc_log() <= cap_log2:
+            break
+        path = refine(labels, open_labels, path, sliced, sweeps=tune_sweeps, beta=1.0, alpha=alpha,
+                      seed=seed + it)["path"]
+        if Tree(labels, open_labels, path, sliced).tsc_log() <= cap_log2:
+            break
+    else:
+        raise ValueError("no slicing of at most 256 bonds fits the cap")
+    r = refine(labels, open_labels, path, sliced, cap_log2=cap_log2, sweeps=final_sweeps, alpha=alpha,
+               seed=seed + 1000)
+    r["sliced"] = sliced
+    return r

@@ -108,3 +108,21 @@ def test_refined_path_gives_the_same_amplitudes_and_respects_the_cap():
 def test_only_two_tensor_bonds_are_accepted():
     with pytest.raises(ValueError):
         planner.Tree([[0, 1], [0], [0, 1]], [], [(0, 1), (0, 2)])
+
+
+def test_dynamic_slicing_fits_the_cap_and_keeps_the_amplitudes():
+    from tn_inputs.paths import choose_slices
+    _, net, best = configs.build("rqc12")
+    ext = net.extents()
+    cap = path_cost(net.labels, net.open_labels, ext, best["path"])["max_log2"] - 2
+
+    def choose(path, k):
+        return choose_slices(net.labels, net.open_labels, ext, path, cap, max_sliced=k)
+
+    r = planner.dynamic_slicing(net.labels, net.open_labels, best["path"], cap, choose, tune_sweeps=5,
+                                final_sweeps=10)
+    assert r["tsc_log2"] <= cap and len(r["sliced"]) >= 1
+    assert path_cost(net.labels, net.open_labels, ext, r["path"], r["sliced"])["max_log2"] <= cap
+    a = contract.amplitudes(net.tensors, net.labels, net.open_labels, best["path"])
+    b = contract.amplitudes(net.tensors, net.labels, net.open_labels, r["path"], r["sliced"])
+    assert metrics.rel_l2(b, a) <= 1e-12
