@@ -394,7 +394,7 @@ def run_slicing_choice(tn, torch, configs, workload, prec, n_candidates, n_timed
     candidate is then timed on the GPU (n_timed seeded slices at full size, the model's
     tiles) and its time extrapolated to all its slices (slices cost the same), so each
     ranking's pick and its rank agreement with the measurement can be compared.  Two more
-    candidates: the greedy slicing on the tree refined by the annealer (Sec. 3.1 score and
+    candidates: the greedy slicing on the tree refined by the annealer (Sec. 3.2 score and
     local updates, every intermediate kept under the cap), and Sec. 3.2's dynamic slicing
     (one bond at a time, the tree re-annealed after each cut), timed the same way."""
     from paper_2310_03978_amd import costmodel, planner

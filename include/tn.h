@@ -73,18 +73,35 @@ typedef struct {
   int32_t host_only;       /* 1 = plan on the host only: describe/steps work, contraction
                               calls return TN_E_STATE and no device memory is touched */
   int32_t split_policy;    /* 0 = split products on steps that are MFMA-bound, FP32 elsewhere;
-                              1 = split products on every MFMA step */
+                              1 = split products on every MFMA step;
+                              2 = split products on every step, small ones included, except steps
+                                  that read an intermediate of fewer than 4 elements (small
+                                  networks and tests that must exercise the split kernels) */
   int32_t record_steps;    /* 1 = time every step's main kernel launch with HIP events on the
                               plan's stream (read with tn_plan_step_times) */
-  int32_t tuning;          /* 0 = tile shapes from the shape heuristic; 1 = autotune: time every
-                              MFMA step with each tile shape at plan creation and keep the
-                              fastest (cached per step signature for the life of the process) */
-  int32_t reserved;
+  int32_t tuning;          /* 0 = tile shapes from the shape heuristic (m and n extents);
+                              1 = autotune: time every MFMA step with each tile shape at plan
+                                  creation and keep the fastest (cached per step signature for the
+                                  life of the process, and in tuning_cache when given);
+                              2 = learned model: every MFMA step takes the tile with the least
+                                  time predicted by cost_model (tn_plan_tune_with_model), which
+                                  then must be non-NULL; works on host-only plans too */
+  int32_t deterministic;   /* 0 or 1.  Every reduction of this library (K splits, cross-slice
+                              sums, gradient sums) runs in a fixed order, so results are bitwise
+                              reproducible run to run with either value; other values: TN_E_ARG */
   void* workspace;         /* caller-owned device memory for every device buffer of the plan (e.g.
                               a torch uint8 tensor), or NULL: the library allocates.  It must hold
                               the workspace_bytes a host-only plan of the same network reports, must
                               outlive the plan and is not freed by it.  Too small: TN_E_NOMEM. */
   int64_t workspace_bytes; /* size of workspace */
+  /* Fields below are read only when struct_size covers them (zero otherwise). */
+  const char* tuning_cache;          /* tuning = 1: path of a text file of measured tile choices
+                                        ("signature tile" lines).  Read before tuning, when it
+                                        exists; the choices of this plan are merged into it after
+                                        tuning.  Unreadable lines are ignored; a file that cannot
+                                        be written gives TN_E_ARG.  NULL = in-process cache only. */
+  struct tn_costmodel_s* cost_model; /* tuning = 2: the model that picks the tiles (borrowed for
+                                        the duration of tn_plan_create only) */
 } tn_options;
 
 /* Plan summary.  Operation counts follow Sec. 2.4: flops = 8*B*M*N*K per step

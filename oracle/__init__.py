@@ -8,7 +8,8 @@ calls it and shares no code with it.
 * ``naive``       -- explicit-loop contraction of tiny networks
 * ``statevector`` -- brute-force state-vector simulation of the circuit
 * ``metrics``     -- amplitude error measures (Sec. 4.3)
-* ``split``       -- hi/lo operand splitting of the extended-precision products (Sec. 4.2)
+* ``split``       -- hi/lo operand splitting and split dot products of the
+                     extended-precision products (Sec. 4.2)
 
 Pinned by tests/test_oracle_pins.py against the state vector, closed forms,
 normalisation, slicing and path invariance, and brute-force loops.

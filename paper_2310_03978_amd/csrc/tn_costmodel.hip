@@ -290,6 +290,7 @@ tn_status cm_upload(tn_costmodel_s* m, const float* X, const float* T, int64_t n
 extern "C" {
 
 tn_status tn_costmodel_create(tn_costmodel* out, int32_t n_features, uint64_t seed) {
+  TN_TRY
   if (!out || n_features < 1 || n_features > MAXF) return cm_fail(TN_E_ARG, "n_features must be in [1, 32]");
   *out = nullptr;
   tn_costmodel_s* m = new (std::nothrow) tn_costmodel_s();
@@ -321,33 +322,45 @@ tn_status tn_costmodel_create(tn_costmodel* out, int32_t n_features, uint64_t se
   }
   *out = m;
   return TN_OK;
+  TN_CATCH
 }
 
-void tn_costmodel_destroy(tn_costmodel m) { delete m; }
+void tn_costmodel_destroy(tn_costmodel m) {
+  TN_TRY_VOID
+  delete m;
+  TN_CATCH_VOID
+}
 
 tn_status tn_costmodel_describe(tn_costmodel m, int32_t* n_features, int32_t* hidden, int64_t* n_params) {
+  TN_TRY
   if (!m) return cm_fail(TN_E_ARG, "null model");
   if (n_features) *n_features = m->F;
   if (hidden) *hidden = H;
   if (n_params) *n_params = m->P;
   return TN_OK;
+  TN_CATCH
 }
 
 tn_status tn_costmodel_set_normalization(tn_costmodel m, const float* mean, const float* stdv) {
+  TN_TRY
   if (!m || !mean || !stdv) return cm_fail(TN_E_ARG, "null argument");
   for (int f = 0; f < m->F; ++f)
     if (!(stdv[f] > 0.f)) return cm_fail(TN_E_ARG, "std must be positive");
   tn_status st = cm_check(hipMemcpy(m->d_mean, mean, m->F * 4, hipMemcpyHostToDevice), "mean");
   if (!st) st = cm_check(hipMemcpy(m->d_std, stdv, m->F * 4, hipMemcpyHostToDevice), "std");
   return st;
+  TN_CATCH
 }
 
 tn_status tn_costmodel_get_params(tn_costmodel m, float* out, int64_t n) {
+  TN_TRY
   if (!m || !out || n != m->P) return cm_fail(TN_E_ARG, "n must equal the parameter count");
   return cm_check(hipMemcpy(out, m->d_p, n * 4, hipMemcpyDeviceToHost), "params");
+  TN_CATCH
 }
 
 tn_status tn_costmodel_set_params(tn_costmodel m, const float* in, int64_t n) {
+  TN_TRY
   if (!m || !in || n != m->P) return cm_fail(TN_E_ARG, "n must equal the parameter count");
   m->step = 0;
   std::vector<float> zeros(m->P, 0.f);
@@ -355,9 +368,11 @@ tn_status tn_costmodel_set_params(tn_costmodel m, const float* in, int64_t n) {
   if (!st) st = cm_check(hipMemcpy(m->d_m, zeros.data(), n * 4, hipMemcpyHostToDevice), "moments");
   if (!st) st = cm_check(hipMemcpy(m->d_v, zeros.data(), n * 4, hipMemcpyHostToDevice), "moments");
   return st;
+  TN_CATCH
 }
 
 tn_status tn_costmodel_predict(tn_costmodel m, const float* X, int64_t n, float* y) {
+  TN_TRY
   if (!m || (n > 0 && (!X || !y)) || n < 0) return cm_fail(TN_E_ARG, "bad arguments");
   if (n == 0) return TN_OK;
   tn_status st = cm_upload(m, X, nullptr, n);
@@ -367,10 +382,12 @@ tn_status tn_costmodel_predict(tn_costmodel m, const float* X, int64_t n, float*
                      m->d_std, m->d_p, nullptr, nullptr, nullptr, m->d_y);
   if ((st = cm_check(hipGetLastError(), "predict"))) return st;
   return cm_check(hipMemcpy(y, m->d_y, n * 4, hipMemcpyDeviceToHost), "predict copy");
+  TN_CATCH
 }
 
 tn_status tn_costmodel_gradient(tn_costmodel m, const float* X, const float* t, int64_t n, float* grad,
                                 float* loss) {
+  TN_TRY
   if (!m || !X || !t || n < 1) return cm_fail(TN_E_ARG, "bad arguments");
   tn_status st = cm_upload(m, X, t, n);
   if (!st) st = cm_reserve(m, n, n);
@@ -382,18 +399,22 @@ tn_status tn_costmodel_gradient(tn_costmodel m, const float* X, const float* t, 
   }
   if (!st && grad) st = cm_check(hipMemcpy(grad, m->d_g, m->P * 4, hipMemcpyDeviceToHost), "grad");
   return st;
+  TN_CATCH
 }
 
 tn_status tn_costmodel_adam_step(tn_costmodel m, const float* grad, int64_t n, float lr) {
+  TN_TRY
   if (!m || !grad || n != m->P) return cm_fail(TN_E_ARG, "bad arguments");
   tn_status st = cm_check(hipMemcpy(m->d_g, grad, n * 4, hipMemcpyHostToDevice), "grad");
   if (!st) st = cm_adam(m, lr);
   if (!st) st = cm_check(hipDeviceSynchronize(), "adam sync");
   return st;
+  TN_CATCH
 }
 
 tn_status tn_costmodel_train(tn_costmodel m, const float* X, const float* t, int64_t n, int32_t epochs,
                              int32_t batch, float lr, uint64_t seed, float* final_loss) {
+  TN_TRY
   if (!m || !X || !t || n < 1 || epochs < 0 || batch < 1) return cm_fail(TN_E_ARG, "bad arguments");
   tn_status st = cm_upload(m, X, t, n);
   if (!st) st = cm_reserve(m, std::max<int64_t>(batch, n), n);
@@ -424,6 +445,7 @@ tn_status tn_costmodel_train(tn_costmodel m, const float* X, const float* t, int
   }
   if (!st) st = cm_check(hipDeviceSynchronize(), "train sync");
   return st;
+  TN_CATCH
 }
 
 }  // extern "C"

@@ -109,3 +109,16 @@ struct ReduceArgs {
 // Detail text for tn_last_error_message() on the calling thread (defined with the planner).
 void tn_set_error_detail(const char* msg);
 
+// Exception barrier of the C entry points: no C++ exception crosses the ABI.  Called
+// inside a catch handler, tn_api_exception_status() records the detail and returns
+// TN_E_NOMEM for a failed or impossible host allocation, TN_E_STATE otherwise.
+int tn_api_exception_status() noexcept;
+#define TN_TRY try {
+#define TN_CATCH \
+  }              \
+  catch (...) { return (tn_status)tn_api_exception_status(); }
+#define TN_TRY_VOID try {
+#define TN_CATCH_VOID \
+  }                   \
+  catch (...) {}
+

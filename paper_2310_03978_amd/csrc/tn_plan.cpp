@@ -28,6 +28,8 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <set>
 #include <string>
 #include <vector>
@@ -48,6 +50,27 @@ tn_status fail(tn_status s, const std::string& msg) {
 }  // namespace
 
 void tn_set_error_detail(const char* msg) { g_err = msg ? msg : ""; }
+
+int tn_api_exception_status() noexcept {
+  int status = TN_E_STATE;
+  const char* what = "internal error";
+  try {
+    throw;
+  } catch (const std::bad_alloc&) {
+    status = TN_E_NOMEM;
+    what = "host memory allocation failed";
+  } catch (const std::length_error&) {
+    status = TN_E_NOMEM;
+    what = "requested host buffer is larger than the host can address";
+  } catch (...) {
+  }
+  try {
+    g_err = what;
+  } catch (...) {
+    g_err.clear();
+  }
+  return status;
+}
 
 namespace {
 
@@ -411,9 +434,34 @@ void set_tile(const tn_plan_s* p, Step& st, int tile) {
   st.scratch_elems = st.splits > 1 ? (int64_t(st.splits) << (bbits + mb + nb)) : 0;
 }
 
+// Tile id from the step's m and n bits (the shape heuristic).
+int heuristic_tile(int mb, int nb) {
+  if (nb >= 7 && mb >= 8) return TN_TILE_256x128;
+  if (nb >= 7 && mb >= 7) return TN_TILE_128x128;
+  if (mb >= 7) return TN_TILE_128x64;
+  return TN_TILE_64x64;
+}
+
+// split_policy 2: every step runs split products on the MFMA kernels, except steps that
+// read an intermediate of fewer than 4 elements (the split storage is blocked by 4)
+bool forced_split(const tn_plan_s* p, const Step& st) {
+  if (p->precision == TN_PREC_C64 || p->opts.split_policy != 2 || p->tensors.empty()) return false;
+  for (int x : {st.ta, st.tb}) {
+    const Tensor& T = p->tensors[x];
+    if (!T.leaf && T.elems < 4) return false;
+  }
+  return true;
+}
+
 void choose_kernel(tn_plan_s* p, Step& st) {
   const int bbits = (int)st.bb.size() + (st.per_slice ? p->s_bits : 0);
   const int mb = (int)st.mb.size(), nb = (int)st.nb.size(), kb = (int)st.kb.size();
+  if (forced_split(p, st)) {
+    st.kernel = p->precision == TN_PREC_F16X3 ? TN_K_MFMA_F16X3 : TN_K_MFMA_BF16X3;
+    st.dot = false;
+    set_tile(p, st, heuristic_tile(mb, nb));
+    return;
+  }
   const bool small = (kb <= 6 && bbits + mb + nb <= 14) || (bbits + mb + nb + kb <= 16);
   // batched dot products (at most 4 output elements per batch, K >= 2^10): an MFMA tile
   // would be almost empty; one block per output element splits K instead
@@ -431,12 +479,7 @@ void choose_kernel(tn_plan_s* p, Step& st) {
   }
   st.kernel = split_prec ? (p->precision == TN_PREC_F16X3 ? TN_K_MFMA_F16X3 : TN_K_MFMA_BF16X3)
                          : TN_K_MFMA_F32;
-  int tile;
-  if (nb >= 7 && mb >= 8) tile = TN_TILE_256x128;
-  else if (nb >= 7 && mb >= 7) tile = TN_TILE_128x128;
-  else if (mb >= 7) tile = TN_TILE_128x64;
-  else tile = TN_TILE_64x64;
-  set_tile(p, st, tile);
+  set_tile(p, st, heuristic_tile(mb, nb));
 }
 
 // Offset (elements) in tensor T of the open bonds' values for bitstring key `key`:
@@ -1433,7 +1476,45 @@ tn_status apply_tile(tn_plan_s* p, int s, int tile) {
                "desc upload");
 }
 
+// tuning_cache file: one "signature<TAB>tile" line per measured step signature.
+void load_tuning_cache(const char* path) {
+  FILE* f = fopen(path, "r");
+  if (!f) return;   // a missing file is an empty cache
+  char line[256];
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  while (fgets(line, sizeof(line), f)) {
+    char* tab = strchr(line, '\t');
+    if (!tab) continue;
+    *tab = 0;
+    char* end = nullptr;
+    const long tile = strtol(tab + 1, &end, 10);
+    if (end == tab + 1 || tile < 0 || tile >= TN_N_TILES) continue;
+    g_tune_cache[line] = (int)tile;
+  }
+  fclose(f);
+}
+
+tn_status save_tuning_cache(const char* path) {
+  std::map<std::string, int> all;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    all = g_tune_cache;
+  }
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return fail(TN_E_ARG, std::string("tuning_cache: cannot write ") + tmp);
+  bool ok = true;
+  for (const auto& kv : all) ok = ok && fprintf(f, "%s\t%d\n", kv.first.c_str(), kv.second) > 0;
+  ok = (fclose(f) == 0) && ok;
+  if (!ok || rename(tmp.c_str(), path) != 0) {
+    remove(tmp.c_str());
+    return fail(TN_E_ARG, std::string("tuning_cache: cannot write ") + path);
+  }
+  return TN_OK;
+}
+
 tn_status autotune(tn_plan_s* p) {
+  if (p->opts.tuning_cache) load_tuning_cache(p->opts.tuning_cache);
   hipEvent_t e0, e1;
   tn_status r = check(hipEventCreate(&e0), "event");
   if (r) return r;
@@ -1485,6 +1566,7 @@ tn_status autotune(tn_plan_s* p) {
   hipEventDestroy(e1);
   if (!r) r = check(hipStreamSynchronize(p->stream), "tuning sync");
   if (!r) r = validate_bounds(p);
+  if (!r && p->opts.tuning_cache) r = save_tuning_cache(p->opts.tuning_cache);
   return r;
 }
 
@@ -1590,11 +1672,15 @@ tn_status create_plan(tn_plan* out, int32_t n_tensors, const int32_t* ranks, con
       delete p;
       return fail(TN_E_ARG, "a sparse state needs at least one bitstring and one open label");
     }
+    if (n_open > 64) {
+      delete p;
+      return fail(TN_E_UNSUPPORTED, "a sparse state measures at most 64 open labels");
+    }
     p->sparse = true;
-    p->bkeys.resize(n_bitstrings);
+    p->bkeys.resize(n_bitstrings);   // may throw: the entry points turn that into TN_E_NOMEM
     for (int64_t i = 0; i < n_bitstrings; ++i) {
       uint64_t k = 0;
-      for (int32_t c = 0; c < n_open && c < 64; ++c) {
+      for (int32_t c = 0; c < n_open; ++c) {
         const uint8_t v = bitstrings[i * n_open + c];
         if (v > 1) {
           delete p;
@@ -1606,11 +1692,23 @@ tn_status create_plan(tn_plan* out, int32_t n_tensors, const int32_t* ranks, con
     }
   }
   if (opts) {
-    if (opts->struct_size < (int32_t)offsetof(tn_options, reserved)) {
+    if (opts->struct_size < (int32_t)offsetof(tn_options, deterministic)) {
       delete p;
       return fail(TN_E_ARG, "tn_options.struct_size too small");
     }
     memcpy(&p->opts, opts, std::min<size_t>(sizeof(tn_options), (size_t)opts->struct_size));
+  }
+  if (p->opts.deterministic != 0 && p->opts.deterministic != 1) {
+    delete p;
+    return fail(TN_E_ARG, "tn_options.deterministic must be 0 or 1");
+  }
+  if (p->opts.tuning < 0 || p->opts.tuning > 2 || (p->opts.tuning == 2 && !p->opts.cost_model)) {
+    delete p;
+    return fail(TN_E_ARG, "tn_options.tuning must be 0, 1 or 2 (2 needs cost_model)");
+  }
+  if (p->opts.split_policy < 0 || p->opts.split_policy > 2) {
+    delete p;
+    return fail(TN_E_ARG, "tn_options.split_policy must be 0, 1 or 2");
   }
   p->host_only = p->opts.host_only != 0;
   p->stream = reinterpret_cast<hipStream_t>(p->opts.stream);
@@ -1622,6 +1720,9 @@ tn_status create_plan(tn_plan* out, int32_t n_tensors, const int32_t* ranks, con
   g_err.clear();
   tn_status st = plan_build(p, n_tensors, ranks, labels, extents, data, n_open, open_labels, n_steps, path,
                             n_sliced, sliced_labels);
+  if (st == TN_OK && p->opts.tuning == 2) st = tn_plan_tune_with_model(p, p->opts.cost_model, nullptr, 0);
+  p->opts.cost_model = nullptr;   // borrowed for creation only
+  p->opts.tuning_cache = nullptr;
   if (st != TN_OK) {
     std::string keep = g_err;
     delete p;
@@ -1639,8 +1740,10 @@ tn_status tn_plan_create(tn_plan* out, int32_t n_tensors, const int32_t* ranks, 
                          const int64_t* const* extents, const double* const* data, int32_t n_open,
                          const int32_t* open_labels, int32_t n_steps, const int32_t* path, int32_t n_sliced,
                          const int32_t* sliced_labels, const tn_options* opts) {
+  TN_TRY
   return create_plan(out, n_tensors, ranks, labels, extents, data, n_open, open_labels, n_steps, path, n_sliced,
                      sliced_labels, 0, nullptr, opts);
+  TN_CATCH
 }
 
 tn_status tn_plan_create_sparse(tn_plan* out, int32_t n_tensors, const int32_t* ranks, const int32_t* const* labels,
@@ -1648,22 +1751,31 @@ tn_status tn_plan_create_sparse(tn_plan* out, int32_t n_tensors, const int32_t* 
                                 const int32_t* open_labels, int32_t n_steps, const int32_t* path, int32_t n_sliced,
                                 const int32_t* sliced_labels, int64_t n_bitstrings, const uint8_t* bitstrings,
                                 const tn_options* opts) {
+  TN_TRY
   if (!bitstrings) return fail(TN_E_ARG, "null bitstrings");
   return create_plan(out, n_tensors, ranks, labels, extents, data, n_open, open_labels, n_steps, path, n_sliced,
                      sliced_labels, n_bitstrings, bitstrings, opts);
+  TN_CATCH
 }
 
 tn_status tn_plan_sparse_index(tn_plan p, int64_t* index, int64_t n_bitstrings) {
+  TN_TRY
   if (!p || !index) return fail(TN_E_ARG, "null argument");
   if (!p->sparse) return fail(TN_E_STATE, "the plan has no sparse state");
   if (n_bitstrings != (int64_t)p->amp_index.size()) return fail(TN_E_ARG, "n_bitstrings does not match the plan");
   std::copy(p->amp_index.begin(), p->amp_index.end(), index);
   return TN_OK;
+  TN_CATCH
 }
 
-void tn_plan_destroy(tn_plan plan) { delete plan; }
+void tn_plan_destroy(tn_plan plan) {
+  TN_TRY_VOID
+  delete plan;
+  TN_CATCH_VOID
+}
 
 tn_status tn_plan_describe(tn_plan p, tn_plan_info* out) {
+  TN_TRY
   if (!p || !out) return fail(TN_E_ARG, "null argument");
   memset(out, 0, sizeof(*out));
   out->n_slices = p->n_slices;
@@ -1679,9 +1791,11 @@ tn_status tn_plan_describe(tn_plan p, tn_plan_info* out) {
   out->slice_batch = p->S;
   out->precision = p->precision;
   return TN_OK;
+  TN_CATCH
 }
 
 tn_status tn_plan_steps(tn_plan p, tn_step_info* steps, int32_t cap) {
+  TN_TRY
   if (!p || (!steps && cap > 0) || cap < 0) return fail(TN_E_ARG, "bad arguments");
   const int n = std::min<int>(cap, (int)p->steps.size());
   for (int i = 0; i < n; ++i) {
@@ -1715,9 +1829,11 @@ tn_status tn_plan_steps(tn_plan p, tn_step_info* steps, int32_t cap) {
     o.lds_copy = st.dma;
   }
   return TN_OK;
+  TN_CATCH
 }
 
 tn_status tn_plan_step_times(tn_plan p, double* ms_total, int64_t* launches, int32_t cap) {
+  TN_TRY
   if (!p || cap < 0) return fail(TN_E_ARG, "bad arguments");
   if (p->host_only || !p->opts.record_steps) return fail(TN_E_STATE, "step recording is off");
   tn_status st = check(hipStreamSynchronize(p->stream), "stream sync");
@@ -1741,17 +1857,21 @@ tn_status tn_plan_step_times(tn_plan p, double* ms_total, int64_t* launches, int
   std::fill(p->step_ms.begin(), p->step_ms.end(), 0.0);
   std::fill(p->step_launches.begin(), p->step_launches.end(), 0);
   return TN_OK;
+  TN_CATCH
 }
 
 tn_status tn_plan_step_features(tn_plan p, int32_t step, int32_t tile, float* out, int32_t cap) {
+  TN_TRY
   if (!p || !out || cap < TN_COST_FEATURES) return fail(TN_E_ARG, "bad arguments");
   if (step < 0 || step >= (int32_t)p->steps.size()) return fail(TN_E_ARG, "step out of range");
   if (tile < -1 || tile >= TN_N_TILES) return fail(TN_E_ARG, "tile id out of range");
   step_features(p, p->steps[step], tile, out);
   return TN_OK;
+  TN_CATCH
 }
 
 tn_status tn_plan_set_tile(tn_plan p, int32_t step, int32_t tile) {
+  TN_TRY
   if (!p) return fail(TN_E_ARG, "null plan");
   if (step < 0 || step >= (int32_t)p->steps.size()) return fail(TN_E_ARG, "step out of range");
   if (tile < 0 || tile >= TN_N_TILES) return fail(TN_E_ARG, "tile id out of range");
@@ -1759,9 +1879,11 @@ tn_status tn_plan_set_tile(tn_plan p, int32_t step, int32_t tile) {
   tn_status st = retile_step(p, step, tile);
   if (!st) st = validate_steps(p, p->steps);
   return st;
+  TN_CATCH
 }
 
 tn_status tn_plan_set_step_terms(tn_plan p, int32_t step, int32_t terms) {
+  TN_TRY
   if (!p) return fail(TN_E_ARG, "null plan");
   if (step < 0 || step >= (int32_t)p->steps.size()) return fail(TN_E_ARG, "step out of range");
   Step& st = p->steps[step];
@@ -1771,9 +1893,11 @@ tn_status tn_plan_set_step_terms(tn_plan p, int32_t step, int32_t terms) {
   if (st.terms != terms) ++p->epoch;
   st.terms = terms;
   return TN_OK;
+  TN_CATCH
 }
 
 tn_status tn_plan_tune_with_model(tn_plan p, tn_costmodel model, float* predicted_us, int32_t cap) {
+  TN_TRY
   if (!p || !model) return fail(TN_E_ARG, "null argument");
   int32_t nf = 0;
   tn_status st = tn_costmodel_describe(model, &nf, nullptr, nullptr);
@@ -1809,9 +1933,11 @@ tn_status tn_plan_tune_with_model(tn_plan p, tn_costmodel model, float* predicte
   if (!st && predicted_us)
     for (int s = 0; s < n && s < cap; ++s) predicted_us[s] = std::exp(best_y[s]);
   return st;
+  TN_CATCH
 }
 
 tn_status tn_contract_slices(tn_plan p, int64_t first, int64_t n) {
+  TN_TRY
   if (!p) return fail(TN_E_ARG, "null plan");
   if (p->host_only) return fail(TN_E_STATE, "host-only plan");
   if (first < 0 || n < 0 || first + n > p->n_slices) return fail(TN_E_SLICE, "slice range out of bounds");
@@ -1823,9 +1949,11 @@ tn_status tn_contract_slices(tn_plan p, int64_t first, int64_t n) {
   if (st) return st;
   p->slices_acc += n;
   return TN_OK;
+  TN_CATCH
 }
 
 tn_status tn_slice_partials(tn_plan p, const int64_t* ids, int64_t n, double* out) {
+  TN_TRY
   if (!p || (n > 0 && (!ids || !out)) || n < 0) return fail(TN_E_ARG, "bad arguments");
   if (p->host_only) return fail(TN_E_STATE, "host-only plan");
   for (int64_t i = 0; i < n; ++i)
@@ -1850,9 +1978,11 @@ tn_status tn_slice_partials(tn_plan p, const int64_t* ids, int64_t n, double* ou
   if (st) return st;
   if (flag) return fail(TN_E_NUMERIC, "Inf or NaN in a slice result");
   return TN_OK;
+  TN_CATCH
 }
 
 tn_status tn_amplitudes(tn_plan p, double* out, int64_t n_amp, int64_t* slices_accumulated) {
+  TN_TRY
   if (!p || !out) return fail(TN_E_ARG, "null argument");
   if (p->host_only) return fail(TN_E_STATE, "host-only plan");
   if (n_amp != p->n_amp) return fail(TN_E_ARG, "n_amp does not match the plan's output size");
@@ -1864,9 +1994,11 @@ tn_status tn_amplitudes(tn_plan p, double* out, int64_t n_amp, int64_t* slices_a
   if ((st = check(hipMemcpy(out, p->d_acc, n_amp * 16, hipMemcpyDeviceToHost), "accumulator copy"))) return st;
   if (slices_accumulated) *slices_accumulated = p->slices_acc;
   return TN_OK;
+  TN_CATCH
 }
 
 tn_status tn_accumulator_set(tn_plan p, const double* acc, int64_t n_amp, int64_t slices_accumulated) {
+  TN_TRY
   if (!p || !acc) return fail(TN_E_ARG, "null argument");
   if (p->host_only) return fail(TN_E_STATE, "host-only plan");
   if (n_amp != p->n_amp) return fail(TN_E_ARG, "n_amp does not match the plan's output size");
@@ -1876,9 +2008,11 @@ tn_status tn_accumulator_set(tn_plan p, const double* acc, int64_t n_amp, int64_
   if ((st = check(hipMemcpy(p->d_acc, acc, n_amp * 16, hipMemcpyHostToDevice), "accumulator copy"))) return st;
   p->slices_acc = slices_accumulated;
   return TN_OK;
+  TN_CATCH
 }
 
 tn_status tn_reset(tn_plan p) {
+  TN_TRY
   if (!p) return fail(TN_E_ARG, "null plan");
   if (p->host_only) return fail(TN_E_STATE, "host-only plan");
   tn_status st = check(hipMemsetAsync(p->d_acc, 0, p->n_amp * 16, p->stream), "reset");
@@ -1886,6 +2020,7 @@ tn_status tn_reset(tn_plan p) {
   if ((st = check(hipMemsetAsync(p->d_flag, 0, 4, p->stream), "reset"))) return st;
   p->slices_acc = 0;
   return check(hipStreamSynchronize(p->stream), "reset sync");
+  TN_CATCH
 }
 
 // ---------------------------------------------------------------------------
@@ -2076,6 +2211,7 @@ tn_status group_build(tn_group_s* G, const std::vector<int64_t>& key, tn_group_s
 extern "C" {
 
 tn_status tn_group_create(tn_group* out, const tn_plan* plans, int32_t n, const tn_options* opts) {
+  TN_TRY
   if (!out || !plans || n < 1) return fail(TN_E_ARG, "bad arguments");
   *out = nullptr;
   for (int i = 0; i < n; ++i) {
@@ -2085,7 +2221,7 @@ tn_status tn_group_create(tn_group* out, const tn_plan* plans, int32_t n, const 
     for (int j = 0; j < i; ++j)
       if (plans[j] == plans[i]) return fail(TN_E_ARG, "a plan appears twice in a group");
   }
-  if (opts && opts->struct_size < (int32_t)offsetof(tn_options, reserved))
+  if (opts && opts->struct_size < (int32_t)offsetof(tn_options, deterministic))
     return fail(TN_E_ARG, "tn_options.struct_size too small");
   tn_group_s* G = new (std::nothrow) tn_group_s();
   if (!G) return fail(TN_E_NOMEM, "host allocation failed");
@@ -2116,9 +2252,11 @@ tn_status tn_group_create(tn_group* out, const tn_plan* plans, int32_t n, const 
   }
   *out = G;
   return TN_OK;
+  TN_CATCH
 }
 
 tn_status tn_group_contract(tn_group G, const int64_t* first, const int64_t* count) {
+  TN_TRY
   if (!G || !first || !count) return fail(TN_E_ARG, "bad arguments");
   const int P = (int)G->plans.size();
   // graphs are cached per set of ranges and per plan configuration: a plan re-tiled since
@@ -2181,19 +2319,27 @@ tn_status tn_group_contract(tn_group G, const int64_t* first, const int64_t* cou
   if (st) return st;
   for (int i = 0; i < P; ++i) G->plans[i]->slices_acc += count[i];
   return TN_OK;
+  TN_CATCH
 }
 
 tn_status tn_group_describe(tn_group G, int64_t* n_kernels, int32_t* n_branches) {
+  TN_TRY
   if (!G) return fail(TN_E_ARG, "null group");
   if (n_kernels) *n_kernels = G->last_kernels;
   if (n_branches) *n_branches = G->last_branches;
   return TN_OK;
+  TN_CATCH
 }
 
-void tn_group_destroy(tn_group G) { delete G; }
+void tn_group_destroy(tn_group G) {
+  TN_TRY_VOID
+  delete G;
+  TN_CATCH_VOID
+}
 
 tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_t k, const void* A, const void* B,
                   void* C, void* stream) {
+  TN_TRY
   const int bb = ilog2_exact(batch), mb = ilog2_exact(m), nb = ilog2_exact(n), kb = ilog2_exact(k);
   if (!A || !B || !C) return fail(TN_E_ARG, "null pointer");
   if (bb < 0 || mb < 0 || nb < 0 || kb < 0) return fail(TN_E_UNSUPPORTED, "dimensions must be powers of two");
@@ -2296,10 +2442,12 @@ tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_
   tn_status r2 = check(hipStreamSynchronize(s), "gemm sync");
   hipFree(buf);
   return r ? r : r2;
+  TN_CATCH
 }
 
 tn_status tn_permute(int32_t rank, const int64_t* dims, const int32_t* perm, const void* in, void* out,
                      void* stream) {
+  TN_TRY
   if (rank < 0 || rank > 32 || (rank > 0 && (!dims || !perm)) || !in || !out) return fail(TN_E_ARG, "bad arguments");
   std::vector<int> nb(rank), bit0(rank);
   int total = 0;
@@ -2339,6 +2487,7 @@ tn_status tn_permute(int32_t rank, const int64_t* dims, const int32_t* perm, con
   tn_status r = permute_bits(in_pos, out_pos, in, out, s, d);
   hipFree(d);
   return r;
+  TN_CATCH
 }
 
 }  // extern "C"

@@ -1,6 +1,6 @@
 """Contraction-tree refinement by simulated annealing, with dynamic slicing (host-side planning).
 
-Sec. 3.1 scores a contraction tree with log(T_cc + alpha T_mc) + beta log(T_sc): T_cc the
+Sec. 3.2 scores a contraction tree with log(T_cc + alpha T_mc) + beta log(T_sc): T_cc the
 compute cost of all pairwise steps (Eq. for T_cc, Sec. 2.4), T_mc their memory traffic (Eq. for
 T_mc), T_sc the size of the largest intermediate; alpha weighs bytes against flops for the
 hardware and beta the largest intermediate.  Its local update re-pairs the three nearest

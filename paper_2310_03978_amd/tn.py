@@ -62,8 +62,9 @@ class tn_options(ctypes.Structure):
                 ("mem_cap_elems", ctypes.c_int64), ("stream", ctypes.c_void_p),
                 ("slice_batch", ctypes.c_int32), ("host_only", ctypes.c_int32),
                 ("split_policy", ctypes.c_int32), ("record_steps", ctypes.c_int32),
-                ("tuning", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64)]
+                ("tuning", ctypes.c_int32), ("deterministic", ctypes.c_int32),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64),
+                ("tuning_cache", ctypes.c_char_p), ("cost_model", ctypes.c_void_p)]
 
 
 class tn_plan_info(ctypes.Structure):
@@ -197,9 +198,11 @@ def _stream_handle(stream):
 def tn_plan_create(tensors, labels, open_labels, path, sliced_labels=(), precision="c64",
                    mem_cap_elems: int = 0, stream=None, slice_batch: int = 0,
                    host_only: bool = False, split_policy: int = 0, record_steps: bool = False,
-                   tuning: int = 0, workspace=None, bitstrings=None):
+                   tuning: int = 0, workspace=None, bitstrings=None, tuning_cache=None,
+                   cost_model=None, deterministic: int = 1):
     """Create a plan; returns an opaque handle (int).  Leaves are copied.  With bitstrings
-    (uint8 [count, n_open]) a sparse-state plan (tn_plan_create_sparse)."""
+    (uint8 [count, n_open]) a sparse-state plan (tn_plan_create_sparse).  tuning = 2 takes
+    the tiles from cost_model (a model handle)."""
     n = len(labels)
     ranks = (ctypes.c_int32 * n)(*[len(l) for l in labels])
     lab_arrays = [(ctypes.c_int32 * max(len(l), 1))(*l) for l in labels]
@@ -238,6 +241,9 @@ def tn_plan_create(tensors, labels, open_labels, path, sliced_labels=(), precisi
     opts.split_policy = int(split_policy)
     opts.record_steps = 1 if record_steps else 0
     opts.tuning = int(tuning)
+    opts.deterministic = int(deterministic)
+    opts.tuning_cache = None if tuning_cache is None else os.fsencode(tuning_cache)
+    opts.cost_model = cost_model
     if workspace is not None:   # a device tensor: its memory, caller-owned
         opts.workspace = int(workspace.data_ptr())
         opts.workspace_bytes = int(workspace.numel() * workspace.element_size())
@@ -508,25 +514,30 @@ def tn_permute(x, perm, out, stream=None):
 class Plan:
     """Owning wrapper around a plan handle.
 
-    tuning: 0 = tile shapes from the shape heuristic, 1 = measured autotuning at creation
-    (both in the library), 2 = tiles chosen by the learned step-time model shipped with the
-    package (loaded here and applied with tn_plan_tune_with_model)."""
+    tuning: 0 = tile shapes from the shape heuristic, 1 = measured autotuning at creation,
+    2 = tiles chosen by a learned step-time model (all in the library); for tuning = 2 the
+    model is ``cost_model`` (a CostModel or handle) or, when none is given, the model shipped
+    with the package."""
 
     handle = None
     sparse_index = None
 
     def __init__(self, tensors, labels, open_labels, path, sliced_labels=(), **kw):
-        learned = kw.get("tuning", 0) == 2
-        if learned:
-            kw["tuning"] = 0
         self.workspace = kw.get("workspace")   # kept alive for the plan's lifetime
-        self.handle = tn_plan_create(tensors, labels, open_labels, path, sliced_labels, **kw)
+        shipped = None
+        if kw.get("tuning", 0) == 2:
+            model = kw.get("cost_model")
+            if model is None:
+                from .costmodel import CostModel
+                shipped = model = CostModel.load()
+            kw["cost_model"] = getattr(model, "handle", model)
+        try:
+            self.handle = tn_plan_create(tensors, labels, open_labels, path, sliced_labels, **kw)
+        finally:
+            if shipped is not None:
+                shipped.close()
         bits = kw.get("bitstrings")
         self.sparse_index = None if bits is None else tn_plan_sparse_index(self.handle, len(bits))
-        if learned:
-            from .costmodel import CostModel
-            with CostModel.load() as model:
-                self.tune_with_model(model)
 
     def close(self):
         if self.handle:

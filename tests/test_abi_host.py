@@ -271,3 +271,108 @@ def test_sparse_plan_host_side():
     y = np.ones((2,), dtype=np.complex128)
     with pytest.raises(tn.TnError):
         tn.Plan([x, y], [(0, 1), (1,)], (0,), [(0, 1)], host_only=True, bitstrings=np.zeros((2, 1), np.uint8))
+
+
+def _raw_sparse_create(n_open, n_bitstrings, bits_buf, opts=None):
+    """tn_plan_create_sparse called directly: a 1-tensor network holding n_open open labels."""
+    import ctypes
+    P = ctypes.POINTER
+    ranks = (ctypes.c_int32 * 1)(n_open)
+    lab = (ctypes.c_int32 * n_open)(*range(n_open))
+    ext = (ctypes.c_int64 * n_open)(*([2] * n_open))
+    lab_pp = (P(ctypes.c_int32) * 1)(ctypes.cast(lab, P(ctypes.c_int32)))
+    ext_pp = (P(ctypes.c_int64) * 1)(ctypes.cast(ext, P(ctypes.c_int64)))
+    op = (ctypes.c_int32 * n_open)(*range(n_open))
+    pa = (ctypes.c_int32 * 1)(0)
+    sl = (ctypes.c_int32 * 1)(0)
+    if opts is None:
+        opts = tn.tn_options()
+        opts.struct_size = ctypes.sizeof(tn.tn_options)
+        opts.host_only = 1
+    h = ctypes.c_void_p()
+    st = tn._lib.tn_plan_create_sparse(ctypes.byref(h), 1, ranks, lab_pp, ext_pp, None, n_open, op, 0, pa, 0, sl,
+                                       n_bitstrings, ctypes.cast(bits_buf, P(ctypes.c_uint8)),
+                                       ctypes.byref(opts))
+    if st == 0:
+        tn.tn_plan_destroy(h.value)
+    return st, tn._lib.tn_last_error_message().decode()
+
+
+def test_huge_allocation_returns_a_status_instead_of_aborting():
+    """The C entry points never let a C++ exception cross the ABI: a request for more host
+    memory than exists (2^61 sampled bitstrings) fails with TN_E_NOMEM."""
+    import ctypes
+    buf = (ctypes.c_uint8 * 8)()
+    st, msg = _raw_sparse_create(2, 1 << 61, buf)
+    assert tn.STATUS[st] == "TN_E_NOMEM", (st, msg)
+    assert msg
+
+
+def test_sparse_state_rejects_more_than_64_measured_labels():
+    import ctypes
+    buf = (ctypes.c_uint8 * 65)()
+    st, msg = _raw_sparse_create(65, 1, buf)
+    assert tn.STATUS[st] == "TN_E_UNSUPPORTED", (st, msg)
+
+
+def test_option_values_are_validated():
+    circ, net, best = configs.build("rqc12")
+    for kw, name in ((dict(deterministic=2), "TN_E_ARG"), (dict(tuning=2), "TN_E_ARG"),
+                     (dict(tuning=3), "TN_E_ARG"), (dict(split_policy=3), "TN_E_ARG")):
+        with pytest.raises(tn.TnError) as e:
+            tn.tn_plan_create(net.tensors, net.labels, net.open_labels, best["path"], (),
+                              host_only=True, **kw)
+        assert e.value.name == name, kw
+    # deterministic 0 and 1 are both accepted (every reduction is fixed-order anyway)
+    for d in (0, 1):
+        h = tn.tn_plan_create(net.tensors, net.labels, net.open_labels, best["path"], (), host_only=True,
+                              deterministic=d)
+        tn.tn_plan_destroy(h)
+
+
+def test_options_of_an_older_struct_size_are_accepted():
+    """struct_size is the ABI version: a caller built before tuning_cache and cost_model
+    existed passes a shorter struct, and the library reads only what it covers."""
+    import ctypes
+    circ, net, best = configs.build("rqc12")
+    h = tn.tn_plan_create(net.tensors, net.labels, net.open_labels, best["path"], (), host_only=True)
+    tn.tn_plan_destroy(h)
+    opts = tn.tn_options()
+    opts.struct_size = tn.tn_options.tuning_cache.offset
+    opts.host_only = 1
+    opts.tuning = 0
+    opts.cost_model = 12345   # beyond struct_size: must not be read
+    ranks = (ctypes.c_int32 * 1)(1)
+    lab = (ctypes.c_int32 * 1)(0)
+    ext = (ctypes.c_int64 * 1)(2)
+    P = ctypes.POINTER
+    lab_pp = (P(ctypes.c_int32) * 1)(ctypes.cast(lab, P(ctypes.c_int32)))
+    ext_pp = (P(ctypes.c_int64) * 1)(ctypes.cast(ext, P(ctypes.c_int64)))
+    op = (ctypes.c_int32 * 1)(0)
+    out = ctypes.c_void_p()
+    st = tn._lib.tn_plan_create(ctypes.byref(out), 1, ranks, lab_pp, ext_pp, None, 1, op, 0, op, 0, op,
+                                ctypes.byref(opts))
+    assert st == 0, tn._lib.tn_last_error_message()
+    tn.tn_plan_destroy(out.value)
+    opts.struct_size = 8   # too short to hold the required fields
+    st = tn._lib.tn_plan_create(ctypes.byref(out), 1, ranks, lab_pp, ext_pp, None, 1, op, 0, op, 0, op,
+                                ctypes.byref(opts))
+    assert tn.STATUS[st] == "TN_E_ARG"
+
+
+def test_split_policy_2_puts_small_steps_on_split_kernels():
+    """split_policy 2: every step of the 12-qubit network whose intermediate operands hold at
+    least 4 elements runs a split kernel; the rest (and policies 0, 1) stay on FP32."""
+    circ, net, best = configs.build("rqc12")
+    for prec, kind in (("f16x3", 2), ("bf16x3", 3)):
+        kinds = {}
+        for pol in (0, 1, 2):
+            h = tn.tn_plan_create(net.tensors, net.labels, net.open_labels, best["path"], (), host_only=True,
+                                  precision=prec, split_policy=pol)
+            try:
+                kinds[pol] = [s["kernel"] for s in tn.tn_plan_steps(h)]
+            finally:
+                tn.tn_plan_destroy(h)
+        assert kind not in kinds[0] and kind not in kinds[1]
+        assert kinds[2].count(kind) >= 0.9 * len(kinds[2])
+        assert set(kinds[2]) <= {0, kind}

@@ -58,3 +58,21 @@ def test_forward_hand_computed_with_clipped_units():
     np.testing.assert_allclose(y, [5.0, 10.5], rtol=0, atol=1e-15)
     # and the loss against targets [4, 10.5] is ((5-4)^2 + 0) / 2
     assert mlp.loss(theta, np.array([[5.0], [-5.0]]), [4.0, 10.5], 1, 2, [1.0], [2.0]) == 0.5
+
+
+def test_adam_impulse_response_tells_beta1_from_beta2():
+    """A gradient g at step 1 and 0 at step 2.  Solving the moment recursions by hand:
+    m2 = b1 (1 - b1) g and v2 = b2 (1 - b2) g^2, so after bias correction
+    m2 / (1 - b1^2) = b1 g / (1 + b1) and v2 / (1 - b2^2) = b2 g^2 / (1 + b2); the second
+    step is lr * sign(g) * (b1 / (1 + b1)) / sqrt(b2 / (1 + b2)) (eps aside).  With
+    b1 = 0.9, b2 = 0.999 that factor is 0.67006; with the two rates swapped it would be
+    0.7261..., so the pin separates them (the first step, lr * sign(g), cannot)."""
+    b1, b2, lr = 0.9, 0.999, 0.01
+    g = np.array([2.5, -0.4])
+    th, m, v = mlp.adam(np.zeros(2), g, np.zeros(2), np.zeros(2), step=1, lr=lr)
+    th, m, v = mlp.adam(th, np.zeros(2), m, v, step=2, lr=lr)
+    factor = (b1 / (1 + b1)) / np.sqrt(b2 / (1 + b2))
+    assert abs(factor - 0.6700583) < 1e-6
+    np.testing.assert_allclose(th, -lr * np.sign(g) * (1 + factor), rtol=1e-6)
+    swapped = (b2 / (1 + b2)) / np.sqrt(b1 / (1 + b1))
+    assert abs(swapped - factor) > 0.05

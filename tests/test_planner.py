@@ -1,4 +1,4 @@
-"""Contraction-tree annealing (Sec. 3.1 score and local update), checked against brute force
+"""Contraction-tree annealing (Sec. 3.2 score and local update), checked against brute force
 over every tree of a small network, against the oracle's amplitudes along the refined path,
 and for self-consistency of its incremental costs."""
 import itertools
