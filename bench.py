@@ -230,34 +230,112 @@ def measured_traffic(kernel: str):
     return None
 
 
-def run_mixed_precision(tn, torch, net, best, prec, sample_ids, n_slices):
-    """Per-step precision (Sec. 4.3, Table 3): single products on the k split steps with the
-    most flops, three products elsewhere.  For each k: time of n_slices slices and the
-    partial amplitudes of the sampled slices (compared with the oracle afterwards)."""
+def run_mixed_precision(tn, torch, net, best, prec, sample_ids, n_slices, budgets):
+    """Per-step precision (Sec. 4.3, Table 3): single products on the top k split steps of
+    the library's ranking by measured time, three products elsewhere.  For each k: time of
+    n_slices slices and the partial amplitudes of the sampled slices (compared with the
+    oracle afterwards).  Then, for each epsilon_L2^2 budget, the library's own choice of k
+    (tn_plan_choose_single_products on the sampled slices, against its three-product
+    amplitudes) with the time of the chosen plan."""
     stream = torch.cuda.current_stream()
-    out = []
+    out, chosen = [], []
+
+    def timed(p):
+        p.contract(0, min(8, n_slices))
+        torch.cuda.synchronize()
+        s0 = torch.cuda.Event(enable_timing=True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        p.contract(0, n_slices)
+        e0.record(stream)
+        torch.cuda.synchronize()
+        p.reset()
+        return s0.elapsed_time(e0)
+
     with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best["sliced"],
                  precision=prec, stream=stream, tuning=2) as p:
-        n_split = sum(1 for s in p.steps() if s["kernel"] in (2, 3))
+        order = p.rank_split_steps(by_time=True)
+        n_split = len(order)
         ks = sorted({0, 1, 2, 4, 8, 16, n_split} & set(range(n_split + 1)))
         st = p.steps()
-        total = sum(s["flops"] * (p.describe()["n_slices"] if s["per_slice"] else 1)
-                    for s in st if s["kernel"] in (2, 3))
+        n_all = p.describe()["n_slices"]
+        total = sum(s["flops"] * (n_all if s["per_slice"] else 1) for s in st if s["kernel"] in (2, 3))
         for k in ks:
             top = p.single_product_top(k)
-            share = sum(st[i]["flops"] * (p.describe()["n_slices"] if st[i]["per_slice"] else 1)
-                        for i in top) / max(total, 1.0)
-            p.contract(0, min(8, n_slices))
+            share = sum(st[i]["flops"] * (n_all if st[i]["per_slice"] else 1) for i in top) / max(total, 1.0)
+            ms = timed(p)
+            out.append({"k": k, "split_flops_share": round(share, 4), "ms": round(ms, 3),
+                        "partial": p.partials(sample_ids)})
+        for budget in budgets:
+            t0 = time.perf_counter()
+            k, eps = p.choose_single_products(budget, sample_ids)
+            choose_s = time.perf_counter() - t0
+            ms = timed(p)
+            chosen.append({"budget": budget, "k": k, "eps_l2sq_vs_three_products": eps, "ms": round(ms, 3),
+                           "choose_s": round(choose_s, 2), "partial": p.partials(sample_ids)})
+    return out, chosen
+
+
+def run_precision_form(tn, torch, configs, n_timed, n_check, with_oracle_subcase):
+    """The precision form at its own size (53-qubit 6x9-minus-one lattice, 12 cycles, 512
+    correlated amplitudes, largest intermediate 2^30): split FP16, split BF16 and complex64
+    on the same slices.  Timing: n_timed consecutive slices from a seeded position (every
+    slice costs the same).  Errors: the split precisions' partial amplitudes of n_check
+    seeded slices (seed 303) against complex64's (no oracle slice of this network finishes
+    in minutes), and, when asked, the 30-qubit 12-cycle sub-case in every precision against
+    the oracle's stored amplitudes."""
+    from oracle import metrics
+    _, net, best = configs.build("rqc53d12")
+    n_slices = 1 << len(best["sliced"])
+    check = sample_slices(n_slices, n_check, 303)
+    first = sample_slices(n_slices, 1, 304)[0] & ~(n_timed - 1)
+    stream = torch.cuda.current_stream()
+    out = {"workload": configs.WORKLOADS["rqc53d12"].description, "slices_timed": n_timed,
+           "timed_range": [first, first + n_timed], "checked_slices": check, "n_slices": n_slices}
+    parts = {}
+    for prec in ("f16x3", "bf16x3", "c64"):
+        t0 = time.perf_counter()
+        with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best["sliced"], precision=prec,
+                     stream=stream, tuning=2) as p:
+            plan_s = time.perf_counter() - t0
+            info = p.describe()
+            parts[prec] = p.partials(check)
+            p.contract(first, min(n_timed, 2))   # warm-up
             torch.cuda.synchronize()
+            p.reset()
             s0 = torch.cuda.Event(enable_timing=True)
             e0 = torch.cuda.Event(enable_timing=True)
             s0.record(stream)
-            p.contract(0, n_slices)
+            p.contract(first, n_timed)
             e0.record(stream)
             torch.cuda.synchronize()
-            p.reset()
-            out.append({"k": k, "split_flops_share": round(share, 4), "ms": round(s0.elapsed_time(e0), 3),
-                        "partial": p.partials(sample_ids)})
+            ms = s0.elapsed_time(e0)
+        flops = info["flops_per_slice"] * n_timed + info["flops_invariant"]
+        out[prec] = {"ms_per_slice": round(ms / n_timed, 3), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+                     "slices_per_s": round(n_timed / (ms * 1e-3), 3), "plan_s": round(plan_s, 2)}
+        log(f"  precision form {prec}: {out[prec]}")
+    out["flops_per_slice"] = info["flops_per_slice"]
+    out["max_intermediate"] = info["max_intermediate"]
+    for prec in ("f16x3", "bf16x3"):
+        out[prec]["rel_l2_vs_c64"] = metrics.rel_l2(parts[prec], parts["c64"])
+        out[prec]["speedup_vs_c64"] = round(out["c64"]["ms_per_slice"] / out[prec]["ms_per_slice"], 3)
+    if with_oracle_subcase:
+        import importlib.util
+        path = os.path.join(ROOT, "tests", "golden", "make_rqc30d12_amplitudes.py")
+        spec = importlib.util.spec_from_file_location("make_rqc30d12_amplitudes", path)
+        fx = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(fx)
+        digest, ref = fx.read_fixture()
+        _, snet, sbest = configs.build("rqc30d12")
+        sub = {"workload": configs.WORKLOADS["rqc30d12"].description,
+               "fixture_matches_network": digest == fx.network_digest(snet, sbest)}
+        for prec in ("f16x3", "bf16x3", "c64"):
+            with tn.Plan(snet.tensors, snet.labels, snet.open_labels, sbest["path"], precision=prec,
+                         stream=stream) as p:
+                p.contract()
+                amps, _ = p.amplitudes()
+            sub[prec] = {k: float(v) for k, v in metrics.report(amps, ref).items()}
+        out["oracle_subcase_30q"] = sub
     return out
 
 
@@ -500,6 +578,16 @@ def cpu_baseline(net, best, ids, flops_slice):
             threads = max(blas)
     except Exception:
         pass
+    blas_threads = threads
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     t0 = time.perf_counter()
     refs = [contract.contract_slice(net.tensors, net.labels, net.open_labels, best["path"],
                                     best["sliced"], sid) for sid in ids]
@@ -507,6 +595,8 @@ def cpu_baseline(net, best, ids, flops_slice):
     n = len(ids)
     return np.asarray(refs), {
         "value": flops_slice * n / dt / 1e12, "unit": "TFLOPS", "cores": threads, "kind": "oracle",
+        "os_cpu_count": os.cpu_count(), "blas_threads": blas_threads, "cpu_model": model,
+        "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
         "slices_per_s": n / dt, "seconds": dt,
         "sample": f"{n} slices (seeded ids {ids}) of the same workload, complex128 numpy "
                   f"tensordot along the same path; flops counted as for the GPU"}
@@ -544,6 +634,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rqc30")
     ap.add_argument("--precisions", default="f16x3,c64")
+    ap.add_argument("--extra-precisions", default="bf16x3",
+                    help="more precisions on the same workload, timed with steps // 4 (at least 1)")
+    ap.add_argument("--precision-form-slices", type=int, default=8,
+                    help="timed slices per precision of the 53-qubit 12-cycle precision form (0 = skip)")
     ap.add_argument("--cpu-slices", type=int, default=8,
                     help="slices in the CPU oracle sample (and in the per-slice error check)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -608,6 +702,14 @@ def main():
         r = runs[prec]
         log(f"  {prec}: {r['ms_per_step']:.1f} ms/step, {r['tflops']:.1f} TFLOPS, "
             f"{r['slices_per_s']:.1f} slices/s")
+    for prec in [p for p in args.extra_precisions.split(",") if p and p not in runs]:
+        k = max(1, args.steps // 4)
+        log(f"running {prec}: warmup 1, steps {k}")
+        runs[prec] = run_precision(tn, torch, net, best, prec, k, 1, sample_ids, args.tuning)
+        runs[prec]["steps"] = k
+        r = runs[prec]
+        log(f"  {prec}: {r['ms_per_step']:.1f} ms/step, {r['tflops']:.1f} TFLOPS, "
+            f"{r['slices_per_s']:.1f} slices/s")
     head = precs[0]
     main_run = runs[head]
     info = main_run["info"]
@@ -644,7 +746,9 @@ def main():
     for prec, r in runs.items():
         out[prec] = {"tflops": round(r["tflops"], 3), "slices_per_s": round(r["slices_per_s"], 2),
                      "ms_per_step": round(r["ms_per_step"], 3),
-                     "plan_and_tuning_s": round(r["plan_s"], 3)}
+                     "plan_and_tuning_s": round(r["plan_s"], 3), "steps": r.get("steps", args.steps)}
+        if prec != "c64" and "c64" in runs:
+            out[prec]["speedup_vs_c64"] = round(runs["c64"]["ms_per_step"] / r["ms_per_step"], 3)
     if "c64" in runs and head != "c64":
         out["speedup_vs_c64"] = round(runs["c64"]["ms_per_step"] / main_run["ms_per_step"], 3)
         ref_c64 = runs["c64"]["amps"]
@@ -671,7 +775,11 @@ def main():
     mixed = None
     if args.mixed_precision and head != "c64":
         log(f"per-step precision: single products on the top-k split steps, {head}")
-        mixed = run_mixed_precision(tn, torch, net, best, head, sample_ids, 32)
+        mixed = run_mixed_precision(tn, torch, net, best, head, sample_ids, 32, (1e-5, 1e-4))
+    if args.precision_form_slices > 0:
+        log(f"precision form: rqc53d12, {args.precision_form_slices} timed slices per precision")
+        out["precision_form"] = run_precision_form(tn, torch, configs, args.precision_form_slices, 2,
+                                                   not args.no_cpu_baseline)
     if args.batching > 0:
         log(f"batching form: {args.batching} uneven circuits + {args.batching_slices} slices of "
             f"{args.batching_workload}")
@@ -685,10 +793,19 @@ def main():
         out["cpu_baseline"] = cb
         if mixed:
             # Table 3's trend: time and error against the oracle as single products spread
-            out["mixed_precision"] = {"precision": head, "slices_timed": 32, "sampled_slices": len(ref), "top_k": [
-                {"k": r["k"], "split_flops_share": r["split_flops_share"], "ms": r["ms"],
-                 "eps_l2sq": metrics.eps_l2sq(r["partial"], ref), "rel_l2": metrics.rel_l2(r["partial"], ref)}
-                for r in mixed]}
+            top, chosen = mixed
+            base_ms = top[0]["ms"]
+            out["mixed_precision"] = {
+                "precision": head, "slices_timed": 32, "sampled_slices": len(ref), "ranking": "measured time",
+                "top_k": [{"k": r["k"], "split_flops_share": r["split_flops_share"], "ms": r["ms"],
+                           "eps_l2sq": metrics.eps_l2sq(r["partial"], ref), "rel_l2": metrics.rel_l2(r["partial"], ref)}
+                          for r in top],
+                "budget_choice": [{"budget": c["budget"], "k": c["k"],
+                                   "eps_l2sq_vs_three_products": c["eps_l2sq_vs_three_products"],
+                                   "eps_l2sq_vs_oracle": metrics.eps_l2sq(c["partial"], ref),
+                                   "rel_l2_vs_oracle": metrics.rel_l2(c["partial"], ref), "ms": c["ms"],
+                                   "speedup_vs_three_products": round(base_ms / c["ms"], 3),
+                                   "choose_s": c["choose_s"]} for c in chosen]}
             log(f"  {out['mixed_precision']}")
         for prec, r in runs.items():
             # a11: errors of the sampled slices' amplitudes against the complex128 oracle

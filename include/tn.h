@@ -219,6 +219,27 @@ tn_status tn_plan_step_times(tn_plan plan, double* ms_total, int64_t* launches, 
  * step that does not run a split kernel or terms other than 1 and 3. */
 tn_status tn_plan_set_step_terms(tn_plan plan, int32_t step, int32_t terms);
 
+/* Split-precision steps ranked costliest first, into order[0 .. min(cap, *n_split)) (step
+ * indices; *n_split, may be NULL, receives their number).  by_time = 1 ranks by the time
+ * the steps take on one chunk of slices, measured with events on the plan's stream (Sec.
+ * 4.3 sorts contractions by actual computation time; device plans only, the accumulator
+ * is untouched); by_time = 0 by flops per contraction (slice-dependent steps counted once
+ * per slice).  Steps of equal cost keep their order. */
+tn_status tn_plan_rank_split_steps(tn_plan plan, int32_t by_time, int32_t* order, int32_t cap, int32_t* n_split);
+
+/* Per-step precision chosen under an error budget (Sec. 4.3, Table 3 and the equation for
+ * epsilon_L2^2).  The split steps are ranked by measured time (as tn_plan_rank_split_steps
+ * with by_time = 1).  The per-slice amplitudes of slice_ids[0 .. n_ids) are computed with
+ * three products on every step (the reference), then with one product (hi * hi) on the
+ * top k steps for growing k (1, 2, 3, 4, 6, 9, ..., every split step), each time with
+ * epsilon_L2^2 = |L2^2 - L2^2'| / L2^2 over all those amplitudes.  The largest k reached
+ * before the first k whose epsilon_L2^2 exceeds `budget` is kept: the plan leaves this call
+ * with one product on its top k steps and three elsewhere (*k_chosen = k, 0 if even k = 1
+ * exceeds the budget; *eps_l2sq = its epsilon_L2^2; either may be NULL).  The accumulator
+ * is untouched.  TN_E_STATE for host-only plans and plans without split steps. */
+tn_status tn_plan_choose_single_products(tn_plan plan, double budget, const int64_t* slice_ids, int64_t n_ids,
+                                         int32_t* k_chosen, double* eps_l2sq);
+
 /* Contract slices [first_slice, first_slice + n_slices) and ADD their amplitudes into the
  * plan's FP64 accumulator, summing in increasing slice id (Sec. 3.2, Sec. 5: sub-task
  * results are summed).  Asynchronous on opts.stream; slice-independent steps are computed
@@ -236,6 +257,28 @@ tn_status tn_slice_partials(tn_plan plan, const int64_t* slice_ids, int64_t n, d
  * of slices added since the last reset.  TN_E_NUMERIC if Inf/NaN reached a slice result,
  * TN_E_DEVICE if a kernel failed. */
 tn_status tn_amplitudes(tn_plan plan, double* out, int64_t n_amp, int64_t* slices_accumulated);
+
+/* Verification statistics of the accumulated amplitudes (Sec. 2.2 LXEB; Sec. 4.3 LXEB
+ * through the squared norm; Sec. 5.1 Porter-Thomas histogram), computed on the GPU in FP64.
+ * The samples are the plan's bitstrings for a sparse-state plan (a repeated bitstring counts
+ * each time), else every amplitude of the accumulator; sample i has p_i = |a_i|^2 (the
+ * accumulator is taken as is: the caller divides by nothing and contracts every slice
+ * first).  With D = 2^n_qubits and m samples:
+ *   sum_p = sum p_i, sum_p2 = sum p_i^2 (fixed-order sums), mean_dp = D sum_p / m,
+ *   mean_dp2 = D^2 sum_p2 / m, lxeb = mean_dp - 1 (F_l of the sampled LXEB equation).
+ * hist (n_bins int64 on the host, may be NULL when n_bins = 0) counts x = log(D p_i) in
+ * n_bins equal bins over [x_lo, x_hi); samples below x_lo (p = 0 included) go to the first
+ * bin, samples at or above x_hi to the last.  Synchronises the plan's stream; allocates and
+ * frees about 8 m + 16 m / 256 + 8 n_bins bytes of device memory.  TN_E_NUMERIC if Inf/NaN
+ * reached a slice result. */
+typedef struct {
+  int64_t samples;
+  double sum_p, sum_p2;
+  double mean_dp, mean_dp2;
+  double lxeb;
+} tn_xeb_stats;
+tn_status tn_plan_xeb(tn_plan plan, int32_t n_qubits, int32_t n_bins, double x_lo, double x_hi,
+                      tn_xeb_stats* stats, int64_t* hist);
 
 /* Restore an accumulator (checkpoint resume): acc is n_amp complex128 on the host. */
 tn_status tn_accumulator_set(tn_plan plan, const double* acc, int64_t n_amp,

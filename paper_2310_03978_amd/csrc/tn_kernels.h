@@ -67,6 +67,9 @@ struct BatchTask {
 hipError_t tn_launch_batch(const BatchTask* tasks, const int32_t* block_task, int64_t blocks, hipStream_t s);
 hipError_t tn_launch_slice_reduce(const ReduceArgs& r, hipStream_t s);
 hipError_t tn_launch_absmax(const void* x, int64_t n, uint32_t* dst, hipStream_t s);
+// part: 2 * ceil(m / 256) doubles; hist: nbins zeroed counters; out: 2 doubles (sum p, sum p^2)
+hipError_t tn_launch_xeb(const double* acc, const int64_t* idx, int64_t m, double log_d, int32_t nbins, double x_lo,
+                         double x_hi, double* part, unsigned long long* hist, double* out, hipStream_t s);
 hipError_t tn_launch_fill_u32(void* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t tn_launch_scale_pow2(void* x, int64_t n, const int32_t* e, hipStream_t s);
 void tn_tile_shape(int tile, int* bm, int* bn, int* threads);

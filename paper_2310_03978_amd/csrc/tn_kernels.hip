@@ -21,6 +21,8 @@
 //  k_permute<V>       LDS-staged index permutation, coalesced on both sides.
 //  k_slice_reduce     FP64 cross-slice sum in increasing slice order.
 //  k_batch            element-wise launches of many plans as one kernel (groups).
+//  k_xeb_blocks / k_xeb_final  LXEB sums and the Porter-Thomas histogram of the
+//                     FP64 amplitudes (verification, Sec. 2.2 and Sec. 5.1).
 //
 // The complex product is a real GEMM on stacked blocks: A is read as the real
 // matrix [Ar Ai] (M x 2K, the interleaved complex storage itself), B is expanded
@@ -1202,6 +1204,62 @@ __device__ void slice_reduce_block(const ReduceArgs& r, int64_t block) {
 
 __global__ __launch_bounds__(256) void k_slice_reduce(ReduceArgs r) { slice_reduce_block(r, blockIdx.x); }
 
+// ---------------------------------------------------------------------------
+// Verification statistics (LXEB, Porter-Thomas histogram) of the FP64 amplitudes:
+// sample i has probability p_i = |acc[idx ? idx[i] : i]|^2; each block sums p and p^2
+// of its samples in a fixed tree order into part[block][0..1] and counts x = log(D p)
+// into histogram bins (integer atomics: the counts do not depend on order);
+// k_xeb_final adds the block sums in block order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_xeb_blocks(const double* __restrict__ acc, const int64_t* __restrict__ idx,
+                                                    int64_t m, double log_d, int32_t nbins, double x_lo,
+                                                    double inv_width, double* __restrict__ part,
+                                                    unsigned long long* __restrict__ hist) {
+  __shared__ double s1[256], s2[256];
+  const int t = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 256 + t;
+  double p = 0.0;
+  if (i < m) {
+    const int64_t j = idx ? idx[i] : i;
+    const double re = acc[2 * j], im = acc[2 * j + 1];
+    p = re * re + im * im;
+    if (nbins > 0) {
+      const double x = p > 0.0 ? log(p) + log_d : -INFINITY;
+      const double fb = (x - x_lo) * inv_width;
+      int64_t b;
+      if (!(fb < (double)nbins)) b = nbins - 1;   // above the range (and NaN)
+      else if (!(fb >= 0.0)) b = 0;               // below the range (and p = 0)
+      else b = (int64_t)fb;
+      atomicAdd(hist + b, 1ull);
+    }
+  }
+  s1[t] = p;
+  s2[t] = p * p;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      s1[t] += s1[t + w];
+      s2[t] += s2[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[2 * blockIdx.x] = s1[0];
+    part[2 * blockIdx.x + 1] = s2[0];
+  }
+}
+
+__global__ void k_xeb_final(const double* __restrict__ part, int64_t blocks, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double a = 0.0, b = 0.0;
+  for (int64_t k = 0; k < blocks; ++k) {
+    a += part[2 * k];
+    b += part[2 * k + 1];
+  }
+  out[0] = a;
+  out[1] = b;
+}
+
 // max(|re|, |im|) over a buffer, as float bits
 __global__ __launch_bounds__(256) void k_absmax(const float2* __restrict__ x, int64_t n, uint32_t* dst) {
   __shared__ uint32_t red[8];
@@ -1326,6 +1384,19 @@ hipError_t tn_launch_batch(const BatchTask* tasks, const int32_t* block_task, in
 hipError_t tn_launch_slice_reduce(const ReduceArgs& r, hipStream_t s) {
   const int64_t blocks = (r.n_amp + 255) / 256;
   hipLaunchKernelGGL(k_slice_reduce, dim3((unsigned)blocks), dim3(256), 0, s, r);
+  return hipGetLastError();
+}
+
+hipError_t tn_launch_xeb(const double* acc, const int64_t* idx, int64_t m, double log_d, int32_t nbins, double x_lo,
+                         double x_hi, double* part, unsigned long long* hist, double* out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const int64_t blocks = (m + 255) / 256;
+  const double inv_width = nbins > 0 ? nbins / (x_hi - x_lo) : 0.0;
+  hipLaunchKernelGGL(k_xeb_blocks, dim3((unsigned)blocks), dim3(256), 0, s, acc, idx, m, log_d, nbins, x_lo,
+                     inv_width, part, hist);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_xeb_final, dim3(1), dim3(64), 0, s, part, blocks, out);
   return hipGetLastError();
 }
 

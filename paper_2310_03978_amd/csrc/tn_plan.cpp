@@ -1936,26 +1936,13 @@ tn_status tn_plan_tune_with_model(tn_plan p, tn_costmodel model, float* predicte
   TN_CATCH
 }
 
-tn_status tn_contract_slices(tn_plan p, int64_t first, int64_t n) {
-  TN_TRY
-  if (!p) return fail(TN_E_ARG, "null plan");
-  if (p->host_only) return fail(TN_E_STATE, "host-only plan");
-  if (first < 0 || n < 0 || first + n > p->n_slices) return fail(TN_E_SLICE, "slice range out of bounds");
-  if (n == 0) return TN_OK;
-  std::vector<Launch> ls;
-  invariant_launches(p, p->steps, p->d_desc, ls);
-  for (auto& c : chunks_of(p, first, n)) chunk_launches(p, p->steps, p->d_desc, c.first, c.second, nullptr, ls);
-  tn_status st = execute(p, ls);
-  if (st) return st;
-  p->slices_acc += n;
-  return TN_OK;
-  TN_CATCH
-}
+}  // extern "C"
 
-tn_status tn_slice_partials(tn_plan p, const int64_t* ids, int64_t n, double* out) {
-  TN_TRY
-  if (!p || (n > 0 && (!ids || !out)) || n < 0) return fail(TN_E_ARG, "bad arguments");
-  if (p->host_only) return fail(TN_E_STATE, "host-only plan");
+namespace {
+
+// Per-slice amplitudes of the given slices, true scale, complex128 interleaved, on the
+// host (the accumulator is untouched).  Synchronous.
+tn_status partials_to_host(tn_plan_s* p, const int64_t* ids, int64_t n, double* out) {
   for (int64_t i = 0; i < n; ++i)
     if (ids[i] < 0 || ids[i] >= p->n_slices) return fail(TN_E_SLICE, "slice id out of range");
   if (n == 0) return TN_OK;
@@ -1978,6 +1965,141 @@ tn_status tn_slice_partials(tn_plan p, const int64_t* ids, int64_t n, double* ou
   if (st) return st;
   if (flag) return fail(TN_E_NUMERIC, "Inf or NaN in a slice result");
   return TN_OK;
+}
+
+// Time of every step's launches over one chunk of slices (the plan's chunk size, from
+// slice 0), measured with events on the plan's stream; the chunk's amplitudes go to the
+// partials buffer, so the accumulator is untouched.  Records of the caller's own step
+// timing (options.record_steps) are kept aside meanwhile.
+tn_status measure_step_ms(tn_plan_s* p, std::vector<double>& ms) {
+  std::vector<tn_plan_s::Timing> keep;
+  keep.swap(p->pending);
+  const int keep_rec = p->opts.record_steps;
+  p->opts.record_steps = 1;
+  std::vector<Launch> ls;
+  invariant_launches(p, p->steps, p->d_desc, ls);
+  chunk_launches(p, p->steps, p->d_desc, 0, p->s_bits, p->d_part, ls);
+  tn_status st = execute(p, ls);
+  p->opts.record_steps = keep_rec;
+  if (!st) st = check(hipStreamSynchronize(p->stream), "timing sync");
+  ms.assign(p->steps.size(), 0.0);
+  for (auto& t : p->pending) {
+    float x = 0.f;
+    if (!st) st = check(hipEventElapsedTime(&x, t.start, t.stop), "event elapsed");
+    ms[t.step] += x;
+    p->event_pool.push_back({t.start, t.stop});
+  }
+  p->pending.swap(keep);
+  return st;
+}
+
+// The split-precision steps, costliest first (Sec. 4.3 ranks contractions by their
+// actual computation time): by measured time over one chunk, or by flops per
+// contraction (slice-dependent steps count once per slice).  Ties keep step order.
+tn_status rank_split_steps(tn_plan_s* p, bool by_time, std::vector<int>& rank) {
+  std::vector<double> cost(p->steps.size(), 0.0);
+  if (by_time) {
+    tn_status st = measure_step_ms(p, cost);
+    if (st) return st;
+  } else {
+    for (size_t i = 0; i < p->steps.size(); ++i)
+      cost[i] = p->steps[i].flops * (p->steps[i].per_slice ? (double)p->n_slices : 1.0);
+  }
+  rank.clear();
+  for (size_t i = 0; i < p->steps.size(); ++i)
+    if (p->steps[i].kernel == TN_K_MFMA_F16X3 || p->steps[i].kernel == TN_K_MFMA_BF16X3) rank.push_back((int)i);
+  std::stable_sort(rank.begin(), rank.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  return TN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tn_status tn_contract_slices(tn_plan p, int64_t first, int64_t n) {
+  TN_TRY
+  if (!p) return fail(TN_E_ARG, "null plan");
+  if (p->host_only) return fail(TN_E_STATE, "host-only plan");
+  if (first < 0 || n < 0 || first + n > p->n_slices) return fail(TN_E_SLICE, "slice range out of bounds");
+  if (n == 0) return TN_OK;
+  std::vector<Launch> ls;
+  invariant_launches(p, p->steps, p->d_desc, ls);
+  for (auto& c : chunks_of(p, first, n)) chunk_launches(p, p->steps, p->d_desc, c.first, c.second, nullptr, ls);
+  tn_status st = execute(p, ls);
+  if (st) return st;
+  p->slices_acc += n;
+  return TN_OK;
+  TN_CATCH
+}
+
+tn_status tn_slice_partials(tn_plan p, const int64_t* ids, int64_t n, double* out) {
+  TN_TRY
+  if (!p || (n > 0 && (!ids || !out)) || n < 0) return fail(TN_E_ARG, "bad arguments");
+  if (p->host_only) return fail(TN_E_STATE, "host-only plan");
+  return partials_to_host(p, ids, n, out);
+  TN_CATCH
+}
+
+tn_status tn_plan_rank_split_steps(tn_plan p, int32_t by_time, int32_t* order, int32_t cap, int32_t* n_split) {
+  TN_TRY
+  if (!p || cap < 0 || (cap > 0 && !order)) return fail(TN_E_ARG, "bad arguments");
+  if (by_time && p->host_only) return fail(TN_E_STATE, "ranking by measured time needs a device plan");
+  std::vector<int> rank;
+  tn_status st = rank_split_steps(p, by_time != 0, rank);
+  if (st) return st;
+  for (int i = 0; i < cap && i < (int)rank.size(); ++i) order[i] = rank[i];
+  if (n_split) *n_split = (int32_t)rank.size();
+  return TN_OK;
+  TN_CATCH
+}
+
+tn_status tn_plan_choose_single_products(tn_plan p, double budget, const int64_t* ids, int64_t n_ids,
+                                         int32_t* k_chosen, double* eps_l2sq) {
+  TN_TRY
+  if (!p || !ids || n_ids < 1 || !(budget >= 0.0)) return fail(TN_E_ARG, "bad arguments");
+  if (p->host_only) return fail(TN_E_STATE, "host-only plan");
+  for (int64_t i = 0; i < n_ids; ++i)
+    if (ids[i] < 0 || ids[i] >= p->n_slices) return fail(TN_E_SLICE, "slice id out of range");
+  std::vector<int> rank;
+  tn_status st = rank_split_steps(p, true, rank);
+  if (st) return st;
+  if (rank.empty()) return fail(TN_E_STATE, "the plan has no split-precision step");
+  auto set_top = [&](int k) {
+    for (size_t i = 0; i < rank.size(); ++i) {
+      Step& s = p->steps[rank[i]];
+      const int terms = (int)i < k ? 1 : 3;
+      if (s.terms != terms) ++p->epoch;
+      s.terms = terms;
+    }
+  };
+  // reference: three products on every step
+  set_top(0);
+  const size_t len = (size_t)(2 * p->n_amp * n_ids);
+  std::vector<double> ref(len), cur(len);
+  if ((st = partials_to_host(p, ids, n_ids, ref.data()))) return st;
+  double l2_ref = 0.0;
+  for (double x : ref) l2_ref += x * x;
+  int best_k = 0;
+  double best_eps = 0.0;
+  const int n_split = (int)rank.size();
+  for (int k = 1; k <= n_split;) {
+    set_top(k);
+    if ((st = partials_to_host(p, ids, n_ids, cur.data()))) break;
+    double l2 = 0.0;
+    for (double x : cur) l2 += x * x;
+    const double eps = l2_ref > 0.0 ? std::fabs(l2 - l2_ref) / l2_ref : 0.0;
+    if (!(eps <= budget)) break;
+    best_k = k;
+    best_eps = eps;
+    if (k == n_split) break;
+    // candidate k grow by about 1.5x (1, 2, 3, 4, 6, 9, ...), always ending at n_split
+    k = std::min(n_split, std::max(k + 1, (k * 3) / 2));
+  }
+  set_top(best_k);
+  if (st) return st;
+  if (k_chosen) *k_chosen = best_k;
+  if (eps_l2sq) *eps_l2sq = best_eps;
+  return TN_OK;
   TN_CATCH
 }
 
@@ -1993,6 +2115,61 @@ tn_status tn_amplitudes(tn_plan p, double* out, int64_t n_amp, int64_t* slices_a
   if (flag) return fail(TN_E_NUMERIC, "Inf or NaN reached a slice result");
   if ((st = check(hipMemcpy(out, p->d_acc, n_amp * 16, hipMemcpyDeviceToHost), "accumulator copy"))) return st;
   if (slices_accumulated) *slices_accumulated = p->slices_acc;
+  return TN_OK;
+  TN_CATCH
+}
+
+tn_status tn_plan_xeb(tn_plan p, int32_t n_qubits, int32_t n_bins, double x_lo, double x_hi, tn_xeb_stats* stats,
+                      int64_t* hist) {
+  TN_TRY
+  if (!p || !stats || n_qubits < 0 || n_qubits > 1000 || n_bins < 0 || n_bins > (1 << 20) ||
+      (n_bins > 0 && (!hist || !(x_hi > x_lo))))
+    return fail(TN_E_ARG, "bad arguments");
+  if (p->host_only) return fail(TN_E_STATE, "host-only plan");
+  tn_status st = check(hipStreamSynchronize(p->stream), "stream sync");
+  if (st) return st;
+  int32_t flag = 0;
+  if ((st = check(hipMemcpy(&flag, p->d_flag, 4, hipMemcpyDeviceToHost), "flag copy"))) return st;
+  if (flag) return fail(TN_E_NUMERIC, "Inf or NaN reached a slice result");
+  // samples: one per bitstring of a sparse-state plan (repeats count again), else every amplitude
+  const int64_t m = p->sparse ? (int64_t)p->amp_index.size() : p->n_amp;
+  const int64_t blocks = (m + 255) / 256;
+  const size_t idx_bytes = p->sparse ? (size_t)m * 8 : 0;
+  const size_t part_bytes = (size_t)blocks * 16, hist_bytes = (size_t)n_bins * 8;
+  char* buf = nullptr;
+  if (hipMalloc((void**)&buf, idx_bytes + part_bytes + hist_bytes + 16) != hipSuccess) {
+    hipGetLastError();
+    return fail(TN_E_NOMEM, "xeb buffers: device allocation failed");
+  }
+  int64_t* d_idx = p->sparse ? reinterpret_cast<int64_t*>(buf) : nullptr;
+  double* d_part = reinterpret_cast<double*>(buf + idx_bytes);
+  unsigned long long* d_hist = reinterpret_cast<unsigned long long*>(buf + idx_bytes + part_bytes);
+  double* d_out = reinterpret_cast<double*>(buf + idx_bytes + part_bytes + hist_bytes);
+  if (d_idx) st = check(hipMemcpyAsync(d_idx, p->amp_index.data(), idx_bytes, hipMemcpyHostToDevice, p->stream),
+                        "index upload");
+  if (!st && n_bins > 0) st = check(tn_launch_fill_u32(d_hist, 0, (int64_t)n_bins * 2, p->stream), "hist clear");
+  const double log_d = n_qubits * std::log(2.0);
+  if (!st)
+    st = check(tn_launch_xeb(p->d_acc, d_idx, m, log_d, n_bins, x_lo, x_hi, d_part, d_hist, d_out, p->stream),
+               "xeb kernels");
+  double sums[2] = {0.0, 0.0};
+  std::vector<unsigned long long> h(n_bins);
+  if (!st) st = check(hipMemcpyAsync(sums, d_out, 16, hipMemcpyDeviceToHost, p->stream), "xeb copy");
+  if (!st && n_bins > 0)
+    st = check(hipMemcpyAsync(h.data(), d_hist, hist_bytes, hipMemcpyDeviceToHost, p->stream), "hist copy");
+  tn_status st2 = check(hipStreamSynchronize(p->stream), "xeb sync");
+  hipFree(buf);
+  if (st) return st;
+  if (st2) return st2;
+  const double D = std::ldexp(1.0, n_qubits);
+  memset(stats, 0, sizeof(*stats));
+  stats->samples = m;
+  stats->sum_p = sums[0];
+  stats->sum_p2 = sums[1];
+  stats->mean_dp = m > 0 ? D * sums[0] / (double)m : 0.0;
+  stats->mean_dp2 = m > 0 ? D * D * sums[1] / (double)m : 0.0;
+  stats->lxeb = stats->mean_dp - 1.0;
+  for (int i = 0; i < n_bins; ++i) hist[i] = (int64_t)h[i];
   return TN_OK;
   TN_CATCH
 }
@@ -2337,20 +2514,36 @@ void tn_group_destroy(tn_group G) {
   TN_CATCH_VOID
 }
 
-tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_t k, const void* A, const void* B,
-                  void* C, void* stream) {
-  TN_TRY
-  const int bb = ilog2_exact(batch), mb = ilog2_exact(m), nb = ilog2_exact(n), kb = ilog2_exact(k);
+}  // extern "C"
+
+namespace {
+
+// The product C = A B of tn_gemm, planned as one contraction step with row-major
+// operands (batch bits on top).
+struct GemmPlan {
+  tn_plan_s tmp;
+  Step st;
+  int bb = 0, mb = 0, nb = 0, kb = 0;
+  size_t desc_bytes = 0, slot_bytes = 256, scratch_bytes = 0;
+  size_t total_bytes() const { return desc_bytes + slot_bytes + scratch_bytes; }
+};
+
+tn_status gemm_plan(GemmPlan& G, int32_t precision, int64_t batch, int64_t m, int64_t n, int64_t k, const void* A,
+                    const void* B, void* C) {
+  G.bb = ilog2_exact(batch);
+  G.mb = ilog2_exact(m);
+  G.nb = ilog2_exact(n);
+  G.kb = ilog2_exact(k);
+  const int bb = G.bb, mb = G.mb, nb = G.nb, kb = G.kb;
   if (!A || !B || !C) return fail(TN_E_ARG, "null pointer");
   if (bb < 0 || mb < 0 || nb < 0 || kb < 0) return fail(TN_E_UNSUPPORTED, "dimensions must be powers of two");
   if (precision < 0 || precision > 2) return fail(TN_E_ARG, "unknown precision");
   if (bb > 16 || mb > 30 || nb > 30 || kb > 30 || bb + mb + nb > 34) return fail(TN_E_UNSUPPORTED, "too large");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  tn_plan_s tmp;
+  tn_plan_s& tmp = G.tmp;
+  Step& st = G.st;
   tmp.precision = precision;
   tmp.opts.split_policy = 1;
   tmp.host_only = true;
-  Step st;
   for (int j = 0; j < bb; ++j) st.bb.push_back(j);
   for (int j = 0; j < mb; ++j) st.mb.push_back(bb + j);
   for (int j = 0; j < nb; ++j) st.nb.push_back(bb + mb + j);
@@ -2382,18 +2575,23 @@ tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_
   if (tile_env && st.kernel != TN_K_SMALL) set_tile(&tmp, st, atoi(tile_env) % TN_N_TILES);
   build_desc(&tmp, st);
   // device scratch: desc, max/exp slots, split partials
-  const size_t desc_bytes = (sizeof(GettDesc) + 255) & ~size_t(255);
-  const size_t slot_bytes = 256;
-  const size_t scratch_bytes = st.scratch_elems * 8;
-  char* buf = nullptr;
-  if (hipMalloc((void**)&buf, desc_bytes + slot_bytes + scratch_bytes) != hipSuccess) {
-    hipGetLastError();
-    return fail(TN_E_NOMEM, "scratch allocation failed");
-  }
+  G.desc_bytes = (sizeof(GettDesc) + 255) & ~size_t(255);
+  G.scratch_bytes = st.kernel != TN_K_SMALL && st.splits > 1 ? (size_t)st.scratch_elems * 8 : 0;
+  return TN_OK;
+}
+
+// Issue the product on stream s with `buf` (device, G.total_bytes()) as its scratch:
+// the descriptor, the max / exponent slots (cleared by a fill kernel) and the K-split
+// partials.  Asynchronous.
+tn_status gemm_issue(const GemmPlan& G, int32_t precision, const void* A, const void* B, void* C, char* buf,
+                     hipStream_t s) {
+  const Step& st = G.st;
+  const int bb = G.bb, mb = G.mb, nb = G.nb, kb = G.kb;
+  const int64_t batch = int64_t(1) << bb, m = int64_t(1) << mb, n = int64_t(1) << nb, k = int64_t(1) << kb;
   GettDesc* dd = reinterpret_cast<GettDesc*>(buf);
-  uint32_t* slots = reinterpret_cast<uint32_t*>(buf + desc_bytes);  // maxA maxB maxC expA expB expC
+  uint32_t* slots = reinterpret_cast<uint32_t*>(buf + G.desc_bytes);  // maxA maxB maxC expA expB expC
   tn_status r = check(hipMemcpyAsync(dd, &st.desc, sizeof(GettDesc), hipMemcpyHostToDevice, s), "desc");
-  if (!r) r = check(hipMemsetAsync(slots, 0, slot_bytes, s), "slots");
+  if (!r) r = check(tn_launch_fill_u32(slots, 0, (int64_t)(G.slot_bytes / 4), s), "slots");
   GettArgs g;
   memset(&g, 0, sizeof(g));
   g.A = reinterpret_cast<const float*>(A);
@@ -2425,7 +2623,7 @@ tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_
       g.tiles_n_bits = st.tiles_n_bits;
       const int64_t blocks = int64_t(st.splits) << (st.tiles_m_bits + st.tiles_n_bits + bb);
       if (st.splits > 1) {
-        g.scratch = reinterpret_cast<float*>(buf + desc_bytes + slot_bytes);
+        g.scratch = reinterpret_cast<float*>(buf + G.desc_bytes + G.slot_bytes);
         g.write_scratch = 1;
         r = check(tn_launch_gett(st.kernel, st.tile, d, g, blocks, s), "gemm");
         g.write_scratch = 0;
@@ -2439,6 +2637,26 @@ tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_
   }
   if (!r && precision != 0)
     r = check(tn_launch_scale_pow2(C, batch * m * n, reinterpret_cast<int32_t*>(slots + 5), s), "rescale");
+  return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_t k, const void* A, const void* B,
+                  void* C, void* stream) {
+  TN_TRY
+  GemmPlan G;
+  tn_status r = gemm_plan(G, precision, batch, m, n, k, A, B, C);
+  if (r) return r;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* buf = nullptr;
+  if (hipMalloc((void**)&buf, G.total_bytes()) != hipSuccess) {
+    hipGetLastError();
+    return fail(TN_E_NOMEM, "scratch allocation failed");
+  }
+  r = gemm_issue(G, precision, A, B, C, buf, s);
   tn_status r2 = check(hipStreamSynchronize(s), "gemm sync");
   hipFree(buf);
   return r ? r : r2;

@@ -40,7 +40,8 @@ EXPORTED = ["tn_plan_create", "tn_plan_create_sparse", "tn_plan_sparse_index", "
             "tn_plan_step_times", "tn_contract_slices", "tn_slice_partials", "tn_amplitudes", "tn_accumulator_set",
             "tn_reset", "tn_group_create", "tn_group_contract", "tn_group_describe",
             "tn_group_destroy", "tn_plan_step_features", "tn_plan_set_tile", "tn_plan_set_step_terms",
-            "tn_plan_tune_with_model", "tn_costmodel_create", "tn_costmodel_destroy",
+            "tn_plan_tune_with_model", "tn_plan_rank_split_steps", "tn_plan_choose_single_products",
+            "tn_plan_xeb", "tn_costmodel_create", "tn_costmodel_destroy",
             "tn_costmodel_describe", "tn_costmodel_set_normalization", "tn_costmodel_get_params",
             "tn_costmodel_set_params", "tn_costmodel_predict", "tn_costmodel_gradient",
             "tn_costmodel_adam_step", "tn_costmodel_train", "tn_gemm", "tn_permute",
@@ -74,6 +75,11 @@ class tn_plan_info(ctypes.Structure):
                 ("bytes_per_slice", ctypes.c_double), ("bytes_invariant", ctypes.c_double),
                 ("max_intermediate", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("slice_batch", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class tn_xeb_stats(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_int64), ("sum_p", ctypes.c_double), ("sum_p2", ctypes.c_double),
+                ("mean_dp", ctypes.c_double), ("mean_dp2", ctypes.c_double), ("lxeb", ctypes.c_double)]
 
 
 class tn_step_info(ctypes.Structure):
@@ -119,6 +125,9 @@ _lib.tn_slice_partials.restype = ctypes.c_int
 _lib.tn_amplitudes.argtypes = [ctypes.c_void_p, _P(ctypes.c_double), ctypes.c_int64,
                                _P(ctypes.c_int64)]
 _lib.tn_amplitudes.restype = ctypes.c_int
+_lib.tn_plan_xeb.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                             _P(tn_xeb_stats), _P(ctypes.c_int64)]
+_lib.tn_plan_xeb.restype = ctypes.c_int
 _lib.tn_accumulator_set.argtypes = [ctypes.c_void_p, _P(ctypes.c_double), ctypes.c_int64,
                                     ctypes.c_int64]
 _lib.tn_accumulator_set.restype = ctypes.c_int
@@ -143,6 +152,12 @@ _lib.tn_plan_set_step_terms.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.
 _lib.tn_plan_set_step_terms.restype = ctypes.c_int
 _lib.tn_plan_tune_with_model.argtypes = [ctypes.c_void_p, ctypes.c_void_p, _F32P, ctypes.c_int32]
 _lib.tn_plan_tune_with_model.restype = ctypes.c_int
+_lib.tn_plan_rank_split_steps.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_int32), ctypes.c_int32,
+                                          _P(ctypes.c_int32)]
+_lib.tn_plan_rank_split_steps.restype = ctypes.c_int
+_lib.tn_plan_choose_single_products.argtypes = [ctypes.c_void_p, ctypes.c_double, _P(ctypes.c_int64),
+                                                ctypes.c_int64, _P(ctypes.c_int32), _P(ctypes.c_double)]
+_lib.tn_plan_choose_single_products.restype = ctypes.c_int
 _lib.tn_costmodel_create.argtypes = [_P(ctypes.c_void_p), ctypes.c_int32, ctypes.c_uint64]
 _lib.tn_costmodel_create.restype = ctypes.c_int
 _lib.tn_costmodel_destroy.argtypes = [ctypes.c_void_p]
@@ -321,6 +336,15 @@ def tn_amplitudes(plan):
     return out, count.value
 
 
+def tn_plan_xeb(plan, n_qubits: int, n_bins: int = 0, x_lo: float = -6.0, x_hi: float = 3.0):
+    """(stats dict, histogram int64 array) of the accumulated amplitudes (tn_plan_xeb)."""
+    st = tn_xeb_stats()
+    hist = np.zeros(max(int(n_bins), 1), dtype=np.int64)
+    _check(_lib.tn_plan_xeb(plan, int(n_qubits), int(n_bins), float(x_lo), float(x_hi), ctypes.byref(st),
+                            hist.ctypes.data_as(_P(ctypes.c_int64)) if n_bins > 0 else None))
+    return {name: getattr(st, name) for name, _ in tn_xeb_stats._fields_}, hist[:n_bins]
+
+
 def tn_accumulator_set(plan, acc, slices_accumulated: int):
     acc = np.ascontiguousarray(np.asarray(acc, dtype=np.complex128))
     _check(_lib.tn_accumulator_set(plan, acc.view(np.float64).ctypes.data_as(_P(ctypes.c_double)),
@@ -416,6 +440,23 @@ def tn_plan_set_tile(plan, step: int, tile: int):
 
 def tn_plan_set_step_terms(plan, step: int, terms: int):
     _check(_lib.tn_plan_set_step_terms(plan, int(step), int(terms)))
+
+
+def tn_plan_rank_split_steps(plan, by_time: bool) -> list:
+    n = tn_plan_describe(plan)["n_steps"]
+    order = (ctypes.c_int32 * max(n, 1))()
+    count = ctypes.c_int32()
+    _check(_lib.tn_plan_rank_split_steps(plan, 1 if by_time else 0, order, n, ctypes.byref(count)))
+    return [int(order[i]) for i in range(count.value)]
+
+
+def tn_plan_choose_single_products(plan, budget: float, slice_ids):
+    """(k, eps_l2sq): the plan keeps single products on its top k split steps."""
+    ids = np.ascontiguousarray(np.asarray(slice_ids, dtype=np.int64))
+    k, eps = ctypes.c_int32(), ctypes.c_double()
+    _check(_lib.tn_plan_choose_single_products(plan, float(budget), ids.ctypes.data_as(_P(ctypes.c_int64)),
+                                               len(ids), ctypes.byref(k), ctypes.byref(eps)))
+    return k.value, eps.value
 
 
 def tn_plan_tune_with_model(plan, model) -> np.ndarray:
@@ -575,6 +616,10 @@ class Plan:
     def step_times(self):
         return tn_plan_step_times(self.handle)
 
+    def xeb(self, n_qubits, n_bins=0, x_lo=-6.0, x_hi=3.0):
+        """LXEB statistics and the Porter-Thomas histogram of the accumulated amplitudes."""
+        return tn_plan_xeb(self.handle, n_qubits, n_bins, x_lo, x_hi)
+
     def partials(self, ids):
         out = tn_slice_partials(self.handle, ids)
         if self.sparse_index is not None:
@@ -596,16 +641,21 @@ class Plan:
     def set_step_terms(self, step, terms):
         tn_plan_set_step_terms(self.handle, step, terms)
 
-    def single_product_top(self, k):
-        """Run the k split steps with the most flops per contraction (per-slice steps count
-        once per slice) as hi*hi only, the others as three products; returns their indices."""
-        st = self.steps()
-        n = self.describe()["n_slices"]
-        split = [i for i, s in enumerate(st) if s["kernel"] in (2, 3)]
-        top = sorted(split, key=lambda i: -st[i]["flops"] * (n if st[i]["per_slice"] else 1))[:k]
-        for i in split:
-            tn_plan_set_step_terms(self.handle, i, 1 if i in top else 3)
-        return top
+    def rank_split_steps(self, by_time=True):
+        """Split steps costliest first (measured time, or flops per contraction)."""
+        return tn_plan_rank_split_steps(self.handle, by_time)
+
+    def single_product_top(self, k, by_time=True):
+        """Run the top k split steps of the library's ranking as hi*hi only, the others as
+        three products; returns their indices."""
+        order = self.rank_split_steps(by_time)
+        for i, s in enumerate(order):
+            tn_plan_set_step_terms(self.handle, s, 1 if i < k else 3)
+        return order[:k]
+
+    def choose_single_products(self, budget, slice_ids):
+        """Largest top-k set of single-product steps under an epsilon_L2^2 budget: (k, eps)."""
+        return tn_plan_choose_single_products(self.handle, budget, slice_ids)
 
     def tune_with_model(self, model):
         """Tile every MFMA step by the model's predicted time; returns predicted us per step."""

@@ -220,7 +220,12 @@ def test_step_terms_setting_and_errors():
             p.set_step_terms(other[0], 1)
         with pytest.raises(tn.TnError):
             p.set_step_terms(len(st), 1)
-        top = p.single_product_top(2)
+        order = p.rank_split_steps(by_time=False)
+        assert sorted(order) == split
+        assert [st[i]["flops"] for i in order] == sorted((st[i]["flops"] for i in split), reverse=True)
+        with pytest.raises(tn.TnError):   # measured ranking needs a device plan
+            p.rank_split_steps(by_time=True)
+        top = p.single_product_top(2, by_time=False)
         costs = sorted((st[i]["flops"] for i in split), reverse=True)
         assert sorted((st[i]["flops"] for i in top), reverse=True) == costs[:2]
         after = p.steps()

@@ -690,11 +690,52 @@ def test_single_product_on_top_steps_trend():
             got, _ = p.amplitudes()
             if k == 0:
                 assert np.array_equal(got, base)
-            errs.append(metrics.eps_l2sq(got, ref))
-            print(f"top-{k} of {n_split} split steps single: eps_l2^2 {errs[-1]:.3e} rel_l2 {metrics.rel_l2(got, ref):.3e}",
-                  flush=True)
+            errs.append(metrics.rel_l2(got, ref))
+            print(f"top-{k} of {n_split} split steps single: eps_l2^2 {metrics.eps_l2sq(got, ref):.3e} "
+                  f"rel_l2 {errs[-1]:.3e}", flush=True)
+            # one fp16 product per step: each operand rounded to 11 significant bits (relative
+            # 2^-12), so a step adds about 2^-11.5 relative error; k such steps add in
+            # quadrature at most sqrt(k) times that (bound doubled)
+            bound = TOL["f16x3"] / 100 if k == 0 else 2 * 2.0 ** -11.5 * np.sqrt(k)
+            assert errs[-1] <= bound, (k, errs[-1], bound)
     assert errs[-1] > errs[0]
-    assert metrics.rel_l2(got, ref) <= 2e-2
+
+
+@pytest.mark.parametrize("budget", [1e-6, 1e-4])
+def test_single_products_chosen_under_a_budget(budget):
+    """Per-step precision chosen by the library under an epsilon_L2^2 budget (Sec. 4.3,
+    Table 3): the plan keeps single products on its k costliest split steps (ranked by
+    measured time) with epsilon_L2^2 <= budget against its three-product amplitudes; against
+    the oracle the error is then at most the budget plus the three-product error."""
+    import importlib.util
+    import os
+    print(f"single products under budget {budget}", flush=True)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_rqc30d12_amplitudes.py")
+    spec = importlib.util.spec_from_file_location("make_rqc30d12_amplitudes", path)
+    fx = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(fx)
+    digest, ref = fx.read_fixture()
+    _, net, best = configs.build("rqc30d12")
+    assert digest == fx.network_digest(net, best)
+    with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], precision="f16x3") as p:
+        p.contract()
+        three, _ = p.amplitudes()
+        k, eps = p.choose_single_products(budget, [0])
+        st = p.steps()
+        single = [i for i, s in enumerate(st) if s["terms"] == 1]
+        order = p.rank_split_steps(by_time=True)
+        p.reset()
+        p.contract()
+        got, _ = p.amplitudes()
+    print(f"budget {budget}: k = {k} of {len(order)} split steps, eps_l2^2 {eps:.3e} against three products, "
+          f"{metrics.eps_l2sq(got, ref):.3e} against the oracle (three products {metrics.eps_l2sq(three, ref):.3e})",
+          flush=True)
+    assert eps <= budget and len(single) == k
+    assert abs(metrics.eps_l2sq(got, three) - eps) <= 1e-3 * budget + 1e-12
+    assert metrics.eps_l2sq(got, ref) <= budget * (1 + 1e-6) + metrics.eps_l2sq(three, ref) + 1e-12
+    if budget >= 1e-4:
+        assert k >= 1
+    assert metrics.rel_l2(got, ref) <= 2 * 2.0 ** -11.5 * np.sqrt(max(k, 1))
 
 
 def _all_open(rows, cols, cycles, seed):
