@@ -494,7 +494,8 @@ def run_slicing_choice(tn, torch, configs, workload, prec, n_candidates, n_timed
     t0 = time.perf_counter()
     dyn = planner.dynamic_slicing(
         net.labels, net.open_labels, best["path"], w.cap_log2,
-        lambda pth, k: choose_slices(net.labels, net.open_labels, ext, pth, w.cap_log2, max_sliced=k))
+        lambda pth, cut: choose_slices(net.labels, net.open_labels, ext, pth, w.cap_log2, start=cut,
+                                       max_sliced=len(cut) + 1))
     dyn_s = time.perf_counter() - t0
     cands.append((dyn["path"], dyn["sliced"]))
     stream = torch.cuda.current_stream()

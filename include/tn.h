@@ -362,6 +362,19 @@ tn_status tn_plan_set_tile(tn_plan plan, int32_t step, int32_t tile);
  * The model must have TN_COST_FEATURES inputs.  Works on host-only plans. */
 tn_status tn_plan_tune_with_model(tn_plan plan, tn_costmodel model, float* predicted_us, int32_t cap);
 
+/* Predicted microseconds per launch of canonical pairwise steps, for scoring contraction
+ * trees by predicted time instead of flop and byte counts (the hardware-weighted score of
+ * Sec. 3.2, learned).  shapes[4 i .. 4 i + 3] = (batch, m, n, k) bit counts of step i, each
+ * 0..30, batch at most 16: extents 2^batch x 2^m x 2^n x 2^k complex, laid out as a plan
+ * lays out intermediates for their consumer (k innermost in both operands, operands and
+ * result stored split when the step runs a split kernel), in `precision` (tn_precision).
+ * The kernel and K split follow the planner's rules for such a step; us[i] receives the
+ * model's time for the tile it predicts fastest.  The model must have TN_COST_FEATURES
+ * inputs.  Synchronous (one forward pass over all candidates on the GPU).
+ * TN_E_UNSUPPORTED for bit counts out of range. */
+tn_status tn_costmodel_predict_shapes(tn_costmodel model, int32_t precision, const int32_t* shapes, int64_t n,
+                                      float* us);
+
 /* MLP with n_features inputs (1..32), two hidden layers of 64 ReLU units and one output,
  * FP32, trained with MSE loss and Adam (beta1 0.9, beta2 0.999, eps 1e-8) by the library's
  * HIP kernels (forward, per-sample deltas, per-weight gradient sums in sample order, Adam).
@@ -386,10 +399,15 @@ tn_status tn_costmodel_gradient(tn_costmodel model, const float* X, const float*
                                 float* grad, float* loss);
 /* One Adam update of the parameters with the given gradient (n_params host floats). */
 tn_status tn_costmodel_adam_step(tn_costmodel model, const float* grad, int64_t n, float lr);
-/* Minibatch training: `epochs` passes over the n samples in an order shuffled per epoch
- * (Fisher-Yates driven by splitmix64 of `seed`), one Adam step per batch of `batch`
- * samples (the last batch of an epoch may be smaller).  *final_loss (may be NULL) receives
- * the MSE over all n samples after training. */
+/* Minibatch training: `epochs` passes over the n samples in an order shuffled per epoch,
+ * one Adam step per batch of `batch` consecutive samples of that order (the last batch of an
+ * epoch may be smaller; its loss is the mean over its own samples).  The order starts as
+ * 0..n-1 and is shuffled in place before every epoch e = 0, 1, ... by Fisher-Yates
+ * (Durstenfeld's form): for i = n-1 down to 1, swap entries i and
+ * j = splitmix64(seed XOR splitmix64(e * 2^32 + i)) mod (i + 1), with splitmix64 the
+ * generator of Steele, Lea and Flood (2014) applied to its argument as the state (state +
+ * 0x9e3779b97f4a7c15, then its two xor-shift-multiply rounds and the final xor-shift).
+ * *final_loss (may be NULL) receives the MSE over all n samples after training. */
 tn_status tn_costmodel_train(tn_costmodel model, const float* X, const float* t, int64_t n,
                              int32_t epochs, int32_t batch, float lr, uint64_t seed,
                              float* final_loss);

@@ -74,3 +74,53 @@ def adam(theta, grad, m, v, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ---------------------------------------------------------------------------
+# Minibatch training with the shuffled order the library documents for
+# tn_costmodel_train (the shuffle's random numbers cannot be passed in, so both
+# sides implement the same counter-based generator from its published definition).
+# ---------------------------------------------------------------------------
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 (Steele, Lea, Flood 2014) output for state x: add the golden-ratio
+    increment, then the two xor-shift-multiply rounds and the final xor-shift."""
+    x = (x + 0x9E3779B97F4A7C15) & _M64
+    x = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & _M64
+    return x ^ (x >> 31)
+
+
+def epoch_orders(n: int, epochs: int, seed: int):
+    """The sample order of every epoch: Fisher-Yates (Durstenfeld) in place on the previous
+    epoch's order (0..n-1 before the first), swap i with j = splitmix64(seed ^ splitmix64(
+    e 2^32 + i)) mod (i + 1) for i = n-1 .. 1."""
+    order = list(range(n))
+    out = []
+    for e in range(epochs):
+        for i in range(n - 1, 0, -1):
+            j = splitmix64((seed ^ splitmix64((e * (1 << 32) + i) & _M64)) & _M64) % (i + 1)
+            order[i], order[j] = order[j], order[i]
+        out.append(list(order))
+    return out
+
+
+def train(theta, X, t, n_in, hidden, mean, std, epochs: int, batch: int, lr: float, seed: int):
+    """Minibatch Adam: per epoch, consecutive batches of `batch` samples of that epoch's order
+    (the last one may be smaller), one gradient of the batch's mean squared error and one
+    Adam update each.  Returns the parameters after training."""
+    X = np.asarray(X, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    theta = np.asarray(theta, dtype=np.float64)
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    step = 0
+    for order in epoch_orders(X.shape[0], epochs, seed):
+        for off in range(0, len(order), batch):
+            idx = order[off:off + batch]
+            g = gradient(theta, X[idx], t[idx], n_in, hidden, mean, std)
+            step += 1
+            theta, m, v = adam(theta, g, m, v, step, lr)
+    return theta

@@ -139,6 +139,37 @@ def predict_plan_us(plan, model: CostModel, n_slices: int | None = None) -> floa
     return total
 
 
+class StepTimeTable:
+    """The model's time of a pairwise step by its (m, n, k) bit counts, for scoring contraction
+    trees by predicted time (planner.refine(step_time=...)).  A step is the library's canonical
+    step of those extents (tn_costmodel_predict_shapes: k innermost in both operands, the
+    planner's kernel, the fastest predicted tile) with `batch_bits` batch bits; both operand
+    orders are asked and the faster kept.  Answers are cached; prefill() asks many shapes in
+    one forward pass."""
+
+    def __init__(self, model: CostModel, precision="f16x3", batch_bits: int = 0):
+        self.model, self.precision, self.batch_bits = model, precision, int(batch_bits)
+        self.cache = {}
+
+    def prefill(self, shapes):
+        todo = sorted({(int(m), int(n), int(k)) for m, n, k in shapes} - set(self.cache))
+        if not todo:
+            return
+        rows = []
+        for m, n, k in todo:
+            rows.append((self.batch_bits, m, n, k))
+            rows.append((self.batch_bits, n, m, k))
+        us = tn.tn_costmodel_predict_shapes(self.model.handle, self.precision, rows)
+        for i, key in enumerate(todo):
+            self.cache[key] = float(min(us[2 * i], us[2 * i + 1]))
+
+    def __call__(self, m: int, n: int, k: int) -> float:
+        key = (int(m), int(n), int(k))
+        if key not in self.cache:
+            self.prefill([key])
+        return self.cache[key]
+
+
 # MI355X roofline of the analytic model: dense MFMA peaks (FP32 for the complex64 GEMM,
 # FP16 / BF16 for the split form, whose three products each run the step's flops), FP32
 # vector for the small kernel, HBM3E bandwidth.
@@ -215,7 +246,8 @@ def records_to_arrays(records):
 
 def tile_choice_report(records, model: CostModel, default_tiles: dict) -> dict:
     """Compare, per (tag, step) measured with every tile, the measured time of the
-    model's argmin tile with the default (heuristic) tile and the fastest tile.
+    model's argmin tile with the default (heuristic) tile and the fastest tile; also
+    summed over only the steps where the model's and the heuristic's tiles differ.
 
     default_tiles maps (tag, step) -> tile id the shape heuristic picks.
     """
@@ -224,9 +256,11 @@ def tile_choice_report(records, model: CostModel, default_tiles: dict) -> dict:
         if r["tile"] < 0:
             continue
         groups.setdefault((r["tag"], r["step"]), []).append(r)
-    tot = {"model": 0.0, "heuristic": 0.0, "best": 0.0, "worst": 0.0}
+    tot = {"model": 0.0, "heuristic": 0.0, "best": 0.0, "worst": 0.0,
+           "model_where_differ": 0.0, "heuristic_where_differ": 0.0}
     n = 0
     hits = 0
+    differ = 0
     for key, rs in groups.items():
         if len(rs) < 2 or key not in default_tiles:
             continue
@@ -237,12 +271,18 @@ def tile_choice_report(records, model: CostModel, default_tiles: dict) -> dict:
         if default_tiles[key] not in tiles:
             continue
         pick = int(np.argmin(pred))
+        heur = tiles.index(default_tiles[key])
         tot["model"] += meas[pick]
-        tot["heuristic"] += meas[tiles.index(default_tiles[key])]
+        tot["heuristic"] += meas[heur]
+        if pick != heur:
+            differ += 1
+            tot["model_where_differ"] += meas[pick]
+            tot["heuristic_where_differ"] += meas[heur]
         tot["best"] += meas.min()
         tot["worst"] += meas.max()
         hits += int(meas[pick] <= meas.min() * 1.05)
         n += 1
     tot["steps"] = n
+    tot["differ"] = differ
     tot["within_5pct_of_best"] = hits
     return tot

@@ -5,7 +5,8 @@
 // and steers the choice of tile shapes (tn_plan_tune_with_model).  The paper
 // ranks contractions by measured time (Sec. 4.1) and scores contraction trees
 // with a hardware-weighted cost (Sec. 3.2); here that cost is learned from
-// rocprof timings of the library's own kernels.
+// per-launch timings of the library's own kernels, taken with HIP events on the
+// plan's stream (a rocprofv3 kernel trace of the same launches agrees with them).
 //
 // Parameters (FP32, one flat array): W1 [H x F], b1 [H], W2 [H x H], b2 [H],
 // w3 [H], b3 [1].  Inputs are standardised with a per-feature mean and std.

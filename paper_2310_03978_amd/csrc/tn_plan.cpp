@@ -1940,6 +1940,85 @@ tn_status tn_plan_tune_with_model(tn_plan p, tn_costmodel model, float* predicte
 
 namespace {
 
+// A pairwise step of 2^bb x 2^mb x 2^nb x 2^kb complex extents laid out the way a plan lays
+// out intermediates for their consumer: k innermost in both operands (A: k, m, batch bits;
+// B: k, n, batch bits; C: n, m, batch bits, lowest first), operands and result stored split
+// when the step runs a split kernel; kernel and K split by the planner's own rules.
+void canonical_step(tn_plan_s& tmp, Step& st, int32_t precision, int bb, int mb, int nb, int kb) {
+  tmp.precision = precision;
+  tmp.host_only = true;
+  for (int j = 0; j < bb; ++j) st.bb.push_back(j);
+  for (int j = 0; j < mb; ++j) st.mb.push_back(bb + j);
+  for (int j = 0; j < nb; ++j) st.nb.push_back(bb + mb + j);
+  for (int j = 0; j < kb; ++j) st.kb.push_back(bb + mb + nb + j);
+  Tensor TA, TB, TC;
+  TA.bits = st.kb;
+  TA.bits.insert(TA.bits.end(), st.mb.begin(), st.mb.end());
+  TA.bits.insert(TA.bits.end(), st.bb.begin(), st.bb.end());
+  TB.bits = st.kb;
+  TB.bits.insert(TB.bits.end(), st.nb.begin(), st.nb.end());
+  TB.bits.insert(TB.bits.end(), st.bb.begin(), st.bb.end());
+  TC.bits = st.nb;
+  TC.bits.insert(TC.bits.end(), st.mb.begin(), st.mb.end());
+  TC.bits.insert(TC.bits.end(), st.bb.begin(), st.bb.end());
+  TA.elems = int64_t(1) << TA.bits.size();
+  TB.elems = int64_t(1) << TB.bits.size();
+  TC.elems = int64_t(1) << TC.bits.size();
+  tmp.tensors = {TA, TB, TC};
+  st.ta = 0;
+  st.tb = 1;
+  st.tc = 2;
+  choose_kernel(&tmp, st);
+  if (st.kernel == TN_K_MFMA_F16X3 || st.kernel == TN_K_MFMA_BF16X3)
+    for (auto& T : tmp.tensors) T.fmt = TN_FMT_SPLIT;
+  if (st.kernel != TN_K_SMALL) build_desc(&tmp, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+tn_status tn_costmodel_predict_shapes(tn_costmodel model, int32_t precision, const int32_t* shapes, int64_t n,
+                                      float* us) {
+  TN_TRY
+  if (!model || n < 0 || (n > 0 && (!shapes || !us))) return fail(TN_E_ARG, "bad arguments");
+  if (precision < 0 || precision > 2) return fail(TN_E_ARG, "unknown precision");
+  int32_t nf = 0;
+  tn_status st = tn_costmodel_describe(model, &nf, nullptr, nullptr);
+  if (st) return st;
+  if (nf != TN_COST_FEATURES) return fail(TN_E_ARG, "model must take the step features as input");
+  std::vector<float> X;
+  std::vector<int64_t> owner;
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t* s = shapes + 4 * i;
+    for (int j = 0; j < 4; ++j)
+      if (s[j] < 0 || s[j] > 30) return fail(TN_E_UNSUPPORTED, "shape bits must lie in 0..30");
+    if (s[0] > 16) return fail(TN_E_UNSUPPORTED, "at most 16 batch bits");
+    tn_plan_s tmp;
+    Step step;
+    canonical_step(tmp, step, precision, s[0], s[1], s[2], s[3]);
+    const bool mfma = step.kernel != TN_K_SMALL;
+    for (int t = 0; t < (mfma ? TN_N_TILES : 1); ++t) {
+      const size_t o = X.size();
+      X.resize(o + TN_COST_FEATURES);
+      step_features(&tmp, step, mfma ? t : -1, X.data() + o);
+      owner.push_back(i);
+    }
+  }
+  if (n == 0) return TN_OK;
+  std::vector<float> y(owner.size());
+  if ((st = tn_costmodel_predict(model, X.data(), (int64_t)owner.size(), y.data()))) return st;
+  std::vector<float> best(n, 1e30f);
+  for (size_t r = 0; r < owner.size(); ++r) best[owner[r]] = std::min(best[owner[r]], y[r]);
+  for (int64_t i = 0; i < n; ++i) us[i] = std::exp(best[i]);
+  return TN_OK;
+  TN_CATCH
+}
+
+}  // extern "C"
+
+namespace {
+
 // Per-slice amplitudes of the given slices, true scale, complex128 interleaved, on the
 // host (the accumulator is untouched).  Synchronous.
 tn_status partials_to_host(tn_plan_s* p, const int64_t* ids, int64_t n, double* out) {
@@ -2662,6 +2741,7 @@ tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_
   return r ? r : r2;
   TN_CATCH
 }
+
 
 tn_status tn_permute(int32_t rank, const int64_t* dims, const int32_t* perm, const void* in, void* out,
                      void* stream) {

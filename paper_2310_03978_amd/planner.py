@@ -3,7 +3,9 @@
 Sec. 3.2 scores a contraction tree with log(T_cc + alpha T_mc) + beta log(T_sc): T_cc the
 compute cost of all pairwise steps (Eq. for T_cc, Sec. 2.4), T_mc their memory traffic (Eq. for
 T_mc), T_sc the size of the largest intermediate; alpha weighs bytes against flops for the
-hardware and beta the largest intermediate.  Its local update re-pairs the three nearest
+hardware and beta the largest intermediate.  With a `step_time` function (for instance the
+learned step-time model, costmodel.StepTimeTable) the first term becomes the log of the summed
+predicted step times instead: the hardware weighting is learned rather than a fixed alpha.  Its local update re-pairs the three nearest
 descendants of a vertex (for a vertex with children x and y = (a, b): ((x, a), b) or
 ((x, b), a)), and a sweep visits every vertex from the root towards the leaves.  `refine`
 anneals a tree for given sliced labels, keeping every intermediate under a memory cap;
@@ -34,7 +36,8 @@ DEFAULT_BETA = 0.1
 class Tree:
     """Binary contraction tree over n leaves; vertex ids: leaves 0..n-1, then internal ones."""
 
-    def __init__(self, labels, open_labels, path, sliced=()):
+    def __init__(self, labels, open_labels, path, sliced=(), step_time=None):
+        self.step_time = step_time
         ids = sorted({l for lab in labels for l in lab})
         self.bit = {l: i for i, l in enumerate(ids)}
         counts = {}
@@ -86,15 +89,24 @@ class Tree:
                           self._size_log(ml ^ mr))
         return 8.0 * 2.0 ** lu, 8.0 * (2.0 ** ll + 2.0 ** lr + 2.0 ** lc), lc
 
+    def _vertex_time(self, ml, mr):
+        """step_time(m, n, k) of one pairwise step (0 without a step_time function): m, n the
+        bits kept from the left and right operand, k the bits they share (summed)."""
+        if self.step_time is None:
+            return 0.0
+        return self.step_time(self._size_log(ml & ~mr), self._size_log(mr & ~ml), self._size_log(ml & mr))
+
     def _recompute(self):
         self.mask = {v: m for v, m in enumerate(self.leaf_mask)}
-        self.cc, self.mc, self.sc = {}, {}, {}
+        self.cc, self.mc, self.sc, self.tp = {}, {}, {}, {}
         for v in range(self.n, 2 * self.n - 1):   # children have smaller ids than parents
             ml, mr = self.mask[self.left[v]], self.mask[self.right[v]]
             self.mask[v] = ml ^ mr
             self.cc[v], self.mc[v], self.sc[v] = self._vertex_costs(ml, mr)
+            self.tp[v] = self._vertex_time(ml, mr)
         self.tcc = sum(self.cc.values())
         self.tmc = sum(self.mc.values())
+        self.ttp = sum(self.tp.values())
         self.sizes = SortedList(self.sc.values())
         self.leaf_max = max(self._size_log(m) for m in self.leaf_mask)
 
@@ -102,6 +114,8 @@ class Tree:
         return max(self.sizes[-1] if self.sizes else 0, self.leaf_max)
 
     def score(self, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA):
+        if self.step_time is not None:
+            return math.log2(self.ttp) + beta * self.tsc_log()
         return math.log2(self.tcc + alpha * self.tmc) + beta * self.tsc_log()
 
     # -- local updates ---------------------------------------------------------
@@ -122,7 +136,7 @@ class Tree:
         a, b = self.left[c], self.right[c]
         keep, move = (b, a) if k == 0 else (a, b)     # keep stays under v, move joins x
         old = (self.left[v], self.right[v], self.left[c], self.right[c], self.mask[c],
-               self.cc[c], self.mc[c], self.sc[c], self.cc[v], self.mc[v])
+               self.cc[c], self.mc[c], self.sc[c], self.cc[v], self.mc[v], self.tp[c], self.tp[v])
         self.left[c], self.right[c] = x, move
         self.parent[x] = c
         self.parent[move] = c
@@ -131,21 +145,26 @@ class Tree:
         self.parent[c] = v
         self.tcc -= self.cc[c] + self.cc[v]
         self.tmc -= self.mc[c] + self.mc[v]
+        self.ttp -= self.tp[c] + self.tp[v]
         self.sizes.remove(self.sc[c])
         mx, mm = self.mask[x], self.mask[move]
         self.mask[c] = mx ^ mm
         self.cc[c], self.mc[c], self.sc[c] = self._vertex_costs(mx, mm)
         self.cc[v], self.mc[v], _ = self._vertex_costs(self.mask[c], self.mask[keep])
+        self.tp[c] = self._vertex_time(mx, mm)
+        self.tp[v] = self._vertex_time(self.mask[c], self.mask[keep])
         self.tcc += self.cc[c] + self.cc[v]
         self.tmc += self.mc[c] + self.mc[v]
+        self.ttp += self.tp[c] + self.tp[v]
         self.sizes.add(self.sc[c])
         return (v, c, old)
 
     def undo(self, rec):
         v, c, old = rec
-        lv, rv, lc, rc, mcm, ccc, mcc, scc, ccv, mcv = old
+        lv, rv, lc, rc, mcm, ccc, mcc, scc, ccv, mcv, tpc, tpv = old
         self.tcc += ccc + ccv - self.cc[c] - self.cc[v]
         self.tmc += mcc + mcv - self.mc[c] - self.mc[v]
+        self.ttp += tpc + tpv - self.tp[c] - self.tp[v]
         self.sizes.remove(self.sc[c])
         self.sizes.add(scc)
         self.left[v], self.right[v], self.left[c], self.right[c] = lv, rv, lc, rc
@@ -154,6 +173,7 @@ class Tree:
         for ch in (lc, rc):
             self.parent[ch] = c
         self.mask[c], self.cc[c], self.mc[c], self.sc[c], self.cc[v], self.mc[v] = mcm, ccc, mcc, scc, ccv, mcv
+        self.tp[c], self.tp[v] = tpc, tpv
 
     # -- paths -------------------------------------------------------------------
     def path(self):
@@ -223,19 +243,21 @@ def anneal_tree(tree, sweeps=40, t_start=1e-4, t_end=1e-7, alpha=DEFAULT_ALPHA, 
 
 
 def refine(labels, open_labels, path, sliced=(), cap_log2=None, sweeps=40, t_start=1e-4, t_end=1e-7,
-           alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, seed=0):
+           alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, seed=0, step_time=None):
     """Anneal the contraction tree of `path` for the given sliced labels; with `cap_log2`, no
-    accepted tree has an intermediate above 2^cap_log2 (the input tree must fit).
+    accepted tree has an intermediate above 2^cap_log2 (the input tree must fit).  With
+    `step_time(m, n, k)` the score sums predicted step times instead of T_cc + alpha T_mc.
 
-    Returns {"path", "score", "start_score", "tsc_log2", "tcc", "tmc"} (costs per slice)."""
-    tree = Tree(labels, open_labels, path, sliced)
+    Returns {"path", "score", "start_score", "tsc_log2", "tcc", "tmc", "time"} (costs per
+    slice; "time" is the summed step_time of the result, 0 without one)."""
+    tree = Tree(labels, open_labels, path, sliced, step_time)
     if cap_log2 is not None and tree.tsc_log() > cap_log2:
         raise ValueError("the input tree does not fit the cap")
     start = tree.score(alpha, beta)
     p, sc = anneal_tree(tree, sweeps, t_start, t_end, alpha, beta, np.random.default_rng(seed), cap_log2)
-    final = Tree(labels, open_labels, p, sliced)
+    final = Tree(labels, open_labels, p, sliced, step_time)
     return {"path": p, "score": sc, "start_score": start, "tsc_log2": final.tsc_log(), "tcc": final.tcc,
-            "tmc": final.tmc}
+            "tmc": final.tmc, "time": final.ttp}
 
 
 def dynamic_slicing(labels, open_labels, path, cap_log2, choose, tune_sweeps=30, final_sweeps=200,
@@ -243,12 +265,18 @@ def dynamic_slicing(labels, open_labels, path, cap_log2, choose, tune_sweeps=30,
     """Sec. 3.2's dynamic slicing: cut bonds one at a time and re-anneal the tree after each
     cut, until the largest intermediate is at most 2^cap_log2; then anneal under the cap.
 
-    `choose(path, k)` returns k labels to slice for the tree of `path` (a greedy slicer).
-    While the tree does not fit, the annealing weighs the largest intermediate fully
-    (beta = 1).  Returns {"path", "sliced", "score", "tsc_log2", "tcc", "tmc"}."""
+    `choose(path, sliced)` returns the labels to slice for the tree of `path`: the list
+    `sliced` (the bonds cut so far, kept) followed by one more bond picked greedily for that
+    tree.  While the tree does not fit, the annealing weighs the largest intermediate fully
+    (beta = 1).  Raises ValueError when the slicer finds no further bond to cut.
+    Returns {"path", "sliced", "score", "tsc_log2", "tcc", "tmc"}."""
     sliced = []
     for it in range(256):
-        sliced = list(choose(path, len(sliced) + 1))
+        grown = list(choose(path, list(sliced)))
+        if len(grown) != len(sliced) + 1 or grown[:len(sliced)] != sliced:
+            raise ValueError("the slicer must keep the bonds cut so far and add exactly one; "
+                             f"it returned {len(grown)} labels after {len(sliced)}")
+        sliced = grown
         if Tree(labels, open_labels, path, sliced).tsc_log() <= cap_log2:
             break
         path = refine(labels, open_labels, path, sliced, sweeps=tune_sweeps, beta=1.0, alpha=alpha,

@@ -44,7 +44,7 @@ EXPORTED = ["tn_plan_create", "tn_plan_create_sparse", "tn_plan_sparse_index", "
             "tn_plan_xeb", "tn_costmodel_create", "tn_costmodel_destroy",
             "tn_costmodel_describe", "tn_costmodel_set_normalization", "tn_costmodel_get_params",
             "tn_costmodel_set_params", "tn_costmodel_predict", "tn_costmodel_gradient",
-            "tn_costmodel_adam_step", "tn_costmodel_train", "tn_gemm", "tn_permute",
+            "tn_costmodel_adam_step", "tn_costmodel_train", "tn_costmodel_predict_shapes", "tn_gemm", "tn_permute",
             "tn_status_string", "tn_last_error_message"]
 
 TN_COST_FEATURES = 29
@@ -173,6 +173,9 @@ _lib.tn_costmodel_set_params.argtypes = [ctypes.c_void_p, _F32P, ctypes.c_int64]
 _lib.tn_costmodel_set_params.restype = ctypes.c_int
 _lib.tn_costmodel_predict.argtypes = [ctypes.c_void_p, _F32P, ctypes.c_int64, _F32P]
 _lib.tn_costmodel_predict.restype = ctypes.c_int
+_lib.tn_costmodel_predict_shapes.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_int32), ctypes.c_int64,
+                                              _F32P]
+_lib.tn_costmodel_predict_shapes.restype = ctypes.c_int
 _lib.tn_costmodel_gradient.argtypes = [ctypes.c_void_p, _F32P, _F32P, ctypes.c_int64, _F32P, _F32P]
 _lib.tn_costmodel_gradient.restype = ctypes.c_int
 _lib.tn_costmodel_adam_step.argtypes = [ctypes.c_void_p, _F32P, ctypes.c_int64, ctypes.c_float]
@@ -504,6 +507,16 @@ def tn_costmodel_predict(model, X) -> np.ndarray:
     y = np.zeros(max(n, 1), dtype=np.float32)
     _check(_lib.tn_costmodel_predict(model, _fp(X), n, _fp(y)))
     return y[:n]
+
+
+def tn_costmodel_predict_shapes(model, precision, shapes) -> np.ndarray:
+    """Predicted microseconds per launch of canonical steps; shapes: (n, 4) ints (b, m, n, k bits)."""
+    sh = np.ascontiguousarray(np.asarray(shapes, dtype=np.int32).reshape(-1, 4))
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    n = sh.shape[0]
+    us = np.zeros(max(n, 1), dtype=np.float32)
+    _check(_lib.tn_costmodel_predict_shapes(model, prec, sh.ctypes.data_as(_P(ctypes.c_int32)), n, _fp(us)))
+    return us[:n]
 
 
 def tn_costmodel_gradient(model, X, t):

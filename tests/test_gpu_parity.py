@@ -43,6 +43,18 @@ def _assert_split_mix(steps, prec, min_share=0.5):
     assert n_split >= min_share * len(kinds), (prec, kinds)
 
 
+def _assert_split_everywhere(steps, prec, min_share=0.8):
+    """split_policy 2: every step runs the split kernel except steps with an operand of fewer
+    than 4 elements (an intermediate that small stays on the FP32 kernel)."""
+    _assert_split_mix(steps, prec, min_share)
+    if prec not in SPLIT_KINDS:
+        return
+    for i, s in enumerate(steps):
+        if s["kernel"] != SPLIT_KINDS[prec]:
+            small = min(s["batch"] * s["m"] * s["k"], s["batch"] * s["k"] * s["n"])
+            assert small < 4, (prec, i, s)
+
+
 @pytest.fixture(scope="module", autouse=True)
 def _need_gpu():
     if not torch.cuda.is_available():
@@ -126,7 +138,7 @@ def test_rqc12_matches_oracle(prec):
     ref = contract.amplitudes(net.tensors, net.labels, net.open_labels, best["path"])
     with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], (), precision=prec,
                  split_policy=2) as p:
-        _assert_split_mix(p.steps(), prec, min_share=0.9)
+        _assert_split_everywhere(p.steps(), prec)
         p.contract()
         got, count = p.amplitudes()
     assert count == 1
@@ -143,7 +155,7 @@ def test_rqc12_sliced_matches_oracle(prec):
     for sb in (1, 4, 16):
         with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], sliced, precision=prec,
                      slice_batch=sb, split_policy=2) as p:
-            _assert_split_mix(p.steps(), prec, min_share=0.9)
+            _assert_split_everywhere(p.steps(), prec)
             p.contract()
             got, count = p.amplitudes()
         assert count == 2 ** len(sliced)
@@ -262,7 +274,7 @@ def test_deterministic_bitwise(prec):
     for _ in range(2):
         with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], sliced, precision=prec,
                      split_policy=2, deterministic=1) as p:
-            _assert_split_mix(p.steps(), prec, min_share=0.9)
+            _assert_split_everywhere(p.steps(), prec)
             p.contract()
             outs.append(p.amplitudes()[0])
     assert np.array_equal(outs[0], outs[1])
@@ -482,7 +494,7 @@ def test_caller_owned_workspace(prec):
     with tn.Plan(*args, host_only=True, **kw) as h:
         need = h.describe()["workspace_bytes"]
     with tn.Plan(*args, **kw) as p:
-        _assert_split_mix(p.steps(), prec, min_share=0.9)
+        _assert_split_everywhere(p.steps(), prec)
         p.contract()
         ref, _ = p.amplitudes()
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
@@ -857,7 +869,7 @@ def test_annealed_path_matches_oracle(prec):
     assert r["path"] != list(best["path"])
     with tn.Plan(net.tensors, net.labels, net.open_labels, r["path"], (), precision=prec,
                  split_policy=2) as p:
-        _assert_split_mix(p.steps(), prec, min_share=0.9)
+        _assert_split_everywhere(p.steps(), prec)
         p.contract()
         got, _ = p.amplitudes()
     _check_amps(got, ref, prec, what="annealed path")

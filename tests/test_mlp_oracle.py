@@ -76,3 +76,59 @@ def test_adam_impulse_response_tells_beta1_from_beta2():
     np.testing.assert_allclose(th, -lr * np.sign(g) * (1 + factor), rtol=1e-6)
     swapped = (b2 / (1 + b2)) / np.sqrt(b1 / (1 + b1))
     assert abs(swapped - factor) > 0.05
+
+
+def test_splitmix64_published_outputs():
+    """The first three outputs of SplitMix64 seeded with 0 (Steele, Lea, Flood 2014; the
+    test vector quoted with the published generator): output k comes from state k * golden."""
+    golden = 0x9E3779B97F4A7C15
+    got = [mlp.splitmix64((k * golden) & ((1 << 64) - 1)) for k in range(3)]
+    assert got == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_epoch_orders_are_permutations_and_change_per_epoch():
+    orders = mlp.epoch_orders(50, 3, seed=42)
+    assert len(orders) == 3
+    for o in orders:
+        assert sorted(o) == list(range(50))
+    assert orders[0] != orders[1] != orders[2]
+    assert mlp.epoch_orders(1, 2, seed=7) == [[0], [0]]
+    assert mlp.epoch_orders(50, 1, seed=42)[0] == orders[0]
+    # a different seed gives a different order
+    assert mlp.epoch_orders(50, 1, seed=43)[0] != orders[0]
+
+
+def test_epoch_orders_cover_every_permutation_of_three():
+    """Fisher-Yates draws every permutation: over many seeds all 3! orders of 3 samples occur
+    with roughly equal frequency (each 1/6)."""
+    counts = {}
+    for seed in range(3000):
+        o = tuple(mlp.epoch_orders(3, 1, seed)[0])
+        counts[o] = counts.get(o, 0) + 1
+    assert len(counts) == 6
+    assert all(abs(c / 3000 - 1 / 6) < 0.03 for c in counts.values()), counts
+
+
+def test_train_with_one_full_batch_is_one_adam_step_on_all_samples():
+    """With batch >= n and one epoch the shuffled order does not matter: the batch loss is the
+    mean over all samples, so training is one Adam step with the full-data gradient."""
+    theta, X, t, F, H, mean, std = _setup(seed=3, n=17)
+    got = mlp.train(theta, X, t, F, H, mean, std, epochs=1, batch=64, lr=0.01, seed=9)
+    g = mlp.gradient(theta, X, t, F, H, mean, std)
+    want, _, _ = mlp.adam(theta, g, np.zeros_like(theta), np.zeros_like(theta), 1, 0.01)
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-15)
+
+
+def test_train_batches_follow_the_epoch_order():
+    """Two epochs of batches of 4 from 10 samples: 3 batches per epoch (4, 4, 2), six Adam steps,
+    each on the samples the epoch's order puts in that batch."""
+    theta, X, t, F, H, mean, std = _setup(seed=5, n=10)
+    got = mlp.train(theta, X, t, F, H, mean, std, epochs=2, batch=4, lr=0.02, seed=11)
+    th, m, v = theta.copy(), np.zeros_like(theta), np.zeros_like(theta)
+    step = 0
+    for order in mlp.epoch_orders(10, 2, 11):
+        for idx in (order[0:4], order[4:8], order[8:10]):
+            step += 1
+            th, m, v = mlp.adam(th, mlp.gradient(th, X[idx], t[idx], F, H, mean, std), m, v, step, 0.02)
+    assert step == 6
+    np.testing.assert_allclose(got, th, rtol=1e-12, atol=1e-15)

@@ -2,6 +2,7 @@
 over every tree of a small network, against the oracle's amplitudes along the refined path,
 and for self-consistency of its incremental costs."""
 import itertools
+import math
 
 import numpy as np
 import pytest
@@ -116,13 +117,72 @@ def test_dynamic_slicing_fits_the_cap_and_keeps_the_amplitudes():
     ext = net.extents()
     cap = path_cost(net.labels, net.open_labels, ext, best["path"])["max_log2"] - 2
 
-    def choose(path, k):
-        return choose_slices(net.labels, net.open_labels, ext, path, cap, max_sliced=k)
+    calls = []
+
+    def choose(path, cut):
+        calls.append(list(cut))
+        return choose_slices(net.labels, net.open_labels, ext, path, cap, start=cut, max_sliced=len(cut) + 1)
 
     r = planner.dynamic_slicing(net.labels, net.open_labels, best["path"], cap, choose, tune_sweeps=5,
                                 final_sweeps=10)
     assert r["tsc_log2"] <= cap and len(r["sliced"]) >= 1
+    # one bond per round, the earlier cuts kept
+    assert [len(c) for c in calls] == list(range(len(r["sliced"])))
+    assert all(r["sliced"][:len(c)] == c for c in calls)
     assert path_cost(net.labels, net.open_labels, ext, r["path"], r["sliced"])["max_log2"] <= cap
     a = contract.amplitudes(net.tensors, net.labels, net.open_labels, best["path"])
     b = contract.amplitudes(net.tensors, net.labels, net.open_labels, r["path"], r["sliced"])
     assert metrics.rel_l2(b, a) <= 1e-12
+
+
+def test_dynamic_slicing_raises_when_the_slicer_stops_growing():
+    _, net, best = configs.build("rqc12")
+    ext = net.extents()
+    cap = path_cost(net.labels, net.open_labels, ext, best["path"])["max_log2"] - 2
+    with pytest.raises(ValueError, match="exactly one"):
+        planner.dynamic_slicing(net.labels, net.open_labels, best["path"], cap, lambda path, cut: list(cut),
+                                tune_sweeps=2, final_sweeps=2)
+
+
+def _analytic_step_time(alpha):
+    # T_cc + alpha T_mc of one step from its (m, n, k) bits: the analytic score's own terms
+    return lambda m, n, k: 8.0 * 2.0 ** (m + n + k) + alpha * 8.0 * (2.0 ** (m + k) + 2.0 ** (n + k) + 2.0 ** (m + n))
+
+
+def test_step_time_score_is_kept_incrementally():
+    _, net, best = configs.build("rqc12")
+    calls = []
+
+    def step_time(m, n, k):
+        calls.append((m, n, k))
+        return 1.0 + m + 2 * n + 3 * k + (m * n * k) % 5
+
+    tree = planner.Tree(net.labels, net.open_labels, best["path"], step_time=step_time)
+    rng = np.random.default_rng(4)
+    recs = []
+    for _ in range(300):
+        v = tree.sweep_order()[int(rng.integers(len(tree.sweep_order())))]
+        mv = tree.moves(v)
+        if mv:
+            recs.append(tree.apply(*mv[int(rng.integers(len(mv)))]))
+        if recs and rng.random() < 0.3:
+            tree.undo(recs.pop())
+    fresh = planner.Tree(net.labels, net.open_labels, tree.path(), step_time=step_time)
+    assert tree.ttp == pytest.approx(fresh.ttp, rel=1e-12)
+    assert tree.score() == pytest.approx(math.log2(fresh.ttp) + planner.DEFAULT_BETA * fresh.tsc_log(), rel=1e-12)
+    assert calls and all(min(c) >= 0 for c in calls)
+
+
+def test_step_time_score_equal_to_the_analytic_terms_anneals_the_same_way():
+    # a step_time that returns exactly T_cc + alpha T_mc of the step makes the learned score
+    # the Sec. 3.2 score: the same seed must give the same tree.  alpha is a power of two so
+    # that every cost is an exact integer and both sums agree to the last bit.
+    _, net, best = configs.build("rqc12")
+    alpha = 128.0
+    a = planner.refine(net.labels, net.open_labels, best["path"], sweeps=15, seed=3, alpha=alpha)
+    b = planner.refine(net.labels, net.open_labels, best["path"], sweeps=15, seed=3,
+                       step_time=_analytic_step_time(alpha))
+    assert a["path"] != list(best["path"])
+    assert a["path"] == b["path"]
+    assert a["score"] == b["score"]
+    assert b["time"] == a["tcc"] + alpha * a["tmc"]

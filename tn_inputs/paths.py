@@ -187,8 +187,12 @@ def _masked_log(mask, lg_items):
 
 
 def choose_slices(labels, open_labels, extents, path, cap_log2: int, min_sliced: int = 0,
-                  max_sliced: int = 64, seed=None, temperature: float = 0.0) -> list:
+                  max_sliced: int = 64, seed=None, temperature: float = 0.0, start=()) -> list:
     """Greedy slicing: cut bonds until the largest intermediate is <= 2^cap_log2.
+
+    ``start`` are labels already sliced: the result begins with them, in that order, and
+    adds bonds after them (with ``max_sliced = len(start) + 1``, exactly one more bond
+    unless none is left to cut).
 
     Slicing a label removes it from every tensor without changing how the other
     labels are classified, so each step's sliced sizes are its unsliced label
@@ -209,7 +213,9 @@ def choose_slices(labels, open_labels, extents, path, cap_log2: int, min_sliced:
         mx = max(_masked_log(o & keep, lg_items) for o in outs + leaves)
         return flops * 2.0 ** _masked_log(smask, lg_items), mx
 
-    sliced, smask = [], 0
+    sliced, smask = list(start), 0
+    for l in sliced:
+        smask |= 1 << l
     while len(sliced) < max_sliced:
         total, mx = cost(smask)
         if mx <= cap_log2 and len(sliced) >= min_sliced:
