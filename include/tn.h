@@ -423,6 +423,23 @@ tn_status tn_costmodel_train(tn_costmodel model, const float* X, const float* t,
 tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_t k,
                   const void* A, const void* B, void* C, void* stream);
 
+/* tn_gemm_noalloc: tn_gemm for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * kernels and results as tn_gemm (bit for bit), but the product's scratch (its layout
+ * descriptor, the max / exponent slots of the split modes and the K-split partials) lives
+ * in a fixed device array of TN_GEMM_NOALLOC_SCRATCH_BYTES that the library's code object
+ * holds on every GPU it runs on until the process ends; the call makes no hipMalloc,
+ * hipFree or other allocating device call.  The array of the current device is used (the
+ * stream must belong to it); its device address is looked up once per device on the first
+ * call there.  The slots are cleared by a fill kernel on every call and the partials are
+ * overwritten, so nothing carries over between calls, but every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other threads, other streams) race and must
+ * be serialised by the caller.  Synchronous like tn_gemm.  A product whose scratch exceeds
+ * the array (large outputs with a K split) gives TN_E_NOMEM and launches nothing. */
+#define TN_GEMM_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+tn_status tn_gemm_noalloc(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_t k,
+                          const void* A, const void* B, void* C, void* stream);
+
 /* tn_permute: out = in with axes permuted: out axis r is in axis perm[r]; dims are the
  * input extents (powers of two), row-major.  rank <= 32. */
 tn_status tn_permute(int32_t rank, const int64_t* dims, const int32_t* perm, const void* in,

@@ -2742,6 +2742,61 @@ tn_status tn_gemm(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_
   TN_CATCH
 }
 
+}  // extern "C"
+
+// Scratch of tn_gemm_noalloc.  Each GPU holds its own copy for the life of the process.
+// Its host-side name is not a device address: host code uses only the address that
+// hipGetSymbolAddress returns for the current device (noalloc_scratch below).
+static __device__ __align__(256) char scratch[TN_GEMM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`, looked up on the first call
+// made with that device current.
+tn_status noalloc_scratch(char** out) {
+  int dev = -1;
+  tn_status r = check(hipGetDevice(&dev), "hipGetDevice");
+  if (r) return r;
+  if (dev < 0 || dev >= kMaxDevices) return fail(TN_E_DEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    r = check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch symbol address");
+    if (r) return r;
+    if (!p) return fail(TN_E_DEVICE, "scratch symbol has no device address");
+    g_noalloc_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return TN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tn_status tn_gemm_noalloc(int32_t precision, int64_t batch, int64_t m, int64_t n, int64_t k, const void* A,
+                          const void* B, void* C, void* stream) {
+  TN_TRY
+  GemmPlan G;
+  tn_status r = gemm_plan(G, precision, batch, m, n, k, A, B, C);
+  if (r) return r;
+  if (G.total_bytes() > TN_GEMM_NOALLOC_SCRATCH_BYTES)
+    return fail(TN_E_NOMEM, "tn_gemm_noalloc: the product needs " + std::to_string(G.total_bytes()) +
+                                " bytes of scratch, more than the fixed " +
+                                std::to_string((size_t)TN_GEMM_NOALLOC_SCRATCH_BYTES) + " bytes");
+  char* buf = nullptr;
+  r = noalloc_scratch(&buf);
+  if (r) return r;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  r = gemm_issue(G, precision, A, B, C, buf, s);
+  tn_status r2 = check(hipStreamSynchronize(s), "gemm sync");
+  return r ? r : r2;
+  TN_CATCH
+}
 
 tn_status tn_permute(int32_t rank, const int64_t* dims, const int32_t* perm, const void* in, void* out,
                      void* stream) {

@@ -44,7 +44,7 @@ EXPORTED = ["tn_plan_create", "tn_plan_create_sparse", "tn_plan_sparse_index", "
             "tn_plan_xeb", "tn_costmodel_create", "tn_costmodel_destroy",
             "tn_costmodel_describe", "tn_costmodel_set_normalization", "tn_costmodel_get_params",
             "tn_costmodel_set_params", "tn_costmodel_predict", "tn_costmodel_gradient",
-            "tn_costmodel_adam_step", "tn_costmodel_train", "tn_costmodel_predict_shapes", "tn_gemm", "tn_permute",
+            "tn_costmodel_adam_step", "tn_costmodel_train", "tn_costmodel_predict_shapes", "tn_gemm", "tn_gemm_noalloc", "tn_permute",
             "tn_status_string", "tn_last_error_message"]
 
 TN_COST_FEATURES = 29
@@ -187,6 +187,8 @@ _lib.tn_gemm.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.
                          ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                          ctypes.c_void_p]
 _lib.tn_gemm.restype = ctypes.c_int
+_lib.tn_gemm_noalloc.argtypes = _lib.tn_gemm.argtypes
+_lib.tn_gemm_noalloc.restype = ctypes.c_int
 _lib.tn_permute.argtypes = [ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_int32),
                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
 _lib.tn_permute.restype = ctypes.c_int
@@ -541,8 +543,11 @@ def tn_costmodel_train(model, X, t, epochs: int, batch: int, lr: float, seed: in
     return float(loss.value)
 
 
-def tn_gemm(A, B, C, precision="c64", stream=None):
-    """C[b] = A[b] @ B[b] on device complex64 torch tensors of shape (b, m, k), (b, k, n), (b, m, n)."""
+def tn_gemm(A, B, C, precision="c64", stream=None, noalloc=False):
+    """C[b] = A[b] @ B[b] on device complex64 torch tensors of shape (b, m, k), (b, k, n), (b, m, n).
+
+    noalloc=True calls tn_gemm_noalloc: the same product with the library's fixed per-device
+    scratch array instead of an allocation (TN_GEMM_NOALLOC_SCRATCH_BYTES at most)."""
     b, m, k = A.shape
     n = B.shape[2]
     if tuple(B.shape) != (b, k, n) or tuple(C.shape) != (b, m, n):
@@ -551,8 +556,8 @@ def tn_gemm(A, B, C, precision="c64", stream=None):
         if not x.is_contiguous() or str(x.dtype) != "torch.complex64" or x.device.type != "cuda":
             raise ValueError("operands must be contiguous complex64 device tensors")
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    _check(_lib.tn_gemm(prec, b, m, n, k, A.data_ptr(), B.data_ptr(), C.data_ptr(),
-                        _stream_handle(stream)))
+    fn = _lib.tn_gemm_noalloc if noalloc else _lib.tn_gemm
+    _check(fn(prec, b, m, n, k, A.data_ptr(), B.data_ptr(), C.data_ptr(), _stream_handle(stream)))
 
 
 def tn_permute(x, perm, out, stream=None):
