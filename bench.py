@@ -471,10 +471,12 @@ def run_slicing_choice(tn, torch, configs, workload, prec, n_candidates, n_timed
     roofline and by the learned model's predicted time with its own tiles.  Every
     candidate is then timed on the GPU (n_timed seeded slices at full size, the model's
     tiles) and its time extrapolated to all its slices (slices cost the same), so each
-    ranking's pick and its rank agreement with the measurement can be compared.  Two more
+    ranking's pick and its rank agreement with the measurement can be compared.  Five more
     candidates: the greedy slicing on the tree refined by the annealer (Sec. 3.2 score and
-    local updates, every intermediate kept under the cap), and Sec. 3.2's dynamic slicing
-    (one bond at a time, the tree re-annealed after each cut), timed the same way."""
+    local updates, every intermediate kept under the cap), Sec. 3.2's dynamic slicing (one
+    bond at a time, the tree re-annealed after each cut), the same two with the learned
+    model's summed step times as the annealing score in place of T_cc + alpha T_mc, and the
+    annealer scored by App. A.2's balanced-index step time, timed the same way."""
     from paper_2310_03978_amd import costmodel, planner
     from tn_inputs.paths import choose_slices
     _, net, best = configs.build(workload)
@@ -501,6 +503,25 @@ def run_slicing_choice(tn, torch, configs, workload, prec, n_candidates, n_timed
     stream = torch.cuda.current_stream()
     rows = []
     with costmodel.CostModel.load() as model:
+        # the same two refinements scored by the learned model (summed predicted step times
+        # in place of T_cc + alpha T_mc)
+        table = costmodel.StepTimeTable(model, prec)
+        t0 = time.perf_counter()
+        lref = planner.refine(net.labels, net.open_labels, best["path"], best["sliced"], cap_log2=w.cap_log2,
+                              sweeps=200, step_time=table)
+        lanneal_s = time.perf_counter() - t0
+        cands.append((lref["path"], list(best["sliced"])))
+        t0 = time.perf_counter()
+        ldyn = planner.dynamic_slicing(
+            net.labels, net.open_labels, best["path"], w.cap_log2,
+            lambda pth, cut: choose_slices(net.labels, net.open_labels, ext, pth, w.cap_log2, start=cut,
+                                           max_sliced=len(cut) + 1), step_time=table)
+        ldyn_s = time.perf_counter() - t0
+        cands.append((ldyn["path"], ldyn["sliced"]))
+        # App. A.2's balanced-index feedback in analytic form (no model)
+        bref = planner.refine(net.labels, net.open_labels, best["path"], best["sliced"], cap_log2=w.cap_log2,
+                              sweeps=200, step_time=planner.balanced_step_time())
+        cands.append((bref["path"], list(best["sliced"])))
         for path, sliced in cands:
             args = (net.tensors, net.labels, net.open_labels, path, sliced)
             with tn.Plan(*args, precision=prec, host_only=True, slice_batch=1) as h:
@@ -554,15 +575,31 @@ def run_slicing_choice(tn, torch, configs, workload, prec, n_candidates, n_timed
                                             out["pick_by_learned_model"]["measured_s"], 3)
     out["learned_vs_analytic_speedup"] = round(out["pick_by_analytic"]["measured_s"] /
                                                out["pick_by_learned_model"]["measured_s"], 3)
-    out["annealed_tree"] = {"candidate": len(rows) - 2, "sliced_labels": rows[-2]["sliced_labels"],
+    ia, idy, ila, ild, ib = (len(rows) - 5, len(rows) - 4, len(rows) - 3, len(rows) - 2, len(rows) - 1)
+    out["annealed_tree"] = {"candidate": ia, "sliced_labels": rows[ia]["sliced_labels"],
                             "score_before": round(ref["start_score"], 4), "score_after": round(ref["score"], 4),
-                            "flops_vs_greedy_tree": round(rows[-2]["flops"] / rows[0]["flops"], 4),
-                            "measured_speedup_vs_greedy_tree": round(rows[0]["measured_s"] / rows[-2]["measured_s"], 3),
+                            "flops_vs_greedy_tree": round(rows[ia]["flops"] / rows[0]["flops"], 4),
+                            "measured_speedup_vs_greedy_tree": round(rows[0]["measured_s"] / rows[ia]["measured_s"], 3),
                             "anneal_s": round(anneal_s, 2)}
-    out["dynamic_slicing"] = {"candidate": len(rows) - 1, "sliced_labels": rows[-1]["sliced_labels"],
-                              "flops_vs_greedy_tree": round(rows[-1]["flops"] / rows[0]["flops"], 4),
-                              "measured_speedup_vs_greedy_tree": round(rows[0]["measured_s"] / rows[-1]["measured_s"], 3),
+    out["dynamic_slicing"] = {"candidate": idy, "sliced_labels": rows[idy]["sliced_labels"],
+                              "flops_vs_greedy_tree": round(rows[idy]["flops"] / rows[0]["flops"], 4),
+                              "measured_speedup_vs_greedy_tree": round(rows[0]["measured_s"] / rows[idy]["measured_s"], 3),
                               "planning_s": round(dyn_s, 1)}
+    # the learned model as the annealing score, against the analytic score on the same task
+    out["learned_score"] = {
+        "annealed_tree": {"candidate": ila, "sliced_labels": rows[ila]["sliced_labels"],
+                          "flops_vs_analytic_annealed": round(rows[ila]["flops"] / rows[ia]["flops"], 4),
+                          "measured_speedup_vs_analytic_annealed": round(rows[ia]["measured_s"] / rows[ila]["measured_s"], 3),
+                          "predicted_step_us_per_slice": round(lref["time"], 1), "anneal_s": round(lanneal_s, 2)},
+        "dynamic_slicing": {"candidate": ild, "sliced_labels": rows[ild]["sliced_labels"],
+                            "flops_vs_analytic_dynamic": round(rows[ild]["flops"] / rows[idy]["flops"], 4),
+                            "measured_speedup_vs_analytic_dynamic": round(rows[idy]["measured_s"] / rows[ild]["measured_s"], 3),
+                            "measured_speedup_vs_greedy_tree": round(rows[0]["measured_s"] / rows[ild]["measured_s"], 3),
+                            "planning_s": round(ldyn_s, 1)},
+        "table_entries": len(table.cache)}
+    out["balanced_score"] = {"candidate": ib, "sliced_labels": rows[ib]["sliced_labels"],
+                             "flops_vs_analytic_annealed": round(rows[ib]["flops"] / rows[ia]["flops"], 4),
+                             "measured_speedup_vs_analytic_annealed": round(rows[ia]["measured_s"] / rows[ib]["measured_s"], 3)}
     out["rows"] = [{k: (round(v, 3) if isinstance(v, float) and k != "flops" else v) for k, v in r.items()}
                    for r in rows]
     return out

@@ -261,15 +261,16 @@ def refine(labels, open_labels, path, sliced=(), cap_log2=None, sweeps=40, t_sta
 
 
 def dynamic_slicing(labels, open_labels, path, cap_log2, choose, tune_sweeps=30, final_sweeps=200,
-                    alpha=DEFAULT_ALPHA, seed=0):
+                    alpha=DEFAULT_ALPHA, seed=0, step_time=None):
     """Sec. 3.2's dynamic slicing: cut bonds one at a time and re-anneal the tree after each
     cut, until the largest intermediate is at most 2^cap_log2; then anneal under the cap.
 
     `choose(path, sliced)` returns the labels to slice for the tree of `path`: the list
     `sliced` (the bonds cut so far, kept) followed by one more bond picked greedily for that
     tree.  While the tree does not fit, the annealing weighs the largest intermediate fully
-    (beta = 1).  Raises ValueError when the slicer finds no further bond to cut.
-    Returns {"path", "sliced", "score", "tsc_log2", "tcc", "tmc"}."""
+    (beta = 1).  With `step_time` the final annealing under the cap scores trees by summed
+    step times (as `refine`).  Raises ValueError when the slicer finds no further bond to cut.
+    Returns {"path", "sliced", "score", "tsc_log2", "tcc", "tmc", "time"}."""
     sliced = []
     for it in range(256):
         grown = list(choose(path, list(sliced)))
@@ -286,6 +287,22 @@ def dynamic_slicing(labels, open_labels, path, cap_log2, choose, tune_sweeps=30,
     else:
         raise ValueError("no slicing of at most 256 bonds fits the cap")
     r = refine(labels, open_labels, path, sliced, cap_log2=cap_log2, sweeps=final_sweeps, alpha=alpha,
-               seed=seed + 1000)
+               seed=seed + 1000, step_time=step_time)
     r["sliced"] = sliced
     return r
+
+
+def balanced_step_time(peak=costmodel.PEAK_SPLIT, bandwidth=costmodel.HBM_BW, k_full=6, mn_full=5):
+    """Analytic step time with App. A.2's balanced-index feedback, for the annealer when no
+    learned model is at hand: the roofline time max(flops / peak, bytes / bandwidth) of a step
+    of 2^m x 2^n x 2^k complex extents, divided by an efficiency that halves for every bit k
+    falls short of k_full (K below 64: memory latency is not hidden along k) and for every bit
+    the smaller of m and n falls short of mn_full (below 32), so the score pushes the tree
+    towards contractions whose GEMM extents reach those sizes.  Returns step_time(m, n, k) in
+    microseconds."""
+    def step_time(m, n, k):
+        flops = 8.0 * 2.0 ** (m + n + k)
+        nbytes = 8.0 * (2.0 ** (m + k) + 2.0 ** (n + k) + 2.0 ** (m + n))
+        eff = 2.0 ** (min(0, k - k_full) + min(0, min(m, n) - mn_full))
+        return max(flops / peak, nbytes / bandwidth) / eff * 1e6
+    return step_time

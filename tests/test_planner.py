@@ -186,3 +186,33 @@ def test_step_time_score_equal_to_the_analytic_terms_anneals_the_same_way():
     assert a["path"] == b["path"]
     assert a["score"] == b["score"]
     assert b["time"] == a["tcc"] + alpha * a["tmc"]
+
+
+def test_balanced_step_time_derates_skinny_steps_only():
+    """App. A.2: GEMMs with K below 64 or m, n below 32 run below the MFMA rate; the balanced
+    step time is the plain roofline time for balanced shapes and larger for skinny ones."""
+    f = planner.balanced_step_time(peak=1e15, bandwidth=1e13)
+
+    def roofline(m, n, k):
+        return max(8.0 * 2.0 ** (m + n + k) / 1e15,
+                   8.0 * (2.0 ** (m + k) + 2.0 ** (n + k) + 2.0 ** (m + n)) / 1e13) * 1e6
+
+    for m, n, k in [(12, 12, 12), (8, 5, 6), (20, 9, 7)]:
+        assert f(m, n, k) == pytest.approx(roofline(m, n, k), rel=1e-12)
+    # K of 8 (3 bits): 8x the roofline time; n of 2 (1 bit): 16x; both: 128x
+    assert f(14, 14, 3) == pytest.approx(8 * roofline(14, 14, 3), rel=1e-12)
+    assert f(20, 1, 12) == pytest.approx(16 * roofline(20, 1, 12), rel=1e-12)
+    assert f(9, 1, 3) == pytest.approx(128 * roofline(9, 1, 3), rel=1e-12)
+
+
+def test_balanced_score_anneals_to_a_valid_tree_no_slower_than_the_start():
+    """Annealing with the balanced step time keeps the best tree it saw: its summed balanced
+    time is at most the starting tree's, and the tree computes the same amplitudes."""
+    _, net, best = configs.build("rqc12")
+    f = planner.balanced_step_time()
+    start = planner.Tree(net.labels, net.open_labels, best["path"], step_time=f).ttp
+    b = planner.refine(net.labels, net.open_labels, best["path"], sweeps=20, seed=5, step_time=f)
+    assert b["time"] <= start
+    a = contract.amplitudes(net.tensors, net.labels, net.open_labels, best["path"])
+    c = contract.amplitudes(net.tensors, net.labels, net.open_labels, b["path"])
+    assert metrics.rel_l2(c, a) <= 1e-12
