@@ -842,6 +842,9 @@ template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 0xf) | (0x7 << 4) | (0xf << 8) | ((N >> 4) << 14));
 }
+
+// s_waitcnt with only the LDS / scalar-memory counter constrained, to zero
+__device__ __forceinline__ void wait_lgkmcnt0() { __builtin_amdgcn_s_waitcnt(0xf | (0x7 << 4) | (0x3 << 14)); }
 }  // namespace
 
 template <int P, int L>
@@ -886,28 +889,31 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
   const uint32_t* Aw = reinterpret_cast<const uint32_t*>(g.A);
   const uint32_t* Bw = reinterpret_cast<const uint32_t*>(g.B);
 
-  const int64_t n_iters = (int64_t)1 << (g.k_split_bits - 4);
+  const int n_iters = 1 << (g.k_split_bits - 4);   // the host keeps k_split_bits - 4 <= 30
   const int64_t k_first = (int64_t)cx.split << g.k_split_bits;
   int64_t ak = a_base + bits_offset(k_first, d->a_k, d->kb);
   int64_t bk = b_base + bits_offset(k_first, d->b_k, d->kb);
   const bool k_linear = d->k_linear != 0;
   const int64_t a_kstep = d->a_kstep, b_kstep = d->b_kstep;
-  int64_t next_it = 0;   // stage whose copy is issued next
-  auto issue = [&]() {
-    char* st = lds + (int)(next_it % S::STAGES) * S::STAGE;
+  int next_it = 0;   // stage whose copy is issued next
+  // Copy stage next_it into LDS buffer `buf`.  Every loop iteration issues exactly one stage,
+  // so the copy count in flight is the same on every iteration; stages past the last one
+  // re-copy the last stage's (in-bounds) data into a buffer no wave reads again.
+  auto issue = [&](int buf) {
+    char* st = lds + buf * S::STAGE;
 #pragma unroll
     for (int i = 0; i < S::CA; ++i)
       __builtin_amdgcn_global_load_lds(Aw + 2 * ak + a_word[i], st + (8 * i + w) * 1024, 16, 0, 0);
 #pragma unroll
     for (int i = 0; i < S::CB; ++i)
-      if ((8 * i + w) * 8 < S::COLS)
+      if (S::COLS >= 64 * S::CB || (8 * i + w) * 8 < S::COLS)   // every wave copies when the columns fill CB rounds
         __builtin_amdgcn_global_load_lds(Bw + 2 * bk + b_word[i], st + S::A_BYTES + (8 * i + w) * 1024, 16, 0, 0);
     if (next_it + 1 < n_iters) {
       if (k_linear) {
         ak += a_kstep;
         bk += b_kstep;
       } else {
-        const int tz = __builtin_ctzll(~(uint64_t)next_it);
+        const int tz = __builtin_ctz(~(uint32_t)next_it);
         ak += d->a_kd[tz];
         bk += d->b_kd[tz];
       }
@@ -927,12 +933,6 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
   // [32, 64); blocks 2, 3: their imaginary parts
   const int half = lane >> 5;
 
-  // Software pipeline over half-stages (8 complex k): the fragments of the next
-  // half-stage are read from LDS while the products of the current one run, so
-  // the MFMA pipe does not wait for LDS latency after each barrier.  The barrier
-  // sits between the two halves of a stage: by then this wave's reads of the
-  // stage are complete (the buffer may be refilled with stage it + 3) and the
-  // next stage's copies have landed (its first half may be read).
   auto read_frags = [&](const char* st, int ks, u32x4 (&xa)[2][2], u32x4 (&xb)[2][2]) {
     const int s0 = ks * 4 + half * 2;      // hi slot of this lane's 4 k (lo slot: s0 + 1)
 #pragma unroll
@@ -956,61 +956,78 @@ __device__ void gett_dma_tile(const GettDesc* __restrict__ d, const GettArgs& g,
     return u32x4{__builtin_amdgcn_alignbit(v.x, v.x, 16), __builtin_amdgcn_alignbit(v.y, v.y, 16),
                  __builtin_amdgcn_alignbit(v.z, v.z, 16), __builtin_amdgcn_alignbit(v.w, v.w, 16)};
   };
-  // hi x hi, hi x lo, lo x hi (slot 2q: hi quad, slot 2q + 1: lo quad), column-major
-  // over the wave tile (dependent products on one accumulator stay 8 MFMAs apart)
-  auto products = [&](const u32x4 (&xa)[2][2], const u32x4 (&xb)[2][2]) {
+  // Software pipeline over half-stages (8 complex k): the fragments of the next
+  // half-stage are read from LDS while the products of the current one run, so
+  // the MFMA pipe does not wait for LDS latency after each barrier.  The barrier
+  // sits between the two halves of a stage: by then this wave's reads of the
+  // stage are complete (the buffer may be refilled with stage it + STAGES) and the
+  // next stage's copies have landed (its first half may be read).  The loop body has
+  // no data-dependent branch: the same copies, waits and LDS reads on every iteration
+  // (the last one reads fragments it does not use), so the wait for a half-stage's
+  // fragments never covers the reads issued for the next one.
+  auto pipeline = [&](auto terms_c) {
+    constexpr int TERMS = decltype(terms_c)::value;
+    // hi x hi, hi x lo, lo x hi (slot 2q: hi quad, slot 2q + 1: lo quad), column-major
+    // over the wave tile (dependent products on one accumulator stay 8 MFMAs apart)
+    auto products = [&](const u32x4 (&xa)[2][2], const u32x4 (&xb)[2][2]) {
 #pragma unroll
-    for (int ni = 0; ni < 2 * S::NB; ++ni) {
-      const u32x4 bh = expand(xb, ni, 0);
+      for (int ni = 0; ni < 2 * S::NB; ++ni) {
+        const u32x4 bh = expand(xb, ni, 0);
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(xa[mi][0], bh, acc[mi][ni]);
-    }
-    if (g.terms == 1) return;   // hi x hi only
+        for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(xa[mi][0], bh, acc[mi][ni]);
+      }
+      if constexpr (TERMS == 3) {
 #pragma unroll
-    for (int ni = 0; ni < 2 * S::NB; ++ni) {
-      const u32x4 bl = expand(xb, ni, 1);
+        for (int ni = 0; ni < 2 * S::NB; ++ni) {
+          const u32x4 bl = expand(xb, ni, 1);
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(xa[mi][0], bl, acc[mi][ni]);
-    }
+          for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(xa[mi][0], bl, acc[mi][ni]);
+        }
 #pragma unroll
-    for (int ni = 0; ni < 2 * S::NB; ++ni) {
-      const u32x4 bh = expand(xb, ni, 0);
+        for (int ni = 0; ni < 2 * S::NB; ++ni) {
+          const u32x4 bh = expand(xb, ni, 0);
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(xa[mi][1], bh, acc[mi][ni]);
+          for (int mi = 0; mi < 2; ++mi) acc[mi][ni] = mfma16<P>(xa[mi][1], bh, acc[mi][ni]);
+        }
+      }
+    };
+    // stages 0 .. STAGES - 2 in flight, wait for stage 0, then the last buffer's stage
+#pragma unroll
+    for (int st0 = 0; st0 + 1 < S::STAGES; ++st0) issue(st0);
+    wait_vmcnt<(S::STAGES - 2) * S::NCOPY>();
+    asm volatile("s_barrier" ::: "memory");
+    issue(S::STAGES - 1);
+    u32x4 fa[2][2], fb[2][2], ga[2][2], gb[2][2];
+    read_frags(lds, 0, fa, fb);
+    int cur = 0;   // buffer of stage it
+    // (scheduling barriers keep each LDS read ahead of the products it overlaps: left
+    // alone, the compiler sinks the reads next to their first use)
+    for (int it = 0; it < n_iters; ++it) {
+      const int nxt = cur + 1 == S::STAGES ? 0 : cur + 1;
+      // this half-stage's fragments (read during the previous products) have landed; waiting
+      // here, before the next reads go out, keeps the wait from covering those reads
+      wait_lgkmcnt0();
+      read_frags(lds + cur * S::STAGE, 1, ga, gb);   // in flight during the first half's products
+      __builtin_amdgcn_sched_barrier(0);
+      products(fa, fb);
+      __builtin_amdgcn_sched_barrier(0);
+      // stage it + 1 landed (the STAGES - 2 younger stages may fly); this wave's reads of
+      // stage it are done, so after the barrier its buffer takes stage it + STAGES
+      wait_vmcnt<(S::STAGES - 2) * S::NCOPY>();
+      wait_lgkmcnt0();
+      __builtin_amdgcn_s_barrier();   // no fence: it would wait for the copies in flight
+      issue(cur);
+      read_frags(lds + nxt * S::STAGE, 0, fa, fb);
+      __builtin_amdgcn_sched_barrier(0);
+      products(ga, gb);
+      __builtin_amdgcn_sched_barrier(0);
+      cur = nxt;
     }
   };
-
-  // wait until the stage a wave needs has landed; with `one_younger` the copies of the
-  // stage after it may still fly (at most one: the last stage is issued only after the
-  // first barrier, into a buffer no wave has read yet)
-  auto wait_landed = [&](bool one_younger) {
-    if (one_younger) wait_vmcnt<S::NCOPY>();
-    else wait_vmcnt<0>();
-  };
-#pragma unroll
-  for (int st0 = 0; st0 + 1 < S::STAGES; ++st0)
-    if (st0 < n_iters) issue();
-  wait_landed(S::STAGES >= 3 && n_iters > 1);
-  asm volatile("s_barrier" ::: "memory");
-  if (S::STAGES - 1 < n_iters) issue();
-  u32x4 fa[2][2], fb[2][2], ga[2][2], gb[2][2];
-  read_frags(lds, 0, fa, fb);
-  for (int64_t it = 0; it < n_iters; ++it) {
-    const char* st = lds + (int)(it % S::STAGES) * S::STAGE;
-    read_frags(st, 1, ga, gb);       // second half of stage it, in flight during the first half's products
-    products(fa, fb);
-    if (it + 1 < n_iters) {
-      // stage it + 1 landed; stage it + 2, if issued, may fly
-      wait_landed(S::STAGES >= 3 && it + 2 < n_iters);
-      // this wave's reads of stage it are done (its buffer takes stage it + STAGES), every
-      // wave's copies of stage it + 1 have landed
-      asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-      if (it + S::STAGES < n_iters) issue();
-      read_frags(lds + (int)((it + 1) % S::STAGES) * S::STAGE, 0, fa, fb);
-    }
-    products(ga, gb);
-  }
-  __syncthreads();   // the epilogue reuses the stage buffers
+  if (g.terms == 1) pipeline(std::integral_constant<int, 1>{});
+  else pipeline(std::integral_constant<int, 3>{});
+  wait_vmcnt<0>();   // the trailing copies land before the epilogue reuses the buffers
+  __syncthreads();
   store_tile<P, S::WM, S::WN, true, 2 * S::NB>(d, g, cx, acc, smem, red);
 }
 

@@ -383,7 +383,7 @@ void build_desc(tn_plan_s* p, Step& st) {
   // columns (which would leave half or three quarters of a 256 x 128 tile empty)
   const bool copy_path = (st.kernel == TN_K_MFMA_F16X3 || st.kernel == TN_K_MFMA_BF16X3) &&
                          st.tile == TN_TILE_256x128 && A.fmt == TN_FMT_SPLIT && B.fmt == TN_FMT_SPLIT &&
-                         d.kb >= 4 && st.k_split_bits >= 4 && d.a_k[0] == 1 && d.a_k[1] == 2 && d.b_k[0] == 1 &&
+                         d.kb >= 4 && st.k_split_bits >= 4 && st.k_split_bits - 4 <= 30 && d.a_k[0] == 1 && d.a_k[1] == 2 && d.b_k[0] == 1 &&
                          d.b_k[1] == 2;
   st.dma = !copy_path ? 0
            : (d.mb >= 8 && d.nb >= 7) ? 1
