@@ -182,6 +182,96 @@ def run_batching(tn, torch, configs, workload, prec, n_small, n_slices, steps):
                                      "amplitudes_identical": bool(small_same)}}
 
 
+def run_batching_full(tn, torch, configs, prec, n_slices, per_graph, n_small):
+    """The batching form at its stated size: n_slices slices of the 40-qubit 5x8 16-cycle network
+    (the tree of Sec. 3.2's dynamic slicing under the 2^28 cap, slice ranges aligned to the chunk
+    size) plus n_small uneven 16-28-qubit circuits, every plan with the learned model's tiles.
+    Contracted plan by plan (tn_contract_slices per plan, the large range in pieces of per_graph
+    slices), then through one group whose graphs each carry per_graph of the slices (the first one
+    also every small circuit): captured beforehand (tn_group_prepare, timed on the host) and
+    replayed (timed with events).  Amplitudes of every plan compared bit for bit."""
+    from paper_2310_03978_amd import planner
+    from tn_inputs.paths import choose_slices
+    _, net, best = configs.build("rqc40")
+    w = configs.WORKLOADS["rqc40"]
+    ext = net.extents()
+    t0 = time.perf_counter()
+    dyn = planner.dynamic_slicing(
+        net.labels, net.open_labels, best["path"], w.cap_log2,
+        lambda pth, cut: choose_slices(net.labels, net.open_labels, ext, pth, w.cap_log2, start=cut,
+                                       max_sliced=len(cut) + 1))
+    planning_s = time.perf_counter() - t0
+    n_total = 1 << len(dyn["sliced"])
+    sb = 16
+    first = sample_slices(n_total, 1, 404)[0] & ~(n_slices - 1)
+    if first + n_slices > n_total:
+        first = n_total - n_slices
+    log(f"  rqc40 tree: {len(dyn['sliced'])} sliced bonds ({n_total} slices), planned in {planning_s:.1f}s; "
+        f"slices [{first}, {first + n_slices}) in graphs of {per_graph}")
+    smalls = configs.uneven_circuits(n_small, seed=1040, cap_log2=22)
+    stream = torch.cuda.current_stream()
+    plans = [tn.Plan(net.tensors, net.labels, net.open_labels, dyn["path"], dyn["sliced"], precision=prec,
+                     stream=stream, slice_batch=sb, tuning=2)]
+    plans += [tn.Plan(n.tensors, n.labels, n.open_labels, b["path"], b.get("sliced", ()), precision=prec,
+                      stream=stream, tuning=2) for n, b in smalls]
+    small_counts = [p.describe()["n_slices"] for p in plans[1:]]   # every slice of every small circuit
+    info0 = plans[0].describe()
+    flops = n_slices * info0["flops_per_slice"] + info0["flops_invariant"] + sum(
+        p.describe()["flops_invariant"] + c * p.describe()["flops_per_slice"] for p, c in zip(plans[1:], small_counts))
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    pieces = [(first + o, per_graph) for o in range(0, n_slices, per_graph)]
+    # plan by plan
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for p, c in zip(plans[1:], small_counts):
+        p.contract(0, c)
+    seq_ms = 0.0
+    for i, (f, c) in enumerate(pieces):
+        plans[0].contract(f, c)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        log(f"  plan by plan: {f + c - first} of {n_slices} slices done, {ev0.elapsed_time(ev1) / 1e3:.1f}s")
+    seq_ms = ev0.elapsed_time(ev1)
+    seq_amps = [p.amplitudes()[0] for p in plans]
+    for p in plans:
+        p.reset()
+    with tn.Group(plans, stream=stream) as g:
+        ranges = []
+        for i, (f, c) in enumerate(pieces):
+            ranges.append(([f] + [0] * n_small, [c] + (small_counts if i == 0 else [0] * n_small)))
+        t0 = time.perf_counter()
+        kernels, branches = [], []
+        for fr, cr in ranges:
+            g.prepare(fr, cr)
+            kernels.append(g.describe()["n_kernels"])
+            branches.append(g.describe()["n_branches"])
+        capture_s = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for i, (fr, cr) in enumerate(ranges):
+            g.contract(fr, cr)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            log(f"  graph replay {i + 1} of {len(ranges)} done, {ev0.elapsed_time(ev1) / 1e3:.1f}s")
+        grp_ms = ev0.elapsed_time(ev1)
+        grp_amps = [p.amplitudes() for p in plans]
+    same = all(np.array_equal(a, b[0]) for a, b in zip(seq_amps, grp_amps))
+    counts_ok = grp_amps[0][1] == n_slices and all(b[1] == c for b, c in zip(grp_amps[1:], small_counts))
+    for p in plans:
+        p.close()
+    return {"workload": "rqc40: 40-qubit 5x8 lattice, 16 cycles, 6 open qubits, cap 2^28, dynamic slicing",
+            "precision": prec, "sliced_labels": len(dyn["sliced"]), "workload_slices": [first, first + n_slices],
+            "slices": n_slices, "slices_per_graph": per_graph, "graphs": len(ranges), "small_circuits": n_small,
+            "small_circuit_slices": int(sum(small_counts)),
+            "planning_s": round(planning_s, 1), "flops": flops, "sequential_ms": round(seq_ms, 1),
+            "graph_ms": round(grp_ms, 1), "speedup": round(seq_ms / grp_ms, 3),
+            "graph_tflops": round(flops / (grp_ms * 1e-3) / 1e12, 2),
+            "graph_slices_per_s": round(n_slices / (grp_ms * 1e-3), 2),
+            "capture_s": round(capture_s, 2), "graph_kernels": kernels, "graph_branches": branches,
+            "amplitudes_identical": bool(same and counts_ok)}
+
+
 def run_tuning_modes(tn, torch, net, best, prec, n_slices):
     """Whole-plan time over n_slices slices with tiles from the shape heuristic, the learned
     step-time model and measured autotuning (a9 / a10)."""
@@ -689,6 +779,8 @@ def main():
                     help="uneven circuits in the batching-form measurement (0 = skip it)")
     ap.add_argument("--batching-workload", default="rqc40")
     ap.add_argument("--batching-slices", type=int, default=32)
+    ap.add_argument("--batching-full", default="",
+                    help="only the batching form at full size, PREC:SLICES:PER_GRAPH (e.g. f16x3:4096:2048)")
     ap.add_argument("--no-permute", dest="permute", action="store_false",
                     help="skip the permutation-kernel bandwidth measurement")
     ap.add_argument("--permute-only", action="store_true",
@@ -718,6 +810,12 @@ def main():
         return
     if args.harvest_check:
         print(json.dumps({"harvest_check": run_harvest_check(tn, torch, configs)}), flush=True)
+        return
+    if args.batching_full:
+        prec, n, per = args.batching_full.split(":")
+        log(f"batching form at full size: {prec}, {n} slices of rqc40 + {args.batching} uneven circuits")
+        print(json.dumps({"batching_full": run_batching_full(tn, torch, configs, prec, int(n), int(per),
+                                                             args.batching)}), flush=True)
         return
 
     t0 = time.perf_counter()

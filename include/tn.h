@@ -315,10 +315,15 @@ tn_status tn_reset(tn_plan plan);
  *   Asynchronous; read results with tn_amplitudes on each plan.  The graph is
  *   captured on the first call with a given set of ranges and replayed (one
  *   hipGraphLaunch) on later calls with the same ranges.
+ * tn_group_prepare: captures (or finds in the group's cache) the graph of those ranges
+ *   without launching it, so that a later tn_group_contract with the same ranges is a
+ *   replay only (for callers that keep capture out of a timed or latency-bound region).
+ *   Adds nothing to any accumulator; errors as tn_group_contract.
  * tn_group_describe: kernel nodes (a batched launch counts once) and branches of
  *   the graph of the last call. */
 tn_status tn_group_create(tn_group* out, const tn_plan* plans, int32_t n_plans, const tn_options* opts);
 tn_status tn_group_contract(tn_group group, const int64_t* first, const int64_t* count);
+tn_status tn_group_prepare(tn_group group, const int64_t* first, const int64_t* count);
 tn_status tn_group_describe(tn_group group, int64_t* n_kernels, int32_t* n_branches);
 void tn_group_destroy(tn_group group);
 

@@ -2511,8 +2511,14 @@ tn_status tn_group_create(tn_group* out, const tn_plan* plans, int32_t n, const 
   TN_CATCH
 }
 
-tn_status tn_group_contract(tn_group G, const int64_t* first, const int64_t* count) {
-  TN_TRY
+}  // extern "C"
+
+namespace {
+
+// The captured graph of plan ranges [first[i], first[i] + count[i]) for the plans' current
+// configurations: from the group's cache, else captured now (graphs of earlier plan
+// configurations are dropped after their last replay has finished).
+tn_status group_graph(tn_group G, const int64_t* first, const int64_t* count, tn_group_s::Cached** out) {
   if (!G || !first || !count) return fail(TN_E_ARG, "bad arguments");
   const int P = (int)G->plans.size();
   // graphs are cached per set of ranges and per plan configuration: a plan re-tiled since
@@ -2529,7 +2535,6 @@ tn_status tn_group_contract(tn_group G, const int64_t* first, const int64_t* cou
   for (auto& c : G->cache)
     if (c.key == key) C = &c;
   if (!C) {
-    // drop graphs of earlier plan configurations (after their last replay has finished)
     bool synced = false;
     for (size_t j = 0; j < G->cache.size();) {
       bool stale = false;
@@ -2555,6 +2560,31 @@ tn_status tn_group_contract(tn_group G, const int64_t* first, const int64_t* cou
       return st;
     }
   }
+  *out = C;
+  return TN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tn_status tn_group_prepare(tn_group G, const int64_t* first, const int64_t* count) {
+  TN_TRY
+  tn_group_s::Cached* C = nullptr;
+  tn_status st = group_graph(G, first, count, &C);
+  if (st) return st;
+  G->last_kernels = C->n_kernels;
+  G->last_branches = C->n_branches;
+  return TN_OK;
+  TN_CATCH
+}
+
+tn_status tn_group_contract(tn_group G, const int64_t* first, const int64_t* count) {
+  TN_TRY
+  tn_group_s::Cached* C = nullptr;
+  tn_status st0 = group_graph(G, first, count, &C);
+  if (st0) return st0;
+  const int P = (int)G->plans.size();
   G->last_kernels = C->n_kernels;
   G->last_branches = C->n_branches;
   tn_status st = TN_OK;

@@ -38,7 +38,7 @@ STATUS = {0: "TN_OK", -1: "TN_E_ARG", -2: "TN_E_LABEL", -3: "TN_E_PATH", -4: "TN
 
 EXPORTED = ["tn_plan_create", "tn_plan_create_sparse", "tn_plan_sparse_index", "tn_plan_destroy", "tn_plan_describe", "tn_plan_steps",
             "tn_plan_step_times", "tn_contract_slices", "tn_slice_partials", "tn_amplitudes", "tn_accumulator_set",
-            "tn_reset", "tn_group_create", "tn_group_contract", "tn_group_describe",
+            "tn_reset", "tn_group_create", "tn_group_contract", "tn_group_prepare", "tn_group_describe",
             "tn_group_destroy", "tn_plan_step_features", "tn_plan_set_tile", "tn_plan_set_step_terms",
             "tn_plan_tune_with_model", "tn_plan_rank_split_steps", "tn_plan_choose_single_products",
             "tn_plan_xeb", "tn_costmodel_create", "tn_costmodel_destroy",
@@ -138,6 +138,8 @@ _lib.tn_group_create.argtypes = [_P(ctypes.c_void_p), _P(ctypes.c_void_p), ctype
 _lib.tn_group_create.restype = ctypes.c_int
 _lib.tn_group_contract.argtypes = [ctypes.c_void_p, _P(ctypes.c_int64), _P(ctypes.c_int64)]
 _lib.tn_group_contract.restype = ctypes.c_int
+_lib.tn_group_prepare.argtypes = [ctypes.c_void_p, _P(ctypes.c_int64), _P(ctypes.c_int64)]
+_lib.tn_group_prepare.restype = ctypes.c_int
 _lib.tn_group_describe.argtypes = [ctypes.c_void_p, _P(ctypes.c_int64), _P(ctypes.c_int32)]
 _lib.tn_group_describe.restype = ctypes.c_int
 _lib.tn_group_destroy.argtypes = [ctypes.c_void_p]
@@ -378,6 +380,12 @@ def tn_group_contract(group, first, count):
     _check(_lib.tn_group_contract(group, f, c))
 
 
+def tn_group_prepare(group, first, count):
+    f = (ctypes.c_int64 * len(first))(*[int(x) for x in first])
+    c = (ctypes.c_int64 * len(count))(*[int(x) for x in count])
+    _check(_lib.tn_group_prepare(group, f, c))
+
+
 def tn_group_describe(group) -> dict:
     nk, nb = ctypes.c_int64(), ctypes.c_int32()
     _check(_lib.tn_group_describe(group, ctypes.byref(nk), ctypes.byref(nb)))
@@ -397,12 +405,19 @@ class Group:
         self.plans = list(plans)
         self.handle = tn_group_create([p.handle for p in self.plans], stream, branches)
 
-    def contract(self, first=None, count=None):
+    def _ranges(self, first, count):
         if first is None:
             first = [0] * len(self.plans)
         if count is None:
             count = [p.describe()["n_slices"] - f for p, f in zip(self.plans, first)]
-        tn_group_contract(self.handle, first, count)
+        return first, count
+
+    def contract(self, first=None, count=None):
+        tn_group_contract(self.handle, *self._ranges(first, count))
+
+    def prepare(self, first=None, count=None):
+        """Capture the graph of these ranges without launching it (a later contract replays)."""
+        tn_group_prepare(self.handle, *self._ranges(first, count))
 
     def describe(self):
         return tn_group_describe(self.handle)

@@ -4,8 +4,10 @@
 
 Data: every step of the plans of seeded uneven lattice circuits (16-28 qubits, depth 8-14),
 the 30-qubit 12-cycle workload, a sparse state of that circuit (2048 bitstrings, seed 13), one
-slice of the 53-qubit 12-cycle workload (intermediates up to 2^30 elements) and the 30-qubit
-14-cycle sliced workload (chunks of 8 slices and of 1 slice), in the three precisions, each MFMA step timed with all four tile shapes (HIP events on the plan's stream).  The model is trained on all circuits but the last
+slice of the 53-qubit 12-cycle workload (intermediates up to 2^30 elements), the 30-qubit
+14-cycle sliced workload (chunks of 8 slices and of 1 slice) and one slice of the 40-qubit
+16-cycle workload, in the three precisions, each MFMA step timed with all four tile shapes (HIP
+events on the plan's stream).  The model is trained on all circuits but the last
 `--held-out` ones and the 14-cycle workload; the saved file records the held-out error and
 the measured time of the tiles the model picks against the shape heuristic's picks.
 """
@@ -31,7 +33,7 @@ def log(*a):
     print(*a, flush=True)
 
 
-def harvest_all(n_circuits: int, precisions, reps: int):
+def harvest_all(n_circuits: int, precisions, reps: int, extra=()):
     circs = configs.uneven_circuits(n_circuits, seed=5000, cap_log2=25)
     items = [(f"u{i}", net, best, 0, None) for i, (net, best) in enumerate(circs)]
     for name in ["rqc30d12", "rqc30"]:
@@ -43,6 +45,10 @@ def harvest_all(n_circuits: int, precisions, reps: int):
     items.append(("rqc53d12sb1", net, best, 1, None))
     _, net, best = configs.build("rqc30")
     items.append(("rqc30sb1", net, best, 1, None))
+    for name in extra:
+        # one slice of a large sliced workload: its largest steps at full size
+        _, net, best = configs.build(name)
+        items.append((f"{name}sb1", net, best, 1, None))
     records, defaults = [], {}
     for prec in precisions:
         for tag, net, best, sb, bits in items:
@@ -62,8 +68,11 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--out", default=costmodel.DEFAULT_MODEL)
     ap.add_argument("--records", default=None, help="also write the harvested records (JSON)")
-    ap.add_argument("--circuits", type=int, default=32)
-    ap.add_argument("--held-out", type=int, default=8)
+    ap.add_argument("--circuits", type=int, default=160)
+    ap.add_argument("--held-out", type=int, default=40)
+    ap.add_argument("--extra-workloads", default="rqc40",
+                    help="sliced workloads harvested on one slice each (largest steps at full size); the "
+                         "53-qubit 14-cycle slicing-choice workload stays out of the data")
     ap.add_argument("--precisions", default="f16x3,c64,bf16x3")
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--epochs", type=int, default=300)
@@ -73,7 +82,8 @@ def main():
     if not torch.cuda.is_available():
         sys.exit("no GPU")
     t0 = time.time()
-    records, defaults = harvest_all(args.circuits, args.precisions.split(","), args.reps)
+    extra = [x for x in args.extra_workloads.split(",") if x]
+    records, defaults = harvest_all(args.circuits, args.precisions.split(","), args.reps, extra)
     if args.records:
         with open(args.records, "w") as f:
             json.dump({"records": records,

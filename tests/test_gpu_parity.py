@@ -451,9 +451,15 @@ def test_group_graph_launch_matches_individual_plans(prec):
             p.contract()
         singles = [p.amplitudes()[0] for p in alone]
         with tn.Group(plans, branches=3) as g:
-            g.contract()
+            # capture without launching: nothing is added to any accumulator
+            g.prepare()
             info = g.describe()
             assert info["n_kernels"] > len(plans) and info["n_branches"] == 3
+            for p in plans:
+                amps0, count0 = p.amplitudes()
+                assert count0 == 0 and not np.any(amps0)
+            g.contract()   # a replay of the prepared graph
+            assert g.describe() == info
             outs = [p.amplitudes() for p in plans]
             for (amps, count), ref, one, p in zip(outs, refs, singles, plans):
                 assert count == p.describe()["n_slices"]
