@@ -185,11 +185,14 @@ def run_batching(tn, torch, configs, workload, prec, n_small, n_slices, steps):
 def run_batching_full(tn, torch, configs, prec, n_slices, per_graph, n_small):
     """The batching form at its stated size: n_slices slices of the 40-qubit 5x8 16-cycle network
     (the tree of Sec. 3.2's dynamic slicing under the 2^28 cap, slice ranges aligned to the chunk
-    size) plus n_small uneven 16-28-qubit circuits, every plan with the learned model's tiles.
-    Contracted plan by plan (tn_contract_slices per plan, the large range in pieces of per_graph
-    slices), then through one group whose graphs each carry per_graph of the slices (the first one
-    also every small circuit): captured beforehand (tn_group_prepare, timed on the host) and
-    replayed (timed with events).  Amplitudes of every plan compared bit for bit."""
+    size) plus n_small uneven 16-28-qubit circuits contracted in full (every slice of each, sliced
+    to a 2^24 cap), every plan with the learned model's tiles.  Contracted plan by plan
+    (tn_contract_slices per plan, the large range in pieces of per_graph slices), then through one
+    group whose graphs each carry per_graph of the large network's slices and a share of every
+    small circuit's slices (each circuit's slices cut into as many contiguous pieces as there are
+    graphs, piece p of circuit j in graph (p + j) mod graphs): captured beforehand
+    (tn_group_prepare, timed on the host) and replayed (timed with events).  Amplitudes and slice
+    counts of every plan compared bit for bit."""
     from paper_2310_03978_amd import planner
     from tn_inputs.paths import choose_slices
     _, net, best = configs.build("rqc40")
@@ -206,54 +209,67 @@ def run_batching_full(tn, torch, configs, prec, n_slices, per_graph, n_small):
     first = sample_slices(n_total, 1, 404)[0] & ~(n_slices - 1)
     if first + n_slices > n_total:
         first = n_total - n_slices
+    pieces = [(first + o, per_graph) for o in range(0, n_slices, per_graph)]
+    G = len(pieces)
     log(f"  rqc40 tree: {len(dyn['sliced'])} sliced bonds ({n_total} slices), planned in {planning_s:.1f}s; "
-        f"slices [{first}, {first + n_slices}) in graphs of {per_graph}")
-    smalls = configs.uneven_circuits(n_small, seed=1040, cap_log2=22)
+        f"slices [{first}, {first + n_slices}) in {G} graphs of {per_graph}")
+    smalls = configs.uneven_circuits(n_small, seed=1040, cap_log2=24)
     stream = torch.cuda.current_stream()
     plans = [tn.Plan(net.tensors, net.labels, net.open_labels, dyn["path"], dyn["sliced"], precision=prec,
                      stream=stream, slice_batch=sb, tuning=2)]
     plans += [tn.Plan(n.tensors, n.labels, n.open_labels, b["path"], b.get("sliced", ()), precision=prec,
-                      stream=stream, tuning=2) for n, b in smalls]
-    small_counts = [p.describe()["n_slices"] for p in plans[1:]]   # every slice of every small circuit
+                      stream=stream, slice_batch=1, tuning=2) for n, b in smalls]
+    small_counts = [p.describe()["n_slices"] for p in plans[1:]]
     info0 = plans[0].describe()
     flops = n_slices * info0["flops_per_slice"] + info0["flops_invariant"] + sum(
         p.describe()["flops_invariant"] + c * p.describe()["flops_per_slice"] for p, c in zip(plans[1:], small_counts))
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    pieces = [(first + o, per_graph) for o in range(0, n_slices, per_graph)]
     # plan by plan
     torch.cuda.synchronize()
     ev0.record(stream)
     for p, c in zip(plans[1:], small_counts):
         p.contract(0, c)
-    seq_ms = 0.0
     for i, (f, c) in enumerate(pieces):
         plans[0].contract(f, c)
         ev1.record(stream)
         torch.cuda.synchronize()
-        log(f"  plan by plan: {f + c - first} of {n_slices} slices done, {ev0.elapsed_time(ev1) / 1e3:.1f}s")
+        if (i + 1) % max(1, G // 8) == 0 or i + 1 == G:
+            log(f"  plan by plan: {f + c - first} of {n_slices} slices done, {ev0.elapsed_time(ev1) / 1e3:.1f}s")
     seq_ms = ev0.elapsed_time(ev1)
     seq_amps = [p.amplitudes()[0] for p in plans]
     for p in plans:
         p.reset()
+
+    def small_piece(j, i):
+        q = (i - j) % G                       # piece q of circuit j goes to graph i
+        n = small_counts[j]
+        lo, hi = q * n // G, (q + 1) * n // G
+        return lo, hi - lo
+
+    ranges = []
+    for i, (f, c) in enumerate(pieces):
+        sp = [small_piece(j, i) for j in range(n_small)]
+        ranges.append(([f] + [x[0] for x in sp], [c] + [x[1] for x in sp]))
+    assert all(sum(r[1][1 + j] for r in ranges) == small_counts[j] for j in range(n_small))
     with tn.Group(plans, stream=stream) as g:
-        ranges = []
-        for i, (f, c) in enumerate(pieces):
-            ranges.append(([f] + [0] * n_small, [c] + (small_counts if i == 0 else [0] * n_small)))
         t0 = time.perf_counter()
         kernels, branches = [], []
-        for fr, cr in ranges:
+        for i, (fr, cr) in enumerate(ranges):
             g.prepare(fr, cr)
             kernels.append(g.describe()["n_kernels"])
             branches.append(g.describe()["n_branches"])
+            if (i + 1) % max(1, G // 8) == 0:
+                log(f"  captured {i + 1} of {G} graphs, {time.perf_counter() - t0:.1f}s")
         capture_s = time.perf_counter() - t0
         torch.cuda.synchronize()
         ev0.record(stream)
         for i, (fr, cr) in enumerate(ranges):
             g.contract(fr, cr)
-            ev1.record(stream)
-            torch.cuda.synchronize()
-            log(f"  graph replay {i + 1} of {len(ranges)} done, {ev0.elapsed_time(ev1) / 1e3:.1f}s")
+            if (i + 1) % max(1, G // 8) == 0 or i + 1 == G:
+                ev1.record(stream)
+                torch.cuda.synchronize()
+                log(f"  graph replays: {i + 1} of {G} done, {ev0.elapsed_time(ev1) / 1e3:.1f}s")
         grp_ms = ev0.elapsed_time(ev1)
         grp_amps = [p.amplitudes() for p in plans]
     same = all(np.array_equal(a, b[0]) for a, b in zip(seq_amps, grp_amps))
@@ -262,14 +278,13 @@ def run_batching_full(tn, torch, configs, prec, n_slices, per_graph, n_small):
         p.close()
     return {"workload": "rqc40: 40-qubit 5x8 lattice, 16 cycles, 6 open qubits, cap 2^28, dynamic slicing",
             "precision": prec, "sliced_labels": len(dyn["sliced"]), "workload_slices": [first, first + n_slices],
-            "slices": n_slices, "slices_per_graph": per_graph, "graphs": len(ranges), "small_circuits": n_small,
-            "small_circuit_slices": int(sum(small_counts)),
-            "planning_s": round(planning_s, 1), "flops": flops, "sequential_ms": round(seq_ms, 1),
-            "graph_ms": round(grp_ms, 1), "speedup": round(seq_ms / grp_ms, 3),
+            "slices": n_slices, "slices_per_graph": per_graph, "graphs": G, "small_circuits": n_small,
+            "small_circuit_slices": int(sum(small_counts)), "planning_s": round(planning_s, 1), "flops": flops,
+            "sequential_ms": round(seq_ms, 1), "graph_ms": round(grp_ms, 1), "speedup": round(seq_ms / grp_ms, 3),
             "graph_tflops": round(flops / (grp_ms * 1e-3) / 1e12, 2),
             "graph_slices_per_s": round(n_slices / (grp_ms * 1e-3), 2),
-            "capture_s": round(capture_s, 2), "graph_kernels": kernels, "graph_branches": branches,
-            "amplitudes_identical": bool(same and counts_ok)}
+            "capture_s": round(capture_s, 2), "graph_kernels_max": max(kernels), "graph_kernels_total": sum(kernels),
+            "graph_branches_max": max(branches), "amplitudes_identical": bool(same and counts_ok)}
 
 
 def run_tuning_modes(tn, torch, net, best, prec, n_slices):

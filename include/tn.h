@@ -315,6 +315,9 @@ tn_status tn_reset(tn_plan plan);
  *   Asynchronous; read results with tn_amplitudes on each plan.  The graph is
  *   captured on the first call with a given set of ranges and replayed (one
  *   hipGraphLaunch) on later calls with the same ranges.
+ *   A graph branch holds at most 8192 kernel nodes (a plan's launches, a batched launch
+ *   counting once): larger ranges give TN_E_UNSUPPORTED before anything is captured, and the
+ *   caller splits them over several calls.
  * tn_group_prepare: captures (or finds in the group's cache) the graph of those ranges
  *   without launching it, so that a later tn_group_contract with the same ranges is a
  *   replay only (for callers that keep capture out of a timed or latency-bound region).

@@ -2336,6 +2336,8 @@ namespace {
 // in order because rounds do).  The element-wise launches of a round (small
 // steps, split-K sums, FP64 slice sums, fills) go out as one batched launch; its
 // MFMA launches follow it one by one.
+constexpr int64_t kMaxBranchNodes = 8192;
+
 tn_status group_build(tn_group_s* G, const std::vector<int64_t>& key, tn_group_s::Cached& C) {
   const int P = (int)G->plans.size();
   std::vector<std::vector<Launch>> chains(P);
@@ -2405,6 +2407,16 @@ tn_status group_build(tn_group_s* G, const std::vector<int64_t>& key, tn_group_s
       }
       rounds[b].push_back(std::move(R));
     }
+  }
+  // Longest chain of kernel nodes in one branch.  A capture with a 74k-node branch ended the
+  // process during capture or instantiation (cause not established); graphs are kept to at
+  // most kMaxBranchNodes nodes per branch, and larger ranges must be split by the caller.
+  for (int b = 0; b < B; ++b) {
+    int64_t nodes = 0;
+    for (const Round& R : rounds[b]) nodes += (R.ntask > 0 ? 1 : 0) + (int64_t)R.single.size();
+    if (nodes > kMaxBranchNodes)
+      return fail(TN_E_UNSUPPORTED, "group graph branch of " + std::to_string(nodes) + " kernel nodes (at most " +
+                                        std::to_string(kMaxBranchNodes) + "): contract fewer slices per call");
   }
   const BatchTask* d_tasks = nullptr;
   const int32_t* d_block_task = nullptr;

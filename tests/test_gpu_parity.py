@@ -598,6 +598,29 @@ def test_rqc40_batching_form_full_size():
             p.close()
 
 
+def test_group_refuses_a_branch_beyond_its_node_limit():
+    """A group graph whose one branch would hold more than 8192 kernel nodes (all 256 slices of
+    the 30-qubit workload one slice per chunk, a few hundred launches each) is refused on the
+    host before anything is captured; a smaller range of the same group then runs normally."""
+    print("group node limit", flush=True)
+    _, net, best = configs.build("rqc30")
+    with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best["sliced"], precision="f16x3",
+                 slice_batch=1) as p:
+        per_slice = sum(1 for s in p.steps() if s["per_slice"])
+        assert 256 * per_slice > 8192
+        with tn.Group([p]) as g:
+            with pytest.raises(tn.TnError) as e:
+                g.prepare([0], [256])
+            assert e.value.status == -9 and "kernel nodes" in str(e.value), e.value
+            amps0, count0 = p.amplitudes()
+            assert count0 == 0
+            g.contract([0], [2])
+            got, count = p.amplitudes()
+        assert count == 2
+        ref = p.partials([0, 1]).sum(axis=0)
+        assert metrics.rel_l2(got, ref) <= 1e-12
+
+
 def test_group_recaptures_after_retile():
     """A plan re-tiled after its group captured a graph: the next group contraction uses the
     new tiles (bitwise equal to the re-tiled plan alone), not the stale graph."""
