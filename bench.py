@@ -447,7 +447,8 @@ def run_precision_form(tn, torch, configs, n_timed, n_check, with_oracle_subcase
 def run_sparse_state(tn, torch, configs, reps):
     """Sparse-state contraction (Sec. 3.3): amplitudes of 4096 sampled bitstrings of the
     30-qubit 12-cycle circuit with every qubit measured, in one contraction; split FP16
-    timed, complex64 for the speed ratio and the amplitude agreement."""
+    timed, complex64 for the speed ratio and the amplitude agreement.  Returns the record
+    and the amplitudes of both precisions (per bitstring)."""
     net, path, bits = configs.sparse_state_workload()
     stream = torch.cuda.current_stream()
     out = {"workload": "rqc30d12 circuit, all 30 qubits measured, 4096 uniform bitstrings, unsliced",
@@ -484,6 +485,28 @@ def run_sparse_state(tn, torch, configs, reps):
             out["max_intermediate"] = info["max_intermediate"]
     out["speedup_vs_c64"] = round(out["c64"]["ms"] / out["f16x3"]["ms"], 3)
     out["rel_l2_f16x3_vs_c64"] = float(np.linalg.norm(amps["f16x3"] - amps["c64"]) / np.linalg.norm(amps["c64"]))
+    return out, amps
+
+
+def sparse_state_vs_oracle(configs, amps, n):
+    """CPU leg: the oracle's definition of n seeded bitstrings' amplitudes of the sparse-state
+    workload (one closed complex128 contraction per bitstring, along a greedy path of the
+    closed network), against the GPU amplitudes of both precisions."""
+    from oracle import metrics, sparse
+    from tn_inputs.paths import greedy_path, path_cost
+    net, _, bits = configs.sparse_state_workload()
+    ids = sample_slices(len(bits), n, 707)
+    opened = set(net.open_labels)
+    closed = [tuple(l for l in lab if l not in opened) for lab in net.labels]
+    ext = net.extents()
+    cands = [greedy_path(closed, (), ext, seed=k, temperature=0.0 if k == 0 else 0.3) for k in range(6)]
+    cpath = min(cands, key=lambda p: path_cost(closed, (), ext, p)["flops_total"])
+    t0 = time.perf_counter()
+    ref = sparse.definition_amplitudes(net.tensors, net.labels, net.open_labels, cpath, bits[ids])
+    out = {"bitstrings": ids, "oracle_s": round(time.perf_counter() - t0, 1)}
+    for prec, a in amps.items():
+        got = a[ids]
+        out[prec] = {"rel_l2": metrics.rel_l2(got, ref), "max_err": metrics.max_err(got, ref)}
     return out
 
 
@@ -921,7 +944,7 @@ def main():
         log(f"  {out['permute']}")
     if args.sparse_state:
         log("sparse-state contraction: 4096 bitstrings of the 30-qubit 12-cycle circuit")
-        out["sparse_state"] = run_sparse_state(tn, torch, configs, 2)
+        out["sparse_state"], sparse_amps = run_sparse_state(tn, torch, configs, 2)
         log(f"  {out['sparse_state']}")
     mixed = None
     if args.mixed_precision and head != "c64":
@@ -942,6 +965,9 @@ def main():
         ref, cb = cpu_baseline(net, best, sample_ids,
                                info["flops_per_slice"] + info["flops_invariant"])
         out["cpu_baseline"] = cb
+        if args.sparse_state:
+            log("sparse state: 4 sampled bitstrings against the oracle's definition (CPU)")
+            out["sparse_state"]["vs_oracle_bitstrings"] = sparse_state_vs_oracle(configs, sparse_amps, 4)
         if mixed:
             # Table 3's trend: time and error against the oracle as single products spread
             top, chosen = mixed
