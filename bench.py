@@ -599,12 +599,13 @@ def run_slicing_choice(tn, torch, configs, workload, prec, n_candidates, n_timed
     roofline and by the learned model's predicted time with its own tiles.  Every
     candidate is then timed on the GPU (n_timed seeded slices at full size, the model's
     tiles) and its time extrapolated to all its slices (slices cost the same), so each
-    ranking's pick and its rank agreement with the measurement can be compared.  Five more
+    ranking's pick and its rank agreement with the measurement can be compared.  Seven more
     candidates: the greedy slicing on the tree refined by the annealer (Sec. 3.2 score and
     local updates, every intermediate kept under the cap), Sec. 3.2's dynamic slicing (one
     bond at a time, the tree re-annealed after each cut), the same two with the learned
-    model's summed step times as the annealing score in place of T_cc + alpha T_mc, and the
-    annealer scored by App. A.2's balanced-index step time, timed the same way."""
+    model's summed step times as the annealing score in place of T_cc + alpha T_mc, the same
+    two with every predicted step time held to at least its flops at the model's own large-step
+    rate, and the annealer scored by App. A.2's balanced-index step time, timed the same way."""
     from paper_2310_03978_amd import costmodel, planner
     from tn_inputs.paths import choose_slices
     _, net, best = configs.build(workload)
@@ -646,6 +647,16 @@ def run_slicing_choice(tn, torch, configs, workload, prec, n_candidates, n_timed
                                            max_sliced=len(cut) + 1), step_time=table)
         ldyn_s = time.perf_counter() - t0
         cands.append((ldyn["path"], ldyn["sliced"]))
+        # the learned score with every step held to at most the model's own large-step rate
+        floored = costmodel.StepTimeTable(model, prec, floor_rate=table.large_step_rate())
+        fref = planner.refine(net.labels, net.open_labels, best["path"], best["sliced"], cap_log2=w.cap_log2,
+                              sweeps=200, step_time=floored)
+        cands.append((fref["path"], list(best["sliced"])))
+        fdyn = planner.dynamic_slicing(
+            net.labels, net.open_labels, best["path"], w.cap_log2,
+            lambda pth, cut: choose_slices(net.labels, net.open_labels, ext, pth, w.cap_log2, start=cut,
+                                           max_sliced=len(cut) + 1), step_time=floored)
+        cands.append((fdyn["path"], fdyn["sliced"]))
         # App. A.2's balanced-index feedback in analytic form (no model)
         bref = planner.refine(net.labels, net.open_labels, best["path"], best["sliced"], cap_log2=w.cap_log2,
                               sweeps=200, step_time=planner.balanced_step_time())
@@ -703,7 +714,8 @@ def run_slicing_choice(tn, torch, configs, workload, prec, n_candidates, n_timed
                                             out["pick_by_learned_model"]["measured_s"], 3)
     out["learned_vs_analytic_speedup"] = round(out["pick_by_analytic"]["measured_s"] /
                                                out["pick_by_learned_model"]["measured_s"], 3)
-    ia, idy, ila, ild, ib = (len(rows) - 5, len(rows) - 4, len(rows) - 3, len(rows) - 2, len(rows) - 1)
+    ia, idy, ila, ild, ifa, ifd, ib = (len(rows) - 7, len(rows) - 6, len(rows) - 5, len(rows) - 4,
+                                       len(rows) - 3, len(rows) - 2, len(rows) - 1)
     out["annealed_tree"] = {"candidate": ia, "sliced_labels": rows[ia]["sliced_labels"],
                             "score_before": round(ref["start_score"], 4), "score_after": round(ref["score"], 4),
                             "flops_vs_greedy_tree": round(rows[ia]["flops"] / rows[0]["flops"], 4),
@@ -724,7 +736,13 @@ def run_slicing_choice(tn, torch, configs, workload, prec, n_candidates, n_timed
                             "measured_speedup_vs_analytic_dynamic": round(rows[idy]["measured_s"] / rows[ild]["measured_s"], 3),
                             "measured_speedup_vs_greedy_tree": round(rows[0]["measured_s"] / rows[ild]["measured_s"], 3),
                             "planning_s": round(ldyn_s, 1)},
-        "table_entries": len(table.cache)}
+        "table_entries": len(table.cache),
+        "floored": {"floor_tflops": round(floored.floor_rate / 1e12, 1),
+                    "annealed_tree": {"candidate": ifa, "flops_vs_analytic_annealed": round(rows[ifa]["flops"] / rows[ia]["flops"], 4),
+                                      "measured_speedup_vs_analytic_annealed": round(rows[ia]["measured_s"] / rows[ifa]["measured_s"], 3)},
+                    "dynamic_slicing": {"candidate": ifd, "sliced_labels": rows[ifd]["sliced_labels"],
+                                        "flops_vs_analytic_dynamic": round(rows[ifd]["flops"] / rows[idy]["flops"], 4),
+                                        "measured_speedup_vs_analytic_dynamic": round(rows[idy]["measured_s"] / rows[ifd]["measured_s"], 3)}}}
     out["balanced_score"] = {"candidate": ib, "sliced_labels": rows[ib]["sliced_labels"],
                              "flops_vs_analytic_annealed": round(rows[ib]["flops"] / rows[ia]["flops"], 4),
                              "measured_speedup_vs_analytic_annealed": round(rows[ia]["measured_s"] / rows[ib]["measured_s"], 3)}

@@ -147,8 +147,13 @@ class StepTimeTable:
     orders are asked and the faster kept.  Answers are cached; prefill() asks many shapes in
     one forward pass."""
 
-    def __init__(self, model: CostModel, precision="f16x3", batch_bits: int = 0):
+    def __init__(self, model: CostModel, precision="f16x3", batch_bits: int = 0, floor_rate: float | None = None):
+        """floor_rate (flop/s), when given, bounds every step's time from below by its flops
+        (8 real flops per complex multiply-add) at that rate, so that an annealer scored by
+        the table cannot favour steps the model predicts faster than, for instance, its own
+        prediction for a large balanced step (large_step_rate())."""
         self.model, self.precision, self.batch_bits = model, precision, int(batch_bits)
+        self.floor_rate = floor_rate
         self.cache = {}
 
     def prefill(self, shapes):
@@ -160,8 +165,16 @@ class StepTimeTable:
             rows.append((self.batch_bits, m, n, k))
             rows.append((self.batch_bits, n, m, k))
         us = tn.tn_costmodel_predict_shapes(self.model.handle, self.precision, rows)
-        for i, key in enumerate(todo):
-            self.cache[key] = float(min(us[2 * i], us[2 * i + 1]))
+        for i, (m, n, k) in enumerate(todo):
+            t = float(min(us[2 * i], us[2 * i + 1]))
+            if self.floor_rate:
+                t = max(t, 8.0 * 2.0 ** (self.batch_bits + m + n + k) / self.floor_rate * 1e6)
+            self.cache[(m, n, k)] = t
+
+    def large_step_rate(self, bits: int = 13) -> float:
+        """flop/s the model predicts for a large balanced step (2^bits x 2^bits x 2^(bits-1))."""
+        us = self(bits, bits, bits - 1)
+        return 8.0 * 2.0 ** (self.batch_bits + 3 * bits - 1) / (us * 1e-6)
 
     def __call__(self, m: int, n: int, k: int) -> float:
         key = (int(m), int(n), int(k))

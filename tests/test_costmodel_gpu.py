@@ -226,3 +226,12 @@ def test_predict_shapes_and_the_learned_annealing_score():
             p.contract()
             got, _ = p.amplitudes()
         assert metrics.rel_l2(got, ref) <= 1e-3
+        # the floored table: no step faster than its flops at the model's large-step rate
+        rate = table.large_step_rate()
+        assert 1e14 < rate < 2.5e15, rate
+        floored = costmodel.StepTimeTable(m, "f16x3", floor_rate=rate)
+        for (m_, n_, k_) in [(13, 13, 12), (12, 12, 12), (4, 4, 2), (10, 14, 6)]:
+            t = floored(m_, n_, k_)
+            assert t >= 8.0 * 2.0 ** (m_ + n_ + k_) / rate * 1e6 * (1 - 1e-9)
+            assert t >= table(m_, n_, k_)
+        assert floored(13, 13, 12) == pytest.approx(table(13, 13, 12), rel=1e-9)

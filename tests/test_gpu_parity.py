@@ -559,9 +559,9 @@ def test_rqc53d12_full_size_properties():
 def test_rqc40_batching_form_full_size():
     """The batching form's shape: slices of the 40-qubit, 16-cycle network (largest
     intermediate 2^28) and 64 uneven 16-28-qubit circuits in one captured graph.  Every
-    plan's amplitudes equal, bit for bit, the same plan's run on its own; the four
-    cheapest uneven circuits also match the oracle, and the graph's 40-qubit sum agrees
-    with the complex64 path's."""
+    plan's amplitudes equal, bit for bit, the same plan's run on its own; every uneven circuit
+    the oracle contracts in well under a second (at most 1e12 flops: 56 of the 64) also
+    matches the oracle, and the graph's 40-qubit sum agrees with the complex64 path's."""
     print("rqc40 batching form", flush=True)
     _, net, best = configs.build("rqc40")
     args = (net.tensors, net.labels, net.open_labels, best["path"], best["sliced"])
@@ -582,7 +582,8 @@ def test_rqc40_batching_form_full_size():
             g.contract([first] + [0] * len(small), [8] + [1] * len(small))
             for p, one in zip(plans, singles):
                 assert np.array_equal(p.amplitudes()[0], one)
-        cheap = sorted(range(len(small)), key=lambda i: small[i][1]["cost"]["flops_total"])[:4]
+        cheap = [i for i in range(len(small)) if small[i][1]["cost"]["flops_total"] <= 1e12]
+        assert len(cheap) >= 48
         for i in cheap:
             n_, b = small[i]
             ref = contract.amplitudes(n_.tensors, n_.labels, n_.open_labels, b["path"])
