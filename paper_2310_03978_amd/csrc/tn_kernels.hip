@@ -408,6 +408,11 @@ struct Tile {
   static constexpr int BUF = P == 0 ? KB * LDA0 + KB * LDB0 : 2 * BM * LDK + 4 * BN * LDK;  // words
   static constexpr int LDC = 2 * BN + 8;                        // epilogue floats per row (64 rows)
   static constexpr int SMEM = 4 * (2 * BUF > 64 * LDC ? 2 * BUF : 64 * LDC);
+  // Waves per SIMD that the LDS (160 KiB per CU) lets resident: where it allows fewer
+  // than two, the register budget of two waves would only cause spills, so the
+  // launch bound asks for one (the wave may then use the whole register file).
+  static constexpr int LDS_WAVES = (160 * 1024 / (SMEM + 64)) * WM * WN;
+  static constexpr int MIN_WAVES = LDS_WAVES >= 8 ? 2 : 1;
 };
 }  // namespace
 
@@ -1041,7 +1046,7 @@ __global__ __launch_bounds__(512, 2) void k_gett_dma(const GettDesc* __restrict_
 }
 
 template <int P, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN, 2) void k_gett_mfma(const GettDesc* __restrict__ d, GettArgs g) {
+__global__ __launch_bounds__(64 * WM * WN, (Tile<P, WM, WN>::MIN_WAVES)) void k_gett_mfma(const GettDesc* __restrict__ d, GettArgs g) {
   extern __shared__ __align__(16) uint32_t smem[];
   __shared__ uint32_t red[16];
   // Blocks are dealt to the 8 XCDs round-robin; renumber so that each XCD owns
