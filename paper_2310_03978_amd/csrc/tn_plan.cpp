@@ -1185,7 +1185,7 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
   if (p->own_memory) p->device_bytes -= max_leaf * 8;
   if (st) return st;
   if (p->opts.tuning == 1) {
-    // timing runs read the (zeroed) arenas before any real data is there
+    // the arenas start zeroed; tuning then runs the steps in order (autotune)
     if ((st = check(hipMemsetAsync(p->d_inv, 0, p->inv_elems * 8, s), "arena clear"))) return st;
     if ((st = check(hipMemsetAsync(p->d_ps, 0, p->ps_elems * 8, s), "arena clear"))) return st;
     if ((st = check(hipMemsetAsync(p->d_max_ps, 0, nt * S * 4, s), "max clear"))) return st;
@@ -1524,9 +1524,16 @@ tn_status autotune(tn_plan_s* p) {
   }
   const int keep_record = p->opts.record_steps;
   p->opts.record_steps = 0;
+  // Steps run in path order on slice chunk 0, each once whether timed or not, so that
+  // every timed step reads the real intermediates of its operands (the clock the chip
+  // holds under a load depends on the data it multiplies).
   for (size_t s = 0; s < p->steps.size() && !r; ++s) {
     Step& st = p->steps[s];
-    if (st.kernel == TN_K_SMALL) continue;
+    const int bits = st.per_slice ? p->s_bits : 0;
+    if (st.kernel == TN_K_SMALL) {
+      r = run_step(p, (int)s, 0, bits);
+      continue;
+    }
     const std::string sig = step_signature(p, st);
     int cached = -1;
     {
@@ -1536,9 +1543,9 @@ tn_status autotune(tn_plan_s* p) {
     }
     if (cached >= 0) {
       r = apply_tile(p, (int)s, cached);
+      if (!r) r = run_step(p, (int)s, 0, bits);
       continue;
     }
-    const int bits = st.per_slice ? p->s_bits : 0;
     int best = st.tile;
     float best_ms = 1e30f;
     for (int tile = 0; tile < TN_N_TILES && !r; ++tile) {
