@@ -289,7 +289,7 @@ def run_batching_full(tn, torch, configs, prec, n_slices, per_graph, n_small):
 
 def run_tuning_modes(tn, torch, net, best, prec, n_slices):
     """Whole-plan time over n_slices slices with tiles from the shape heuristic, the learned
-    step-time model and measured autotuning (a9 / a10)."""
+    step-time model and measured autotuning."""
     stream = torch.cuda.current_stream()
     out = {}
     for name, tuning in (("heuristic", 0), ("learned_model", 2), ("autotune", 1)):
@@ -381,15 +381,26 @@ def run_mixed_precision(tn, torch, net, best, prec, sample_ids, n_slices, budget
     return out, chosen
 
 
-def run_precision_form(tn, torch, configs, n_timed, n_check, with_oracle_subcase):
+def rel_l2(got, ref):
+    """||got - ref|| / ||ref|| over all entries (GPU-against-GPU comparisons of the bench)."""
+    got, ref = np.asarray(got), np.asarray(ref)
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def max_err(got, ref):
+    """max |got - ref| / max |ref| over all entries."""
+    got, ref = np.asarray(got), np.asarray(ref)
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+def run_precision_form(tn, torch, configs, n_timed, n_check):
     """The precision form at its own size (53-qubit 6x9-minus-one lattice, 12 cycles, 512
     correlated amplitudes, largest intermediate 2^30): split FP16, split BF16 and complex64
     on the same slices.  Timing: n_timed consecutive slices from a seeded position (every
     slice costs the same).  Errors: the split precisions' partial amplitudes of n_check
     seeded slices (seed 303) against complex64's (no oracle slice of this network finishes
-    in minutes), and, when asked, the 30-qubit 12-cycle sub-case in every precision against
-    the oracle's stored amplitudes."""
-    from oracle import metrics
+    in minutes).  Also returns the amplitudes of the 30-qubit 12-cycle sub-case in every
+    precision, which the CPU leg compares with the oracle's stored amplitudes."""
     _, net, best = configs.build("rqc53d12")
     n_slices = 1 << len(best["sliced"])
     check = sample_slices(n_slices, n_check, 303)
@@ -422,25 +433,86 @@ def run_precision_form(tn, torch, configs, n_timed, n_check, with_oracle_subcase
     out["flops_per_slice"] = info["flops_per_slice"]
     out["max_intermediate"] = info["max_intermediate"]
     for prec in ("f16x3", "bf16x3"):
-        out[prec]["rel_l2_vs_c64"] = metrics.rel_l2(parts[prec], parts["c64"])
+        out[prec]["rel_l2_vs_c64"] = rel_l2(parts[prec], parts["c64"])
         out[prec]["speedup_vs_c64"] = round(out["c64"]["ms_per_slice"] / out[prec]["ms_per_slice"], 3)
-    if with_oracle_subcase:
-        import importlib.util
-        path = os.path.join(ROOT, "tests", "golden", "make_rqc30d12_amplitudes.py")
-        spec = importlib.util.spec_from_file_location("make_rqc30d12_amplitudes", path)
-        fx = importlib.util.module_from_spec(spec)
-        spec.loader.exec_module(fx)
-        digest, ref = fx.read_fixture()
-        _, snet, sbest = configs.build("rqc30d12")
-        sub = {"workload": configs.WORKLOADS["rqc30d12"].description,
-               "fixture_matches_network": digest == fx.network_digest(snet, sbest)}
-        for prec in ("f16x3", "bf16x3", "c64"):
-            with tn.Plan(snet.tensors, snet.labels, snet.open_labels, sbest["path"], precision=prec,
-                         stream=stream) as p:
-                p.contract()
-                amps, _ = p.amplitudes()
-            sub[prec] = {k: float(v) for k, v in metrics.report(amps, ref).items()}
-        out["oracle_subcase_30q"] = sub
+    _, snet, sbest = configs.build("rqc30d12")
+    sub_amps = {}
+    for prec in ("f16x3", "bf16x3", "c64"):
+        with tn.Plan(snet.tensors, snet.labels, snet.open_labels, sbest["path"], precision=prec,
+                     stream=stream) as p:
+            p.contract()
+            sub_amps[prec], _ = p.amplitudes()
+    return out, sub_amps
+
+
+def precision_subcase_vs_oracle(configs, sub_amps):
+    """CPU leg: the 30-qubit 12-cycle sub-case's amplitudes in every precision against the
+    oracle's stored amplitudes (tests/golden fixture, checked to belong to this network)."""
+    import importlib.util
+    from oracle import metrics
+    path = os.path.join(ROOT, "tests", "golden", "make_rqc30d12_amplitudes.py")
+    spec = importlib.util.spec_from_file_location("make_rqc30d12_amplitudes", path)
+    fx = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(fx)
+    digest, ref = fx.read_fixture()
+    _, snet, sbest = configs.build("rqc30d12")
+    sub = {"workload": configs.WORKLOADS["rqc30d12"].description,
+           "fixture_matches_network": digest == fx.network_digest(snet, sbest)}
+    for prec, amps in sub_amps.items():
+        sub[prec] = {k: float(v) for k, v in metrics.report(amps, ref).items()}
+    return sub
+
+
+def run_precision_form_full(tn, torch, configs, prec, n_slices, piece=128):
+    """The precision form's evaluation at its stated size: n_slices consecutive slices of the
+    53-qubit 12-cycle network (512 correlated amplitudes, largest intermediate 2^30) summed
+    into one FP64 accumulator in one precision, timed with HIP events from the first piece's
+    launch to the last one's end.  Pieces of `piece` slices are enqueued one ahead of the
+    one being waited for, so the device never idles on the host's progress lines.  The same
+    two seeded slices as the default precision-form record (seed 303) are compared with
+    complex64, and the accumulated amplitudes are summarised (squared norm, largest)."""
+    _, net, best = configs.build("rqc53d12")
+    total = 1 << len(best["sliced"])
+    first = sample_slices(total, 1, 304)[0] & ~(n_slices - 1)
+    check = sample_slices(total, 2, 303)
+    stream = torch.cuda.current_stream()
+    out = {"workload": configs.WORKLOADS["rqc53d12"].description, "precision": prec,
+           "slices": n_slices, "range": [first, first + n_slices], "n_slices": total}
+    parts = {}
+    with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best["sliced"], precision="c64",
+                 stream=stream, tuning=2) as p:
+        parts["c64"] = p.partials(check)
+    with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best["sliced"], precision=prec,
+                 stream=stream, tuning=2) as p:
+        info = p.describe()
+        parts[prec] = p.partials(check)
+        p.contract(first, 2)   # warm-up
+        torch.cuda.synchronize()
+        p.reset()
+        n_pieces = (n_slices + piece - 1) // piece
+        ends = []
+        start = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        t0 = time.perf_counter()
+        for i in range(n_pieces + 1):
+            if i < n_pieces:
+                p.contract(first + i * piece, min(piece, n_slices - i * piece))
+                e = torch.cuda.Event(enable_timing=True)
+                e.record(stream)
+                ends.append(e)
+            if i >= 1:
+                ends[i - 1].synchronize()
+                done = min(i * piece, n_slices)
+                log(f"  precision form {prec}: {done}/{n_slices} slices, {time.perf_counter() - t0:.0f} s")
+        ms = start.elapsed_time(ends[-1])
+        amps, count = p.amplitudes()
+    flops = info["flops_per_slice"] * n_slices + info["flops_invariant"]
+    out.update({"ms": round(ms, 1), "ms_per_slice": round(ms / n_slices, 3),
+                "tflops": round(flops / (ms * 1e-3) / 1e12, 2), "slices_per_s": round(n_slices / (ms * 1e-3), 3),
+                "flops": flops, "slices_accumulated": int(count), "amplitudes": int(len(amps)),
+                "sum_abs2": float(np.sum(np.abs(amps) ** 2)), "max_abs": float(np.max(np.abs(amps))),
+                "checked_slices": check, "rel_l2_vs_c64_checked": rel_l2(parts[prec], parts["c64"]),
+                "max_err_vs_c64_checked": max_err(parts[prec], parts["c64"])})
     return out
 
 
@@ -837,6 +909,9 @@ def main():
     ap.add_argument("--batching-slices", type=int, default=32)
     ap.add_argument("--batching-full", default="",
                     help="only the batching form at full size, PREC:SLICES:PER_GRAPH (e.g. f16x3:4096:2048)")
+    ap.add_argument("--precision-form-full", default="",
+                    help="PREC:SLICES: only the precision form's evaluation of SLICES slices of the "
+                         "53-qubit 12-cycle network in one precision")
     ap.add_argument("--no-permute", dest="permute", action="store_false",
                     help="skip the permutation-kernel bandwidth measurement")
     ap.add_argument("--permute-only", action="store_true",
@@ -866,6 +941,12 @@ def main():
         return
     if args.harvest_check:
         print(json.dumps({"harvest_check": run_harvest_check(tn, torch, configs)}), flush=True)
+        return
+    if args.precision_form_full:
+        prec, n = args.precision_form_full.split(":")
+        log(f"precision form at full size: {prec}, {n} slices of rqc53d12")
+        print(json.dumps({"precision_form_full": run_precision_form_full(tn, torch, configs, prec, int(n))}),
+              flush=True)
         return
     if args.batching_full:
         prec, n, per = args.batching_full.split(":")
@@ -970,8 +1051,8 @@ def main():
         mixed = run_mixed_precision(tn, torch, net, best, head, sample_ids, 32, (1e-5, 1e-4))
     if args.precision_form_slices > 0:
         log(f"precision form: rqc53d12, {args.precision_form_slices} timed slices per precision")
-        out["precision_form"] = run_precision_form(tn, torch, configs, args.precision_form_slices, 2,
-                                                   not args.no_cpu_baseline)
+        out["precision_form"], subcase_amps = run_precision_form(tn, torch, configs,
+                                                                 args.precision_form_slices, 2)
     if args.batching > 0:
         log(f"batching form: {args.batching} uneven circuits + {args.batching_slices} slices of "
             f"{args.batching_workload}")
@@ -983,6 +1064,8 @@ def main():
         ref, cb = cpu_baseline(net, best, sample_ids,
                                info["flops_per_slice"] + info["flops_invariant"])
         out["cpu_baseline"] = cb
+        if args.precision_form_slices > 0:
+            out["precision_form"]["oracle_subcase_30q"] = precision_subcase_vs_oracle(configs, subcase_amps)
         if args.sparse_state:
             log("sparse state: 4 sampled bitstrings against the oracle's definition (CPU)")
             out["sparse_state"]["vs_oracle_bitstrings"] = sparse_state_vs_oracle(configs, sparse_amps, 4)
@@ -1003,7 +1086,7 @@ def main():
                                    "choose_s": c["choose_s"]} for c in chosen]}
             log(f"  {out['mixed_precision']}")
         for prec, r in runs.items():
-            # a11: errors of the sampled slices' amplitudes against the complex128 oracle
+            # errors of the sampled slices' amplitudes against the complex128 oracle
             per = [metrics.rel_l2(a, b) for a, b in zip(r["partial"], ref)]
             out[prec]["vs_oracle_slices"] = {
                 "slices": len(per), "rel_l2": metrics.rel_l2(r["partial"], ref),
