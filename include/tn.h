@@ -143,6 +143,10 @@ typedef struct {
                                   (tn_plan_set_step_terms); 0 for the other kernels */
   int32_t merged_bits;         /* sparse-state plans: bits of the merged open bond of a sparse einsum
                                   (its lowest batch bits, indexed through tables); -1 otherwise */
+  int32_t values_first;        /* sparse einsums on MFMA kernels: 1 = blocks of consecutive merged
+                                  values run together (runs of consecutive values share A's slice,
+                                  which the resident blocks then read once through L2); 0 = the
+                                  tiles of one value together */
 } tn_step_info;
 
 /* Build a plan.

@@ -82,6 +82,9 @@ struct GettArgs {
   const int64_t* tab_a;
   const int64_t* tab_b;
   int32_t tab_bits;
+  // 1: the table bits are the lowest bits of the MFMA kernels' block index, so blocks of
+  // consecutive merged values (which share A's slice) run together; 0: tiles of one value
+  int32_t values_first;
   int32_t dot;                  // small steps: one block per output element, K split over the block
 };
 

@@ -431,8 +431,18 @@ __device__ __forceinline__ TileCtx tile_ctx(const GettDesc* __restrict__ d, cons
   TileCtx c;
   c.nbb = d->own_bb + g.chunk_bits;
   const int tmb = g.tiles_m_bits, tnb = g.tiles_n_bits;
-  const uint64_t tix = bid & ((1ull << (tmb + tnb)) - 1);
-  bid >>= tmb + tnb;
+  uint64_t tix;
+  if (g.values_first) {
+    // block index = value | tile << tab_bits | (batch bits above the values) | split
+    const int tb = g.tab_bits;
+    const uint64_t f = bid & ((1ull << tb) - 1);
+    bid >>= tb;
+    tix = bid & ((1ull << (tmb + tnb)) - 1);
+    bid = ((bid >> (tmb + tnb)) << tb) | f;
+  } else {
+    tix = bid & ((1ull << (tmb + tnb)) - 1);
+    bid >>= tmb + tnb;
+  }
   const int gm = tmb < 2 ? tmb : 2, gn = tnb < 3 ? tnb : 3;
   c.tile_m = (tix & ((1ull << gm) - 1)) | (((tix >> (gm + gn)) & ((1ull << (tmb - gm)) - 1)) << gm);
   c.tile_n = ((tix >> gm) & ((1ull << gn) - 1)) | ((tix >> (gm + gn + tmb - gm)) << gn);

@@ -135,6 +135,7 @@ struct Step {
   std::vector<int> ia_labels, ib_labels;   // open-bond labels of A and B the tables index
   std::vector<int64_t> tab_a, tab_b;
   int64_t tab_a_max = 0, tab_b_max = 0;
+  int values_first = 0;   // MFMA block order: merged values fastest (see build_tables)
   int64_t* d_tab_a = nullptr;
   int64_t* d_tab_b = nullptr;
   GettDesc desc;
@@ -522,6 +523,14 @@ void build_tables(tn_plan_s* p, Step& st) {
   }
   st.tab_a_max = *std::max_element(st.tab_a.begin(), st.tab_a.end());
   st.tab_b_max = *std::max_element(st.tab_b.begin(), st.tab_b.end());
+  // Keys are sorted, so when A's open bonds are the high qubits of the result's, runs of
+  // consecutive values read the same slice of A.  Where those runs average 8 values or
+  // more, the MFMA kernels take the values as the fastest part of the block index: the
+  // blocks resident together then share each A tile through L2 (instead of every value
+  // streaming A again) and read one B slice per value.
+  int64_t changes = 0;
+  for (size_t f = 1; f < C.keys.size(); ++f) changes += st.tab_a[f] != st.tab_a[f - 1] ? 1 : 0;
+  st.values_first = C.keys.size() >= 64 && changes * 8 < (int64_t)C.keys.size() ? 1 : 0;
 }
 
 // Every address a kernel forms is a sum of per-bit strides.  Check, for every
@@ -1303,6 +1312,7 @@ void step_launches(const tn_plan_s* p, const Step& st, const GettDesc* d, int s,
     g.tab_a = st.d_tab_a;
     g.tab_b = st.d_tab_b;
     g.tab_bits = p->labels[st.tab_label].nb;
+    g.values_first = st.values_first;
   }
   L.desc = d;
   L.step = s;
@@ -1831,6 +1841,7 @@ tn_status tn_plan_steps(tn_plan p, tn_step_info* steps, int32_t cap) {
     o.flops = st.flops;
     o.terms = (st.kernel == TN_K_MFMA_F16X3 || st.kernel == TN_K_MFMA_BF16X3) ? st.terms : 0;
     o.merged_bits = st.tab_label >= 0 ? p->labels[st.tab_label].nb : -1;
+    o.values_first = st.values_first;
     o.bytes = st.bytes;
     o.tile = st.kernel == TN_K_SMALL ? -1 : st.tile;
     o.lds_copy = st.dma;

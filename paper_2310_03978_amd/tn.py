@@ -90,7 +90,8 @@ class tn_step_info(ctypes.Structure):
                 ("tile_n", ctypes.c_int32), ("a_contig", ctypes.c_int32),
                 ("b_contig", ctypes.c_int32), ("flops", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("tile", ctypes.c_int32), ("lds_copy", ctypes.c_int32),
-                ("terms", ctypes.c_int32), ("merged_bits", ctypes.c_int32)]
+                ("terms", ctypes.c_int32), ("merged_bits", ctypes.c_int32),
+                ("values_first", ctypes.c_int32)]
 
 
 _P = ctypes.POINTER

@@ -878,13 +878,51 @@ def test_lds_copy_512x64_layout_on_the_sparse_state(prec):
                  tuning=0) as p:
         wide = _wide_copy_steps(p)
         st = p.steps()
-        assert any(st[i]["merged_bits"] >= 0 and st[i]["k"] == 4096 and st[i]["lds_copy"] == 2 for i in wide)
+        assert any(st[i]["merged_bits"] >= 0 and st[i]["k"] == 4096 and st[i]["lds_copy"] == 2
+                   and st[i]["values_first"] == 1 for i in wide)
         assert any(st[i]["merged_bits"] >= 0 and st[i]["n"] == 32 and st[i]["lds_copy"] == 3 for i in wide)
         p.contract()
         got, _ = p.amplitudes()
     rel = metrics.rel_l2(got, ref)
     print(f"sparse state on the 512-row layouts, {prec}: rel_l2 vs complex64 {rel:.2e}", flush=True)
     assert rel <= (1e-4 if prec == "f16x3" else 1e-3)
+
+
+_SPARSE_ORACLE = {}
+
+
+@pytest.mark.parametrize("prec", ["c64", "f16x3"])
+def test_sparse_einsum_values_first_matches_oracle(prec):
+    """The sparse state of the 30-qubit 12-cycle circuit, whose 1024-value einsum (runs of
+    about 62 consecutive values share A's slice) takes the block order with the merged
+    values fastest: 6 seeded bitstrings' amplitudes against the oracle's definition (one
+    closed complex128 contraction per bitstring, Sec. 3.3), on the learned model's tiles
+    (the split step on the 512 x 64 LDS-copy layout) and on complex64."""
+    from oracle import sparse
+    from tn_inputs.paths import path_cost
+    print(f"sparse einsum with values first, {prec}", flush=True)
+    net, path, bits = configs.sparse_state_workload()
+    ids = [int(x) for x in np.random.default_rng(808).choice(len(bits), 6, replace=False)]
+    if "ref" not in _SPARSE_ORACLE:
+        opened = set(net.open_labels)
+        closed = [tuple(l for l in lab if l not in opened) for lab in net.labels]
+        ext = net.extents()
+        cands = [greedy_path(closed, (), ext, seed=k, temperature=0.0 if k == 0 else 0.3) for k in range(6)]
+        cpath = min(cands, key=lambda q: path_cost(closed, (), ext, q)["flops_total"])
+        _SPARSE_ORACLE["ref"] = sparse.definition_amplitudes(net.tensors, net.labels, net.open_labels,
+                                                             cpath, bits[ids])
+    ref = _SPARSE_ORACLE["ref"]
+    with tn.Plan(net.tensors, net.labels, net.open_labels, path, precision=prec, bitstrings=bits,
+                 tuning=2) as p:
+        st = p.steps()
+        big = [s for s in st if s["merged_bits"] == 10 and s["k"] == 4096]
+        assert big and big[0]["values_first"] == 1 and big[0]["kernel"] != 0, big
+        if prec == "f16x3":
+            assert big[0]["lds_copy"] == 2, big
+        assert any(s["merged_bits"] >= 0 and s["kernel"] != 0 and s["values_first"] == 0 for s in st)
+        p.contract()
+        got, _ = p.amplitudes()
+    _check_amps(got[ids], ref, prec, rel=1e-5 if prec == "c64" else 1e-4, what="sparse state, values first")
 
 
 @pytest.mark.parametrize("prec", ["c64", "f16x3"])
