@@ -516,6 +516,44 @@ def run_precision_form_full(tn, torch, configs, prec, n_slices, piece=128):
     return out
 
 
+def run_operand_data_check(tn, torch, net, best, desc, n_slices=64, reps=3):
+    """The headline plan (split FP16, shape-heuristic tiles so that every variant runs the
+    same launches) contracted over the same slices with the circuit's own leaves, with
+    leaves of constant value (every multiplier input repeats: the least switching) and with
+    seeded Gaussian leaves: time of the LDS-copy steps and of all steps per pass (HIP
+    events per launch).  The instruction stream is the same in all three, so a difference
+    in time is the clock the chip holds under each data's power draw."""
+    rng = np.random.default_rng(5)
+    variants = [("circuit", net.tensors), ("constant", [np.ones_like(t) for t in net.tensors]),
+                ("gaussian", [(rng.standard_normal(t.shape) + 1j * rng.standard_normal(t.shape)).astype(t.dtype)
+                              for t in net.tensors]), ("circuit_again", net.tensors)]
+    out = {"workload": desc, "precision": "f16x3", "slices_per_pass": n_slices, "passes": reps}
+    for name, tensors in variants:
+        with tn.Plan(tensors, net.labels, net.open_labels, best["path"], best["sliced"], precision="f16x3",
+                     record_steps=True, tuning=0) as p:
+            st = p.steps()
+            dma = [i for i, s in enumerate(st) if s["lds_copy"] == 1]
+            p.contract(0, 16)
+            torch.cuda.synchronize()
+            p.step_times()
+            p.reset()
+            copy_ms, all_ms = [], []
+            for _ in range(reps):
+                p.contract(0, n_slices)
+                torch.cuda.synchronize()
+                ms, _ = p.step_times()
+                copy_ms.append(float(sum(ms[i] for i in dma)))
+                all_ms.append(float(ms.sum()))
+            amps, _ = p.amplitudes()
+        out[name] = {"lds_copy_steps_ms": round(float(np.median(copy_ms)), 2),
+                     "all_steps_ms": round(float(np.median(all_ms)), 2),
+                     "finite": bool(np.all(np.isfinite(amps)))}
+        log(f"  operand data {name}: {out[name]}")
+    out["constant_speedup_of_copy_steps"] = round(out["circuit"]["lds_copy_steps_ms"] /
+                                                  out["constant"]["lds_copy_steps_ms"], 3)
+    return out
+
+
 def run_sparse_state(tn, torch, configs, reps):
     """Sparse-state contraction (Sec. 3.3): amplitudes of 4096 sampled bitstrings of the
     30-qubit 12-cycle circuit with every qubit measured, in one contraction; split FP16
@@ -912,6 +950,9 @@ def main():
     ap.add_argument("--precision-form-full", default="",
                     help="PREC:SLICES: only the precision form's evaluation of SLICES slices of the "
                          "53-qubit 12-cycle network in one precision")
+    ap.add_argument("--operand-data-check", action="store_true",
+                    help="only the headline plan's step times on the circuit's leaves, constant leaves "
+                         "and Gaussian leaves (one JSON line)")
     ap.add_argument("--no-permute", dest="permute", action="store_false",
                     help="skip the permutation-kernel bandwidth measurement")
     ap.add_argument("--permute-only", action="store_true",
@@ -960,6 +1001,9 @@ def main():
     w = configs.WORKLOADS[args.workload]
     log(f"workload {args.workload}: {w.description}; path found in {time.perf_counter() - t0:.1f}s")
     precs = [p for p in args.precisions.split(",") if p]
+    if args.operand_data_check:
+        print(json.dumps({"operand_data_check": run_operand_data_check(tn, torch, net, best, f"{args.workload}: {w.description}")}), flush=True)
+        return
     if args.counter_run:
         counter_run(tn, torch, net, best, precs, args.tuning)
         return
