@@ -7,7 +7,10 @@ the 30-qubit 12-cycle workload, a sparse state of that circuit (2048 bitstrings,
 slice of the 53-qubit 12-cycle workload (intermediates up to 2^30 elements), the 30-qubit
 14-cycle sliced workload (chunks of 8 slices and of 1 slice) and one slice of the 40-qubit
 16-cycle workload, in the three precisions, each MFMA step timed with all four tile shapes (HIP
-events on the plan's stream).  The model is trained on all circuits but the last
+events on the plan's stream).  With `--annealed-workloads`, one slice each of that workload's
+tree annealed with the previously shipped model as the score (with and without the floor at the
+model's large-step rate) joins the data: the annealer steers toward the step shapes whose speed the
+model overstates, and timing them teaches the next model those shapes.  The model is trained on all circuits but the last
 `--held-out` ones and the 14-cycle workload; the saved file records the held-out error and
 the measured time of the tiles the model picks against the shape heuristic's picks.
 """
@@ -33,7 +36,27 @@ def log(*a):
     print(*a, flush=True)
 
 
-def harvest_all(n_circuits: int, precisions, reps: int, extra=()):
+def annealed_trees(name: str):
+    """The workload's tree (its own sliced bonds and cap) annealed with the shipped model's
+    summed step times as the score, without and with the floor at the model's large-step
+    rate; [] when no model has been shipped yet."""
+    from paper_2310_03978_amd import planner
+    if not os.path.exists(costmodel.DEFAULT_MODEL):
+        return []
+    w = configs.WORKLOADS[name]
+    _, net, best = configs.build(name)
+    out = []
+    with costmodel.CostModel.load() as model:
+        table = costmodel.StepTimeTable(model, "f16x3")
+        for tag, st in (("learned", table),
+                        ("floored", costmodel.StepTimeTable(model, "f16x3", floor_rate=table.large_step_rate()))):
+            r = planner.refine(net.labels, net.open_labels, best["path"], best["sliced"], cap_log2=w.cap_log2,
+                               sweeps=200, step_time=st)
+            out.append((f"{name}{tag}sb1", net, {"path": r["path"], "sliced": list(best["sliced"])}, 1, None))
+    return out
+
+
+def harvest_all(n_circuits: int, precisions, reps: int, extra=(), annealed=()):
     circs = configs.uneven_circuits(n_circuits, seed=5000, cap_log2=25)
     items = [(f"u{i}", net, best, 0, None) for i, (net, best) in enumerate(circs)]
     for name in ["rqc30d12", "rqc30"]:
@@ -49,6 +72,8 @@ def harvest_all(n_circuits: int, precisions, reps: int, extra=()):
         # one slice of a large sliced workload: its largest steps at full size
         _, net, best = configs.build(name)
         items.append((f"{name}sb1", net, best, 1, None))
+    for name in annealed:
+        items += annealed_trees(name)
     records, defaults = [], {}
     for prec in precisions:
         for tag, net, best, sb, bits in items:
@@ -73,6 +98,9 @@ def main():
     ap.add_argument("--extra-workloads", default="rqc40",
                     help="sliced workloads harvested on one slice each (largest steps at full size); the "
                          "53-qubit 14-cycle slicing-choice workload stays out of the data")
+    ap.add_argument("--annealed-workloads", default="rqc53d12",
+                    help="workloads whose tree, annealed with the shipped model as the score, is "
+                         "harvested on one slice")
     ap.add_argument("--precisions", default="f16x3,c64,bf16x3")
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--epochs", type=int, default=300)
@@ -83,7 +111,8 @@ def main():
         sys.exit("no GPU")
     t0 = time.time()
     extra = [x for x in args.extra_workloads.split(",") if x]
-    records, defaults = harvest_all(args.circuits, args.precisions.split(","), args.reps, extra)
+    annealed = [x for x in args.annealed_workloads.split(",") if x]
+    records, defaults = harvest_all(args.circuits, args.precisions.split(","), args.reps, extra, annealed)
     if args.records:
         with open(args.records, "w") as f:
             json.dump({"records": records,
