@@ -963,10 +963,30 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
     for (int q : p->slice_bits)
       if (std::find(T.user_layout.begin(), T.user_layout.end(), q) != T.user_layout.end()) T.sbits.push_back(q);
   }
-  // slice chunk size
+  // slice chunk size: the caller's, else 8 slices, raised to 16 or 32 while the chunk's
+  // per-slice arena stays within kAutoChunkBytes (larger chunks give the per-slice GEMMs more
+  // batch; the per-slice arena grows linearly with the chunk, so its one-slice peak decides)
   int64_t want = p->opts.slice_batch > 0 ? p->opts.slice_batch : 8;
   if (p->opts.slice_batch > 0 && ilog2_exact(p->opts.slice_batch) < 0)
     return fail(TN_E_ARG, "slice_batch must be a power of two");
+  if (p->opts.slice_batch <= 0 && p->n_slice_bits > 0) {
+    constexpr double kAutoChunkBytes = 32.0 * (1ull << 30);
+    Arena dry;
+    std::map<int, int64_t> at;   // per-slice intermediates of the dry run -> offset
+    for (const Step& st : p->steps) {
+      if (!st.per_slice) continue;
+      at[st.tc] = dry.alloc(p->tensors[st.tc].elems);
+      for (int x : {st.ta, st.tb}) {
+        auto it = at.find(x);
+        if (it != at.end()) {
+          dry.release(it->second, p->tensors[x].elems);
+          at.erase(it);
+        }
+      }
+    }
+    const double per_slice = 8.0 * (double)dry.peak;
+    while (want < 32 && 2.0 * (double)want * per_slice <= kAutoChunkBytes) want *= 2;
+  }
   p->s_bits = 0;
   while ((int64_t(2) << p->s_bits) <= std::min<int64_t>(want, p->n_slices)) ++p->s_bits;
   if (p->n_slice_bits == 0) p->s_bits = 0;
