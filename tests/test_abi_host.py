@@ -201,6 +201,49 @@ def test_host_plan_reports_workspace_size():
     assert info["workspace_bytes"] >= 8 * info["max_intermediate"] * info["slice_batch"]
 
 
+def test_automatic_slice_chunk():
+    """slice_batch = 0: 8 slices per chunk, raised to 16 or 32 while the chunk's per-slice arena
+    fits in 32 GiB (one-slice arena peak x chunk); a caller's value is kept; never more than
+    the slice count."""
+    circ, net, best = configs.build("rqc30")
+    infos = {}
+    for sb in (0, 8, 16):
+        h = _host_plan(net, best["path"], best["sliced"], precision="f16x3", slice_batch=sb)
+        try:
+            infos[sb] = tn.tn_plan_describe(h)
+        finally:
+            tn.tn_plan_destroy(h)
+    assert infos[8]["slice_batch"] == 8 and infos[16]["slice_batch"] == 16
+    auto = infos[0]["slice_batch"]
+    assert auto in (8, 16, 32)
+    # the per-slice part of the workspace grows with the chunk: check the rule from the
+    # 8- and 16-slice plans' workspaces (same leaves and invariant arena)
+    per_slice = (infos[16]["workspace_bytes"] - infos[8]["workspace_bytes"]) / 8
+    expect = 8
+    while expect < 32 and 2 * expect * per_slice <= 32 * 2**30 * 1.01:
+        expect *= 2
+    assert auto == expect, (auto, per_slice)
+    assert auto == 32   # the 30-qubit workload: about 0.9 GiB per slice
+    _, net, best = configs.build("rqc53d12")   # 2^30-element intermediates: stays at 8
+    h = _host_plan(net, best["path"], best["sliced"], precision="f16x3")
+    try:
+        assert tn.tn_plan_describe(h)["slice_batch"] == 8
+    finally:
+        tn.tn_plan_destroy(h)
+    # a small network: the whole (at most 32-slice) slice range in one chunk
+    rnet = random_network(4, n_tensors=8)
+    rpath = greedy_path(rnet.labels, rnet.open_labels, rnet.extents())
+    ext = rnet.extents()
+    sliced = [l for l in sorted({l for lab in rnet.labels for l in lab})
+              if l not in rnet.open_labels and ext[l] > 1][:2]
+    h = _host_plan(rnet, rpath, sliced)
+    try:
+        info = tn.tn_plan_describe(h)
+        assert 1 < info["n_slices"] <= 32 and info["slice_batch"] == info["n_slices"], info
+    finally:
+        tn.tn_plan_destroy(h)
+
+
 def test_step_terms_setting_and_errors():
     """Per-step product count: split steps default to 3 and accept 1 or 3; other steps and
     other counts are refused; single_product_top marks the costliest split steps."""
