@@ -317,17 +317,18 @@ COUNTERS = os.path.join(ROOT, "profiles", "gett_rqc30_counters.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2310_03978_amd", "csrc", "tn_kernels.hip")
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, slice_batch: int):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
-    when there is none for it or the kernel source changed since the counters were taken
-    (the summary records the SHA-256 of tn_kernels.hip it was measured with)."""
+    when there is none for it, the kernel source changed since the counters were taken (the
+    summary records the SHA-256 of tn_kernels.hip it was measured with) or the plan's slice
+    chunk differs from the one the counters were taken with (the launches would differ)."""
     import hashlib
     try:
         text = open(COUNTERS).read()
     except OSError:
         return None
     src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if f"kernel source sha256: {src}" not in text:
+    if f"kernel source sha256: {src}" not in text or f"slice chunk: {slice_batch}\n" not in text:
         return None
     for line in text.splitlines():
         if line.startswith("traffic per launch:") and f"`{kernel}`" in line:
@@ -1039,7 +1040,7 @@ def main():
     bound, peak, peak_name = PEAK[head] if dom != "k_gett_small" else ("alu", 157.3, "fp32 vector")
     roof = {"bound": bound, "kernel": dom, "achieved": round(achieved, 2),
             "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": measured_traffic(dom),
+            "traffic": measured_traffic(dom, info["slice_batch"]),
             "launches": dk["launches"], "avg_launch_ms": round(dk["ms"] / max(dk["launches"], 1), 4),
             "flops_per_launch": dk["flops"] / max(dk["launches"], 1),
             "algorithmic_bytes_per_launch": dk["bytes"] / max(dk["launches"], 1),
