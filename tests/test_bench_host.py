@@ -24,11 +24,13 @@ def test_kernel_names_follow_the_launched_instances():
     assert bench.kernel_name({"kernel": 2, "tile": 0, "lds_copy": 3}) == "void k_gett_dma<1, 2>"
 
 
-def test_counter_traffic_only_for_known_kernels_of_the_recorded_source():
-    assert bench.measured_traffic("void no_such_kernel<0>") is None
-    t = bench.measured_traffic("void k_gett_dma<1, 0>")
+def test_counter_traffic_only_for_known_kernels_of_the_recorded_source_and_chunk():
+    assert bench.measured_traffic("void no_such_kernel<0>", 32) is None
+    t = bench.measured_traffic("void k_gett_dma<1, 0>", 32)
     # recorded for the current kernel source: a per-launch byte count of the right magnitude
     assert t is None or 1e9 < t < 1e11
+    # another slice chunk runs other launches: no figure
+    assert bench.measured_traffic("void k_gett_dma<1, 0>", 8) is None
 
 
 def test_slice_samples_are_seeded_sorted_and_distinct():
