@@ -313,19 +313,25 @@ def test_numeric_error_is_reported():
 
 @pytest.mark.parametrize("prec", ["c64", "f16x3"])
 def test_rqc30_sampled_slices_match_oracle(prec):
-    """The 30-qubit, 14-cycle, 256-slice workload at full size: sampled slices vs the oracle."""
+    """The 30-qubit, 14-cycle, 256-slice workload at full size, in the launch configuration
+    the bench times (autotuned tiles, the automatic chunk of 32 slices): a sampled slice vs the
+    oracle, and the chunk holding it, contracted as one launch sequence, vs the sum of its
+    slices' partials."""
     print(f"rqc30 {prec}", flush=True)
     circ, net, best = configs.build("rqc30")
     sid = 137
     ref = _rqc30_oracle_slice(sid)
     with tn.Plan(net.tensors, net.labels, net.open_labels, best["path"], best["sliced"],
-                 precision=prec) as p:
+                 precision=prec, tuning=1) as p:
+        chunk = p.describe()["slice_batch"]
+        assert chunk == 32
         part = p.partials([sid])[0]
         # the full run accumulates every slice once; chunked sums agree with partial sums
-        p.contract(128, 16)
+        first = sid - sid % chunk
+        p.contract(first, chunk)
         acc, c = p.amplitudes()
-        assert c == 16
-        parts = p.partials(list(range(128, 144)))
+        assert c == chunk
+        parts = p.partials(list(range(first, first + chunk)))
     rep = metrics.report(part, ref)
     print(f"rqc30 slice {sid} {prec}: {rep}", flush=True)
     _check_amps(part, ref, prec, what=f"rqc30 slice {sid}")
