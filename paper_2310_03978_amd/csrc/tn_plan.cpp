@@ -110,6 +110,7 @@ struct Tensor {
   uint64_t sq = 0;
   int merged = -1;
   std::vector<uint64_t> keys;
+  std::vector<std::pair<uint64_t, int64_t>> key_value;   // (key, value) sorted by key, for lookups
 };
 
 struct Step {
@@ -491,7 +492,8 @@ int64_t open_offset(const tn_plan_s* p, const Tensor& T, uint64_t key) {
   int64_t off = 0;
   if (T.merged >= 0) {
     const uint64_t r = key & T.sq;
-    const int64_t v = std::lower_bound(T.keys.begin(), T.keys.end(), r) - T.keys.begin();
+    const auto it = std::lower_bound(T.key_value.begin(), T.key_value.end(), std::make_pair(r, int64_t(0)));
+    const int64_t v = (it != T.key_value.end() && it->first == r) ? it->second : 0;   // always found
     const Label& L = p->labels[T.merged];
     for (int b = 0; b < L.nb; ++b)
       if ((v >> b) & 1) off += bit_stride(T, L.bit0 + b);
@@ -523,14 +525,14 @@ void build_tables(tn_plan_s* p, Step& st) {
   }
   st.tab_a_max = *std::max_element(st.tab_a.begin(), st.tab_a.end());
   st.tab_b_max = *std::max_element(st.tab_b.begin(), st.tab_b.end());
-  // Keys are sorted, so when A's open bonds are the high qubits of the result's, runs of
-  // consecutive values read the same slice of A.  Where those runs average 8 values or
-  // more, the MFMA kernels take the values as the fastest part of the block index: the
-  // blocks resident together then share each A tile through L2 (instead of every value
-  // streaming A again) and read one B slice per value.
+  // Values are ordered by their restriction to A's qubits first, so runs of consecutive
+  // values read the same slice of A.  Where those runs average 4 values or more, the MFMA
+  // kernels take the values as the fastest part of the block index: the blocks resident
+  // together then share each A tile through L2 (instead of every value streaming A again)
+  // and read one B slice per value.
   int64_t changes = 0;
   for (size_t f = 1; f < C.keys.size(); ++f) changes += st.tab_a[f] != st.tab_a[f - 1] ? 1 : 0;
-  st.values_first = C.keys.size() >= 64 && changes * 8 < (int64_t)C.keys.size() ? 1 : 0;
+  st.values_first = C.keys.size() >= 64 && changes * 4 < (int64_t)C.keys.size() ? 1 : 0;
 }
 
 // Every address a kernel forms is a sum of per-bit strides.  Check, for every
@@ -829,11 +831,19 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
     }
     if (merge) {
       // the merged bond: one value per distinct restriction of the bitstrings to the
-      // union of the operands' measured qubits, in increasing order, padded to a power of two
+      // union of the operands' measured qubits, padded to a power of two; values are
+      // ordered by the restriction to A's qubits, then to B's, so that runs of consecutive
+      // values read the same slice of A (the block order can then share it, build_tables)
       const uint64_t q = A.sq | B.sq;
       for (uint64_t k : p->bkeys) C.keys.push_back(k & q);
       std::sort(C.keys.begin(), C.keys.end());
       C.keys.erase(std::unique(C.keys.begin(), C.keys.end()), C.keys.end());
+      const uint64_t qa = A.sq, qb = B.sq;
+      std::sort(C.keys.begin(), C.keys.end(), [qa, qb](uint64_t x, uint64_t y) {
+        return (x & qa) != (y & qa) ? (x & qa) < (y & qa) : (x & qb) < (y & qb);
+      });
+      for (size_t v = 0; v < C.keys.size(); ++v) C.key_value.push_back({C.keys[v], (int64_t)v});
+      std::sort(C.key_value.begin(), C.key_value.end());
       Label L;
       while ((int64_t(1) << L.nb) < (int64_t)C.keys.size()) ++L.nb;
       L.ext = int64_t(1) << L.nb;
@@ -855,6 +865,7 @@ tn_status plan_build(tn_plan_s* p, int32_t n_tensors, const int32_t* ranks, cons
       C.sq = A.sq | B.sq;
       C.merged = O.merged;
       C.keys = O.keys;
+      C.key_value = O.key_value;
     }
     for (int l : C.labels) count[l]++;
     C.per_slice = A.per_slice || B.per_slice;
