@@ -346,6 +346,22 @@ def _raw_sparse_create(n_open, n_bitstrings, bits_buf, opts=None):
     return st, tn._lib.tn_last_error_message().decode()
 
 
+def test_sparse_einsums_take_the_values_first_block_order_where_a_slices_repeat():
+    """The 30-qubit 12-cycle sparse state (4096 bitstrings): its result values are ordered by
+    A's restriction first, so the 1024-value einsum (A: 16 slices) and the 4096-value einsum
+    (A: about 1000 slices) both take the values-first block order; only sparse einsums on
+    MFMA kernels report it."""
+    net, path, bits = configs.sparse_state_workload()
+    with tn.Plan(net.tensors, net.labels, net.open_labels, path, precision="f16x3", bitstrings=bits,
+                 host_only=True) as p:
+        st = p.steps()
+    big = [s for s in st if s["merged_bits"] == 10 and s["k"] == 4096]
+    wide = [s for s in st if s["merged_bits"] == 12 and s["n"] == 32]
+    assert big and big[0]["values_first"] == 1
+    assert wide and wide[0]["values_first"] == 1
+    assert all(s["values_first"] == 0 for s in st if s["merged_bits"] < 0)
+
+
 def test_huge_allocation_returns_a_status_instead_of_aborting():
     """The C entry points never let a C++ exception cross the ABI: a request for more host
     memory than exists (2^61 sampled bitstrings) fails with TN_E_NOMEM."""
