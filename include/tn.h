@@ -71,7 +71,9 @@ typedef struct {
   void* stream;            /* hipStream_t for every launch of this plan; NULL = default stream */
   int32_t slice_batch;     /* slices contracted together per chunk (power of two); 0 = auto:
                               8, raised to 16 or 32 (never beyond the slice count) while the
-                              chunk's per-slice intermediates fit in 32 GiB */
+                              chunk's per-slice intermediates fit in 32 GiB.  Tiles and K splits
+                              are chosen for full chunks: a caller that contracts fewer slices
+                              per call gets underfilled launches and should pass a smaller value */
   int32_t host_only;       /* 1 = plan on the host only: describe/steps work, contraction
                               calls return TN_E_STATE and no device memory is touched */
   int32_t split_policy;    /* 0 = split products on steps that are MFMA-bound, FP32 elsewhere;
